@@ -1,0 +1,183 @@
+/*
+ * biotst -- space-time Biot slab operator and solver for MI355X (gfx950).
+ *
+ * C ABI.  Koecher, "Space-Time-Parallel Poroelasticity Simulation":
+ *   - section "Poroelasticity": the fully coupled (u, q, p) Biot system;
+ *   - section "Discretisation in Time": dG(r) slabs I_n = (t_{n-1}, t_n),
+ *     marched one after the other;
+ *   - section "Discretisation in Space": RT1 flux / DG-Q1 pressure mixed
+ *     element; the displacement here is continuous Q2;
+ *   - section "Monolithic Approach": the (r+1)-level slab block system;
+ *   - section "Preconditioning technology": GMRES with a fixed-stress,
+ *     level-blockwise (L_j) preconditioner.
+ *
+ * Discretisation contract (shared with any independent checker):
+ *   Mesh: box [0,L_0] x .. x [0,L_{d-1}], n_e uniform cells per axis, cells
+ *   lexicographic x fastest.  1D bases: closed = quadratic Lagrange on
+ *   {0, 1/2, 1}; open = linear Lagrange on the two Gauss points.
+ *   u_c: closed in every axis, array (2n_0+1) x .. ; q_c: closed along axis c,
+ *   open along the others; p: open in every axis, array (2n_0) x .. .
+ *   Spatial level vector = [u_0..u_{d-1}, q_0..q_{d-1}, p], each block x-fastest.
+ *   Slab vector = levels j = 0..r outermost (Lagrange coefficients on the
+ *   right Gauss-Radau points of [0,1]; level r is the end-of-slab value).
+ *   Operator (W^-1-scaled dG(r) system, essential rows = identity):
+ *     Y_i = sum_j T_ij M_t X_j + tau K_s X_i,   T = W^-1 D  (Radau),
+ *     K_s = [[A,0,-bE],[0,Mq,B],[0,B^T,0]],  M_t = [[0,0,0],[0,0,0],[-bE^T,0,-Mp/M]],
+ *     a(u,v) = (2 mu eps(u), eps(v)) + (lam div u, div v), E_ij = (psi_j, div phi_i),
+ *     Mq_ij = (eta K^-1 w_j, w_i), B_ij = -(psi_j, div w_i), Mp_ij = (psi_j, psi_i).
+ *   Boundary: bottom (x_{d-1}=0) u = 0, q.n = 0; lateral faces u.n = 0,
+ *   q.n = 0; top: compressive traction sigma(t) and drained p = 0.
+ *   Slab right-hand side: tau F(t_{n-1} + tau s_i) + g_i M_t X^-_{n-1},
+ *   g = W^-1 phi(0).
+ *
+ * Ownership: every buffer is the caller's.  Device pointers must stay valid
+ * for the duration of a call; `workspace` must outlive the handle.  The
+ * library allocates no device memory: everything it keeps on the device is
+ * carved from the caller's workspace.  Host pointers are only read during
+ * the call.  Handles are not thread-safe.
+ *
+ * Errors: every call returns biot_status.  Argument checks run on the host
+ * before any launch and leave no side effect.  biot_last_error() returns a
+ * thread-local message for the last non-OK status.  Device faults surface at
+ * the next synchronising call as BIOT_ERR_DEVICE.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (0 = null stream).
+ */
+#ifndef BIOTST_H
+#define BIOTST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct biot_problem_s* biot_problem;
+
+typedef enum {
+  BIOT_OK = 0,
+  BIOT_ERR_ARG = 1,        /* invalid argument (checked on the host)             */
+  BIOT_ERR_WORKSPACE = 2,  /* workspace missing or smaller than required         */
+  BIOT_ERR_DEVICE = 3,     /* a HIP call failed                                  */
+  BIOT_ERR_NOCONV = 4,     /* iteration limit reached; x holds the last iterate  */
+  BIOT_ERR_BREAKDOWN = 5,  /* Krylov breakdown with an unconverged residual      */
+  BIOT_ERR_NONFINITE = 6   /* NaN/Inf met in a residual norm                     */
+} biot_status;
+
+typedef enum { BIOT_FP64 = 0, BIOT_MIXED = 1 } biot_precision;
+typedef enum { BIOT_LOAD_STEP = 0, BIOT_LOAD_RAMP = 1 } biot_load_kind;
+
+/* One problem instance.  Section "Poroelasticity": isotropic C (lambda, mu),
+ * Biot coefficient 0 < b < 1, Biot modulus M > 0, viscosity eta; cellwise
+ * permeability K = exp(log_k). */
+typedef struct {
+  int32_t dim;          /* 2 or 3                                                    */
+  int32_t n[3];         /* cells per axis; n[2] ignored for dim == 2                 */
+  double length[3];     /* box edge lengths                                          */
+  int32_t r;            /* dG(r) order, 0..3; all instances of a batch share it      */
+  double tau;           /* slab length > 0                                           */
+  double lambda, mu;    /* Lame parameters: mu > 0, lambda + 2 mu / dim > 0          */
+  double b;             /* Biot coefficient in (0, 1)                                */
+  double M;             /* Biot modulus > 0                                          */
+  double eta;           /* fluid viscosity > 0                                       */
+  double L_fs;          /* fixed-stress parameter; <= 0 selects b^2 / K_dr           */
+  int32_t load_kind;    /* biot_load_kind                                            */
+  double load_s0;       /* top compressive traction magnitude                        */
+  double load_t_ramp;   /* ramp time (> 0 for BIOT_LOAD_RAMP)                        */
+} biot_problem_desc;
+
+/* Solver controls (nullable: defaults in brackets). */
+typedef struct {
+  double rtol;          /* stop when ||b - A x|| <= rtol ||b||          [1e-12]   */
+  int32_t maxit;        /* total GMRES iterations                         [1000]   */
+  int32_t restart;      /* GMRES(m) restart length, <= 64                   [40]   */
+  int32_t precision;    /* biot_precision                                [FP64]   */
+  double inner_rtol;    /* mixed: inner FP32 solve tolerance              [1e-5]   */
+  int32_t max_refine;   /* mixed: outer refinement sweeps                   [20]   */
+  int32_t cheb_degree;  /* Chebyshev degree of the pressure/flux blocks     [8]    */
+} biot_solve_opts;
+
+typedef struct {
+  int32_t iterations;   /* GMRES iterations (inner iterations summed when mixed)   */
+  int32_t restarts;
+  int32_t ir_sweeps;    /* mixed precision refinement sweeps (0 for FP64)          */
+  int32_t status;       /* biot_status of this solve                               */
+  double rel_residual;  /* final true relative residual ||b - A x|| / ||b||        */
+} biot_solve_info;
+
+/* Bytes of device workspace needed for `count` instances. */
+biot_status biot_workspace_bytes(const biot_problem_desc* descs, int32_t count,
+                                 size_t* bytes);
+
+/* Create a handle for `count` instances (count > 1 = batched; instances are
+ * concatenated in every vector argument, each one a full slab vector).
+ * log_k[i]: host array of prod(n) cellwise log K values of instance i.
+ * Validates every descriptor and log_k (finite) before touching the device;
+ * uploads constants into the workspace; returns after `stream` drains. */
+biot_status create_slab_problem(const biot_problem_desc* descs, int32_t count,
+                                const double* const* log_k, void* workspace,
+                                size_t ws_bytes, void* stream, biot_problem* out);
+
+biot_status destroy_slab_problem(biot_problem h);
+
+/* Replace the log-permeability fields (host arrays as in create). */
+biot_status biot_set_log_k(biot_problem h, const double* const* log_k, void* stream);
+
+/* Sizes: spatial DoFs per level and slab-vector offset of instance i. */
+biot_status biot_sizes(biot_problem h, int32_t instance, int64_t* level_dofs,
+                       int64_t* slab_offset, int64_t* state_offset);
+/* Totals over all instances: slab-vector length and state length. */
+biot_status biot_totals(biot_problem h, int64_t* slab_len, int64_t* state_len);
+
+/* y = A x (transpose = 0) or y = A^T x (transpose = 1) on device slab vectors
+ * (section "Monolithic Approach" block system; A^T = T^T kron M_t^T +
+ * tau I kron K_s^T with the same identity rows).  dtype 0: double x, y;
+ * dtype 1: float x, y.  x and y must not alias.  Asynchronous on stream. */
+biot_status apply_operator(biot_problem h, const void* x, void* y, int32_t transpose,
+                           int32_t dtype, void* stream);
+
+/* Slab right-hand side (device): rhs = tau F(t_start + tau s_i) + g_i M_t state,
+ * essential rows zero.  state: device, one spatial level per instance. */
+biot_status slab_rhs(biot_problem h, const double* state, double t_start, double* rhs,
+                     void* stream);
+
+/* Solve A x = rhs (device vectors; x: initial guess in, solution out) with
+ * right-preconditioned restarted GMRES and the level-blockwise fixed-stress
+ * preconditioner (section "Preconditioning technology").  Synchronises
+ * `stream` once per restart cycle.  info: host, one entry per instance. */
+biot_status solve_slab(biot_problem h, const double* rhs, double* x,
+                       const biot_solve_opts* opts, biot_solve_info* info, void* stream);
+
+/* Transposed solve A^T x = rhs (adjoint slab), same preconditioner family. */
+biot_status solve_slab_transposed(biot_problem h, const double* rhs, double* x,
+                                  const biot_solve_opts* opts, biot_solve_info* info,
+                                  void* stream);
+
+/* March nslabs slabs from t_start (section "Discretisation in Time"):
+ * state (device, in/out) = X^- per instance; slabs_out (device, nullable)
+ * receives nslabs slab vectors; checkpoints (device, nullable) receives the
+ * state entering each slab.  infos: host, nslabs * count entries. */
+biot_status step(biot_problem h, int32_t nslabs, double t_start, double* state,
+                 double* slabs_out, double* checkpoints, const biot_solve_opts* opts,
+                 biot_solve_info* infos, void* stream);
+
+/* Discrete adjoint of J = 1/2 sum_n sum_s (p_h(x_s, t_n) - p_obs[n][s])^2 with
+ * respect to cellwise log K.  checkpoints: device, nslabs states as written by
+ * step (the forward slabs are recomputed from them); sensors_xyz: host,
+ * nsens * dim coordinates (shared by all instances); p_obs: device,
+ * count * nslabs * nsens values (instance-major); J: host, count values;
+ * grad_log_k: device, concatenated prod(n) per instance (overwritten). */
+biot_status adjoint_sweep(biot_problem h, int32_t nslabs, double t_start,
+                          const double* checkpoints, const double* sensors_xyz,
+                          int32_t nsens, const double* p_obs, const biot_solve_opts* opts,
+                          double* J, double* grad_log_k, void* stream);
+
+/* Thread-local message describing the last non-OK status. */
+const char* biot_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BIOTST_H */

@@ -1,0 +1,58 @@
+// Internal runtime state behind the opaque biot_problem handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/biotst.h"
+#include "common.h"
+#include "temporal.h"
+
+namespace bt {
+
+// workspace layout builder: the same code sizes and carves the workspace
+struct Layout {
+  size_t off = 0;
+  char* base = nullptr;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct BiotError {
+  biot_status st;
+  std::string msg;
+};
+
+void set_error(const std::string& m);
+void hip_check(hipError_t e, const char* what);
+
+struct MgLevel;     // preconditioner data (precond.h)
+struct PrecData;
+
+}  // namespace bt
+
+struct biot_problem_s {
+  int count = 0, dim = 0, r = 0, nl = 0;
+  std::vector<biot_problem_desc> descs;
+  std::vector<bt::InstDev> inst;       // host copies
+  bt::TemporalConstants tc;
+  bt::TimeMat tm;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  long long slab_len = 0, state_len = 0, ncells = 0;
+  // device arrays (carved from ws)
+  bt::InstDev* d_inst = nullptr;
+  int4* d_work_apply = nullptr;
+  int nwork_apply = 0;
+  double* d_kinv64 = nullptr;
+  float* d_kinv32 = nullptr;
+  double* d_theta = nullptr;
+  bt::PrecData* prec = nullptr;        // owned (host struct with device pointers)
+};

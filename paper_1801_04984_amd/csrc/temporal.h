@@ -1,0 +1,18 @@
+// Host-side dG(r) temporal constants.
+#pragma once
+
+namespace bt {
+
+struct TemporalConstants {
+  int r = 0;
+  double s[4] = {0}, w[4] = {0};   // right Gauss-Radau nodes / weights on [0,1]
+  double T[16] = {0};              // T = W^-1 D, row-major 4x4 (top-left (r+1)^2 used)
+  double g[4] = {0};               // g = W^-1 phi(0)
+  double Q[16] = {0}, Qi[16] = {0};// real block eigenbasis and its inverse
+  double alpha[4] = {0};           // real part of the block of each column of Q
+  double beta[4] = {0};            // +-imaginary part (0 for real eigenvalues)
+};
+
+TemporalConstants make_temporal(int r);
+
+}  // namespace bt

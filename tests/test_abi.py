@@ -1,0 +1,99 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol
+include/biotst.h declares, and rejects bad descriptors on the host with the
+documented status codes and no device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "biotst.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:biot_status|const char\*)\s+(\w+)\s*\(", src, flags=re.M)))
+
+
+def lib():
+    from paper_1801_04984_amd import native
+    try:
+        return native.load_library()
+    except OSError as e:
+        pytest.skip(str(e))
+
+
+def test_every_declared_symbol_is_exported():
+    L = lib()
+    from paper_1801_04984_amd import native
+    names = header_functions()
+    assert len(names) >= 12
+    assert sorted(native.EXPORTS) == names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _ws(desc_list):
+    from paper_1801_04984_amd import native
+    arr = (native.Desc * len(desc_list))(*desc_list)
+    nb = ctypes.c_size_t()
+    st = lib().biot_workspace_bytes(arr, len(desc_list), ctypes.byref(nb))
+    return st, nb.value, lib().biot_last_error().decode()
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("dim", 4, "dim"), ("r", 4, "r must"), ("tau", 0.0, "tau"), ("mu", -1.0, "mu"),
+    ("b", 1.0, "Biot coefficient"), ("b", 0.0, "Biot coefficient"), ("M", 0.0, "modulus"),
+    ("eta", -2.0, "viscosity"), ("load_kind", 7, "load_kind"), ("load_t_ramp", 0.0, "ramp"),
+    ("lam", -5.0, "lambda"), ("tau", float("nan"), "tau"),
+])
+def test_descriptor_validation(field, value, msg):
+    from paper_1801_04984_amd import native
+    d = native.make_desc(W.c2_hetero2d())
+    setattr(d, field, value)
+    st, _, err = _ws([d])
+    assert st == 1 and msg in err
+
+
+def test_batch_rules_and_sizes():
+    from paper_1801_04984_amd import native
+    a = native.make_desc(W.c2_hetero2d())
+    b = native.make_desc(W.c3_hetero3d())
+    st, _, err = _ws([a, b])
+    assert st == 1 and "dim" in err
+    c = native.make_desc(W.c2_hetero2d())
+    c.r = 2
+    st, _, err = _ws([a, c])
+    assert st == 1 and "share r" in err
+    st, n1, _ = _ws([a])
+    st2, n2, _ = _ws([a, a])
+    assert st == 0 and st2 == 0 and n2 > n1 > 0
+    d = native.make_desc(W.c2_hetero2d())
+    d.n[0] = 0
+    assert _ws([d])[0] == 1
+
+
+def test_create_rejects_small_workspace_and_nonfinite_logk():
+    from paper_1801_04984_amd import native
+    L = lib()
+    wl = W.Workload("t", 2, (4, 4), 1, 0.1, 1)
+    d = (native.Desc * 1)(native.make_desc(wl))
+    th = np.zeros(16)
+    th[3] = np.inf
+    arr = (ctypes.POINTER(ctypes.c_double) * 1)(th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    h = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(64)
+    st = L.create_slab_problem(d, 1, arr, ctypes.cast(buf, ctypes.c_void_p), 64, None, ctypes.byref(h))
+    assert st == 1 and "not finite" in L.biot_last_error().decode()
+    th[3] = 0.0
+    st = L.create_slab_problem(d, 1, arr, ctypes.cast(buf, ctypes.c_void_p), 64, None, ctypes.byref(h))
+    assert st == 2 and "workspace too small" in L.biot_last_error().decode()
+    st = L.create_slab_problem(d, 1, arr, None, 1 << 30, None, ctypes.byref(h))
+    assert st == 2
+    assert not h.value
+    assert L.apply_operator(None, None, None, 0, 0, None) == 1
+    assert L.destroy_slab_problem(None) == 1

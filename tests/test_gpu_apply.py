@@ -1,0 +1,73 @@
+"""Parity of the HIP slab operator (apply_operator through the C ABI) with the
+oracle's assembled slab matrix, element by element on seeded inputs."""
+import numpy as np
+import pytest
+
+from tests.gpu_common import field_rel, make_pair, small_workload, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+SHAPES_2D = [(1, 1), (3, 2), (20, 17), (31, 16), (46, 9)]
+
+
+def _check_apply(wls, dtype, transpose, seed=0):
+    torch = torch_cuda()
+    h, probs = make_pair(wls)
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(h.slab_len)
+    xt = torch.tensor(x, dtype=dtype, device="cuda")
+    yt = h.apply(xt, transpose=transpose)
+    torch.cuda.synchronize()
+    y = yt.double().cpu().numpy()
+    for k, prob in enumerate(probs):
+        xs = x[h.slab_offsets[k]: h.slab_offsets[k] + prob.L * prob.N]
+        if dtype == torch.float32:
+            xs = xs.astype(np.float32).astype(np.float64)
+        ref = prob.apply(xs, transpose=transpose)
+        got = y[h.slab_offsets[k]: h.slab_offsets[k] + prob.L * prob.N]
+        if dtype == torch.float64:
+            tol = 1e-12 * np.abs(ref).max()
+            bad = np.abs(got - ref) > tol
+            assert not bad.any(), (wls[k].name, int(bad.sum()), np.abs(got - ref).max(), tol)
+        else:
+            err = field_rel(prob, got, ref)
+            assert max(err.values()) < 2e-5, (wls[k].name, err)
+    h.close()
+
+
+@pytest.mark.parametrize("n", SHAPES_2D)
+@pytest.mark.parametrize("r", [0, 1, 2, 3])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_apply2d_fp64(n, r, transpose):
+    torch = torch_cuda()
+    _check_apply([small_workload(2, n, r, seed=3 + r)], torch.float64, transpose)
+
+
+@pytest.mark.parametrize("n", [(20, 17), (31, 16)])
+@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_apply2d_fp32(n, r, transpose):
+    torch = torch_cuda()
+    _check_apply([small_workload(2, n, r, seed=5)], torch.float32, transpose)
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_apply2d_batched_uneven(transpose):
+    torch = torch_cuda()
+    wls = [small_workload(2, n, 1, seed=10 + i, lam=1.0 + 0.3 * i, b=0.5 + 0.1 * i)
+           for i, n in enumerate([(5, 5), (17, 33), (16, 16), (2, 7)])]
+    _check_apply(wls, torch.float64, transpose)
+
+
+@pytest.mark.parametrize("r", [0, 1, 2])
+def test_slab_rhs_2d(r):
+    torch = torch_cuda()
+    wl = small_workload(2, (19, 16), r, seed=2)
+    h, (prob,) = make_pair([wl])
+    state = np.random.default_rng(4).standard_normal(prob.N)
+    state[prob.mask] = 0.0
+    for t0 in (0.0, 0.13, 0.5):
+        got = h.rhs(torch.tensor(state, device="cuda"), t0).cpu().numpy()
+        ref = prob.rhs(t0, state)
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    h.close()
