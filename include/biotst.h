@@ -89,7 +89,7 @@ typedef struct {
 
 /* Solver controls (nullable: defaults in brackets). */
 typedef struct {
-  double rtol;          /* stop when ||b - A x|| <= rtol ||b||          [1e-12]   */
+  double rtol;          /* stop when ||b - A x|| <= rtol ||b||          [1e-13]   */
   int32_t maxit;        /* total GMRES iterations                         [1000]   */
   int32_t restart;      /* GMRES(m) restart length, <= 64                   [40]   */
   int32_t precision;    /* biot_precision                                [FP64]   */

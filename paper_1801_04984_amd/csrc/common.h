@@ -88,16 +88,20 @@ struct TimeMat {
 };
 
 // --- essential-boundary predicates (bottom = last axis lower face) --------
-// u_c at node m: bottom -> all components; lateral faces of axes < dim-1 -> normal comp
-__device__ __forceinline__ bool u_fixed(const InstDev& I, int c, int mx, int my, int mz) {
-  if (I.dim == 2) {
+// u_c at node m of a Q2 grid with nodal sizes su: bottom -> all components;
+// lateral faces of axes < dim-1 -> the normal component (roller)
+__host__ __device__ __forceinline__ bool ugrid_fixed(int dim, const int* su, int c, int mx, int my, int mz) {
+  if (dim == 2) {
     if (my == 0) return true;
-    return c == 0 && (mx == 0 || mx == I.su[0] - 1);
+    return c == 0 && (mx == 0 || mx == su[0] - 1);
   }
   if (mz == 0) return true;
-  if (c == 0) return mx == 0 || mx == I.su[0] - 1;
-  if (c == 1) return my == 0 || my == I.su[1] - 1;
+  if (c == 0) return mx == 0 || mx == su[0] - 1;
+  if (c == 1) return my == 0 || my == su[1] - 1;
   return false;
+}
+__device__ __forceinline__ bool u_fixed(const InstDev& I, int c, int mx, int my, int mz) {
+  return ugrid_fixed(I.dim, I.su, c, mx, my, mz);
 }
 // q_c at closed coordinate mc along its own axis
 __device__ __forceinline__ bool q_fixed(const InstDev& I, int c, int mc) {

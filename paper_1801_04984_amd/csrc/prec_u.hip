@@ -1,0 +1,224 @@
+// Geometric multigrid for the Q2 elasticity block tau A of the fixed-stress
+// mechanics step (u = (tau A)^-1 (r_u + b tau E p)).
+//
+// Levels are uniform boxes n -> ceil(n/2) per axis; the coarse operator is
+// the same bilinear form rediscretised (for even n the spaces are nested and
+// this equals the Galerkin product).  Prolongation evaluates the coarse Q2
+// function at the fine nodes (tensor product of 1D interpolation tables, valid
+// for non-nested meshes too); restriction is its transpose, applied as one
+// 1D pass per axis.  Essential rows are identity on every level; all level
+// vectors are kept zero there.
+#include "cell2d.h"
+#include "prec.h"
+
+namespace bt {
+
+constexpr int kUT = 16;
+constexpr int kUO = kUT - 1;
+
+int uapply_tile(int dim) { return dim == 2 ? kUO : -1; }
+
+// y = tau A x (mode 0) or y = b - tau A x (mode 1); identity on essential rows
+template <typename T>
+__global__ __launch_bounds__(256) void uapply2d_kernel(const UGridSeg* __restrict__ segs, const int4* __restrict__ work,
+                                                       int mode, const T* __restrict__ X, const T* __restrict__ Bv,
+                                                       T* __restrict__ Y) {
+  __shared__ T E[18][kUT * kUT];
+  const int4 w = work[blockIdx.x];
+  const UGridSeg& G = segs[w.x];
+  const int j = blockIdx.y;
+  const long long vo = G.voff + j * G.vjstride;
+  const T* Xl = X + vo;
+  const T* Bl = Bv + vo;
+  T* Yl = Y + vo;
+  const int lx = threadIdx.x, ly = threadIdx.y, tid = ly * kUT + lx;
+  const int nx = G.n[0], ny = G.n[1];
+  const int i0 = w.y * kUO, j0 = w.z * kUO;
+  const int i = i0 - 1 + lx, jc = j0 - 1 + ly;
+  const bool valid = (i >= 0) && (i < nx) && (jc >= 0) && (jc < ny);
+  const int sux = G.su[0];
+  const long long nu1 = (long long)G.su[0] * G.su[1];
+  const T hx = T(G.h[0]), hy = T(G.h[1]);
+  T ux[3][3], uy[3][3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int mx = 2 * i + a, my = 2 * jc + b;
+      const long long o = mx + (long long)sux * my;
+      ux[b][a] = (valid && !ugrid_fixed(2, G.su, 0, mx, my, 0)) ? Xl[o] : T(0);
+      uy[b][a] = (valid && !ugrid_fixed(2, G.su, 1, mx, my, 0)) ? Xl[nu1 + o] : T(0);
+    }
+  const T pc[2][2] = {{0, 0}, {0, 0}};
+  T ox[3][3], oy[3][3];
+  elast2d<T>(ux, uy, pc, hx, hy, T(G.tau), T(0), T(G.lam), T(G.mu), ox, oy);
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      E[b * 3 + a][tid] = ox[b][a];
+      E[9 + b * 3 + a][tid] = oy[b][a];
+    }
+  __syncthreads();
+  const int mxe = (i0 + kUO >= nx) ? 2 * nx + 1 : 2 * i0 + 2 * kUO;
+  const int mye = (j0 + kUO >= ny) ? 2 * ny + 1 : 2 * j0 + 2 * kUO;
+  const int nmx = mxe - 2 * i0, nmy = mye - 2 * j0;
+  const int nuo = nmx * nmy;
+  for (int idx = tid; idx < 2 * nuo; idx += kUT * kUT) {
+    const int c = idx >= nuo;
+    const int rr = idx - c * nuo;
+    const int mx = 2 * i0 + rr % nmx, my = 2 * j0 + rr / nmx;
+    const long long go = c * nu1 + mx + (long long)sux * my;
+    T v;
+    if (ugrid_fixed(2, G.su, c, mx, my, 0)) {
+      v = T(0);
+    } else {
+      const bool xo = mx & 1, yo = my & 1;
+      const int cx0 = xo ? (mx - 1) / 2 : mx / 2 - 1, ax0 = xo ? 1 : 2;
+      const int cy0 = yo ? (my - 1) / 2 : my / 2 - 1, ay0 = yo ? 1 : 2;
+      const bool vx0 = cx0 >= 0, vx1 = !xo && (mx / 2 < nx);
+      const bool vy0 = cy0 >= 0, vy1 = !yo && (my / 2 < ny);
+      const int tx0 = cx0 - i0 + 1, ty0 = cy0 - j0 + 1;
+      v = 0;
+      if (vy0 && vx0) v += E[c * 9 + ay0 * 3 + ax0][ty0 * kUT + tx0];
+      if (vy0 && vx1) v += E[c * 9 + ay0 * 3 + 0][ty0 * kUT + tx0 + 1];
+      if (vy1 && vx0) v += E[c * 9 + ax0][(ty0 + 1) * kUT + tx0];
+      if (vy1 && vx1) v += E[c * 9 + 0][(ty0 + 1) * kUT + tx0 + 1];
+    }
+    Yl[go] = mode == 0 ? v : Bl[go] - v;
+  }
+}
+
+template <typename T>
+void launch_uapply(int dim, const UGridSeg* segs, const int4* work, int nwork, int nj, int mode, const T* x,
+                   const T* b, T* y, hipStream_t s) {
+  if (dim == 2) {
+    hipLaunchKernelGGL((uapply2d_kernel<T>), dim3(nwork, nj), dim3(kUT, kUT), 0, s, segs, work, mode, x, b, y);
+  } else {
+    launch_uapply3d<T>(segs, work, nwork, nj, mode, x, b, y, s);
+  }
+}
+template void launch_uapply<double>(int, const UGridSeg*, const int4*, int, int, int, const double*, const double*,
+                                    double*, hipStream_t);
+template void launch_uapply<float>(int, const UGridSeg*, const int4*, int, int, int, const float*, const float*,
+                                   float*, hipStream_t);
+
+// ---- restriction pass ------------------------------------------------------------------------
+template <typename T>
+__global__ void rpass_kernel(const RPass* __restrict__ segs, const double* __restrict__ tab, const T* __restrict__ in,
+                             T* __restrict__ out) {
+  const RPass P = segs[blockIdx.y];
+  const int j = blockIdx.z;
+  const long long ni = (long long)P.din[0] * P.din[1] * P.din[2];
+  const long long no = (long long)P.dout[0] * P.dout[1] * P.dout[2];
+  const T* I = in + P.ioff + j * P.ijstride;
+  T* O = out + P.ooff + j * P.ojstride;
+  const long long istr[3] = {1, (long long)P.din[0], (long long)P.din[0] * P.din[1]};
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < no * P.dim;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int c = (int)(t / no);
+    long long rem = t - c * no;
+    int co[3];
+    co[0] = rem % P.dout[0]; rem /= P.dout[0];
+    co[1] = rem % P.dout[1]; rem /= P.dout[1];
+    co[2] = (int)rem;
+    if (P.last && ugrid_fixed(P.dim, P.dout, c, co[0], co[1], co[2])) { O[t] = T(0); continue; }
+    long long base = c * ni;
+    for (int f = 0; f < 3; ++f)
+      if (f != P.axis) base += co[f] * istr[f];
+    const double* tr = tab + P.tab + (long long)co[P.axis] * 2 * P.width;
+    double s = 0.0;
+    for (int k = 0; k < P.width; ++k) {
+      const double wgt = tr[2 * k + 1];
+      if (wgt == 0.0) continue;
+      s += wgt * (double)I[base + (long long)tr[2 * k] * istr[P.axis]];
+    }
+    O[t] = (T)s;
+  }
+}
+template <typename T>
+void launch_rpass(const RPass* segs, int nseg, int nj, long long maxout, const double* tab, const T* in, T* out,
+                  hipStream_t s) {
+  long long b = (maxout + 255) / 256;
+  hipLaunchKernelGGL((rpass_kernel<T>), dim3((unsigned)(b > 65535 ? 65535 : (b < 1 ? 1 : b)), nseg, nj), dim3(256), 0,
+                     s, segs, tab, in, out);
+}
+template void launch_rpass<double>(const RPass*, int, int, long long, const double*, const double*, double*,
+                                   hipStream_t);
+template void launch_rpass<float>(const RPass*, int, int, long long, const double*, const float*, float*,
+                                  hipStream_t);
+
+// ---- prolongation: x_fine += P e_coarse ---------------------------------------------------------
+template <typename T>
+__global__ void uprolong_kernel(const UProl* __restrict__ segs, const double* __restrict__ tab,
+                                const T* __restrict__ e, T* __restrict__ x) {
+  const UProl P = segs[blockIdx.y];
+  const int j = blockIdx.z;
+  const long long nf = (long long)P.sf[0] * P.sf[1] * P.sf[2];
+  const long long nc = (long long)P.sc[0] * P.sc[1] * P.sc[2];
+  const T* Ec = e + P.coff + j * P.cjstride;
+  T* Xf = x + P.foff + j * P.fjstride;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < nf * P.dim;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int c = (int)(t / nf);
+    long long rem = t - c * nf;
+    int m[3];
+    m[0] = rem % P.sf[0]; rem /= P.sf[0];
+    m[1] = rem % P.sf[1]; rem /= P.sf[1];
+    m[2] = (int)rem;
+    if (ugrid_fixed(P.dim, P.sf, c, m[0], m[1], m[2])) continue;
+    const double* tx = tab + P.tab[0] + 4LL * m[0];
+    const double* ty = tab + P.tab[1] + 4LL * m[1];
+    const int Cx = (int)tx[0], Cy = (int)ty[0];
+    double s = 0.0;
+    if (P.dim == 2) {
+      for (int b = 0; b < 3; ++b)
+        for (int a = 0; a < 3; ++a)
+          s += tx[1 + a] * ty[1 + b] * (double)Ec[c * nc + (2 * Cx + a) + (long long)P.sc[0] * (2 * Cy + b)];
+    } else {
+      const double* tz = tab + P.tab[2] + 4LL * m[2];
+      const int Cz = (int)tz[0];
+      for (int cz = 0; cz < 3; ++cz)
+        for (int b = 0; b < 3; ++b)
+          for (int a = 0; a < 3; ++a)
+            s += tx[1 + a] * ty[1 + b] * tz[1 + cz] *
+                 (double)Ec[c * nc + (2 * Cx + a) + (long long)P.sc[0] * ((2 * Cy + b) + (long long)P.sc[1] * (2 * Cz + cz))];
+    }
+    Xf[t] += (T)s;
+  }
+}
+template <typename T>
+void launch_uprolong(const UProl* segs, int nseg, int nj, long long maxfine, const double* tab, const T* e, T* x,
+                     hipStream_t s) {
+  long long b = (maxfine + 255) / 256;
+  hipLaunchKernelGGL((uprolong_kernel<T>), dim3((unsigned)(b > 65535 ? 65535 : (b < 1 ? 1 : b)), nseg, nj), dim3(256),
+                     0, s, segs, tab, e, x);
+}
+template void launch_uprolong<double>(const UProl*, int, int, long long, const double*, const double*, double*,
+                                      hipStream_t);
+template void launch_uprolong<float>(const UProl*, int, int, long long, const double*, const float*, float*,
+                                     hipStream_t);
+
+// ---- y = Dinv x on level segments -------------------------------------------------------------------
+template <typename T>
+__global__ void muldinv_kernel(const LSeg* __restrict__ segs, const T* __restrict__ dinv, const T* __restrict__ x,
+                               T* __restrict__ y) {
+  const LSeg sg = segs[blockIdx.y];
+  const long long off = sg.off + blockIdx.z * sg.jstride, doff = sg.doff + blockIdx.z * sg.djstride;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < sg.len;
+       i += (long long)gridDim.x * blockDim.x)
+    y[off + i] = dinv[doff + i] * x[off + i];
+}
+template <typename T>
+void launch_mul_dinv(const LSeg* segs, int nseg, int nj, long long maxlen, const T* dinv, const T* x, T* y,
+                     hipStream_t s) {
+  long long b = (maxlen + 255) / 256;
+  hipLaunchKernelGGL((muldinv_kernel<T>), dim3((unsigned)(b > 65535 ? 65535 : (b < 1 ? 1 : b)), nseg, nj), dim3(256), 0,
+                     s, segs, dinv, x, y);
+}
+template void launch_mul_dinv<double>(const LSeg*, int, int, long long, const double*, const double*, double*,
+                                      hipStream_t);
+template void launch_mul_dinv<float>(const LSeg*, int, int, long long, const float*, const float*, float*,
+                                     hipStream_t);
+
+}  // namespace bt

@@ -227,6 +227,7 @@ biot_status biot_workspace_bytes(const biot_problem_desc* descs, int32_t count, 
   build_host_state(&tmp, descs, count);
   Layout L;
   plan_layout(&tmp, L, false);
+  destroy_solver(&tmp);
   *bytes = L.off + 256;
   BIOT_CATCH
 }

@@ -1,16 +1,1182 @@
-// Slab solver: right-hand side, GMRES driver, marching and adjoint sweep.
+// Slab solver (host orchestration): preconditioner hierarchy set-up, the
+// level-blockwise fixed-stress preconditioner, restarted GMRES (FP64, or FP32
+// inner solves inside FP64 iterative refinement), slab marching and the
+// discrete adjoint sweep.
+//
+// Sections "Monolithic Approach" and "Preconditioning technology": the slab
+// matrix A = T kron M_t + tau I kron K_s is preconditioned in the real block
+// eigenbasis of T, where it is block diagonal up to the +-beta M_t couplings of
+// complex eigenvalue pairs; those couplings are dropped ("diagonal blockwise")
+// and every remaining dG(0)-type block L_j = alpha_j M_t + tau K_s is
+// approximated by one truncated fixed-stress sweep.
 #include "solver.h"
 
+#include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <random>
 #include <string>
+#include <type_traits>
+#include <vector>
 
+#include "kernels.h"
 #include "kernels_aux.h"
+#include "prec.h"
+#include "vec.h"
 
 namespace bt {
-void plan_solver_layout(biot_problem_s*, Layout&, bool) {}
-void setup_solver(biot_problem_s*, hipStream_t) {}
-void refresh_solver(biot_problem_s*, hipStream_t) {}
-void destroy_solver(biot_problem_s*) {}
+
+constexpr int kMaxRestart = 64;
+constexpr int kNChunk = 96;
+constexpr double kOmegaP = 1.6;          // coarse-correction over-relaxation of the aggregation multigrid
+constexpr int kPDeg = 3;                 // Chebyshev smoothing degree, pressure levels
+constexpr double kPLo = 1.0 / 8.0, kPHi = 1.1;
+constexpr int kUDeg = 2;                 // elasticity levels
+constexpr double kULo = 1.0 / 15.0, kUHi = 1.1;
+constexpr double kQLo = 0.25, kQHi = 1.75;  // Gershgorin interval of Dq^-1 Mq
+constexpr long long kPCoarseCells = 64;
+constexpr long long kUCoarseDofs = 1100;
+
+template <typename T>
+struct PrecBufs {
+  T* V = nullptr;
+  T *w = nullptr, *t = nullptr, *r = nullptr;
+  T *Wr = nullptr, *Wz = nullptr, *Wf = nullptr, *T1 = nullptr, *T2 = nullptr, *T3 = nullptr, *T4 = nullptr;
+  T* dqinv = nullptr;
+  T* pdg_dinv = nullptr;
+  std::vector<T*> pc_x, pc_b, pc_r, pc_d0, pc_d1, pc_coef, pc_dinv;
+  std::vector<T*> u_x, u_b, u_r, u_d0, u_d1, u_y, u_dinv, u_t1, u_t2;
+  T* kinv = nullptr;
+  T *xin = nullptr, *bin = nullptr;   // mixed precision: inner solution / right-hand side
+};
+
+struct PrecData {
+  int nl = 1, dim = 2, count = 1;
+  // pressure hierarchy
+  int npl = 0;
+  std::vector<PDgSeg> pdg;
+  PDgSeg* d_pdg = nullptr;
+  long long pdg_total = 0, pdg_max = 0;
+  std::vector<std::vector<PCellSeg>> pc;
+  std::vector<PCellSeg*> d_pc;
+  std::vector<long long> pc_total, pc_max;
+  // elasticity hierarchy
+  int nul = 0;
+  std::vector<std::vector<UGridSeg>> ug;        // level 0: slab layout
+  std::vector<UGridSeg*> d_ug;
+  std::vector<UGridSeg> ug0c;                   // level 0 compact layout (set-up)
+  UGridSeg* d_ug0c = nullptr;
+  std::vector<long long> u_total, u_max;
+  std::vector<std::vector<int4>> uwork;
+  std::vector<int4*> d_uwork;
+  std::vector<std::vector<std::vector<RPass>>> rp;   // [transition][pass][inst]
+  std::vector<std::vector<RPass*>> d_rp;
+  std::vector<std::vector<long long>> rp_max;
+  std::vector<long long> t1_total, t2_total;
+  std::vector<std::vector<UProl>> up;
+  std::vector<UProl*> d_up;
+  std::vector<std::vector<LSeg>> ul;            // Chebyshev segments per u level (level 0 slab layout)
+  std::vector<LSeg*> d_ul;
+  std::vector<LSeg> ul0c;
+  LSeg* d_ul0c = nullptr;
+  std::vector<double> utab_h;
+  double* d_utab = nullptr;
+  // coarse dense solves
+  std::vector<DSeg> ud, pd;
+  DSeg *d_ud = nullptr, *d_pd = nullptr;
+  double *uAinv = nullptr, *pAinv = nullptr;
+  int u_maxn = 0, p_maxn = 0;
+  long long uAinv_len = 0, pAinv_len = 0;
+  // GMRES segments
+  std::vector<VSeg> gseg;
+  VSeg* d_gseg = nullptr;
+  long long gmax = 0;
+  // scalars
+  double *partial = nullptr, *dot1 = nullptr, *dot2 = nullptr, *dot3 = nullptr, *coef = nullptr, *scal = nullptr;
+  // adjoint helpers
+  double *lam = nullptr, *lam_next = nullptr, *xfwd = nullptr, *arhs = nullptr, *sres = nullptr, *sobs = nullptr;
+  SensorW* sw = nullptr;
+  int max_sens = 256;
+  PrecBufs<double> b64;
+  PrecBufs<float> b32;
+  Mat4 Q, Qi;
+  long long maxN = 0, maxcells = 0;
+};
+
+template <typename T>
+PrecBufs<T>& bufs(PrecData* P);
+template <>
+PrecBufs<double>& bufs<double>(PrecData* P) { return P->b64; }
+template <>
+PrecBufs<float>& bufs<float>(PrecData* P) { return P->b32; }
+
+// ---------------------------------------------------------------------------
+// hierarchy description (host), identical for sizing and carving
+// ---------------------------------------------------------------------------
+static int half(int n) { return (n + 1) / 2; }
+
+// 1D interpolation of the coarse Q2 basis (nc cells) at the fine Q2 nodes (nf cells), both on [0, L]
+static void interp_table(int nf, int nc, std::vector<double>& prol, std::vector<std::vector<std::pair<int, double>>>& rows) {
+  const double L = 1.0;
+  const double hf = L / nf, hc = L / nc;
+  prol.assign(4 * (2 * nf + 1), 0.0);
+  rows.assign(2 * nc + 1, {});
+  for (int m = 0; m < 2 * nf + 1; ++m) {
+    const double x = m * hf / 2.0;
+    int C = (int)std::floor(x / hc + 1e-12);
+    if (C > nc - 1) C = nc - 1;
+    if (C < 0) C = 0;
+    double s = x / hc - C;
+    if (std::fabs(s) < 1e-13) s = 0.0;
+    if (std::fabs(s - 1.0) < 1e-13) s = 1.0;
+    prol[4 * m] = C;
+    for (int a = 0; a < 3; ++a) {
+      double w = phi(a, s);
+      if (std::fabs(w) < 1e-14) w = 0.0;
+      prol[4 * m + 1 + a] = w;
+      if (w != 0.0) rows[2 * C + a].push_back({m, w});
+    }
+  }
+}
+
+static void build_hierarchy(biot_problem_s* h, PrecData* P) {
+  const int d = h->dim, nl = h->nl, cnt = h->count;
+  P->nl = nl; P->dim = d; P->count = cnt;
+  P->maxN = 0; P->maxcells = 0;
+  for (auto& I : h->inst) { P->maxN = std::max(P->maxN, I.N); P->maxcells = std::max(P->maxcells, I.ncells); }
+  // ---- pressure: DG level segments
+  P->pdg.clear();
+  long long off = 0;
+  P->pdg_max = 0;
+  for (int k = 0; k < cnt; ++k) {
+    const InstDev& I = h->inst[k];
+    const auto& D = h->descs[k];
+    PDgSeg s;
+    std::memset(&s, 0, sizeof(s));
+    s.inst = k;
+    s.voff = I.x_off + I.off_p;
+    s.vjstride = I.N;
+    s.dqoff = I.state_off;
+    const long long np = (long long)I.sp[0] * I.sp[1] * I.sp[2];
+    s.doff = off;
+    s.djstride = np;
+    off += nl * np;
+    const double kdr = D.lambda + 2.0 * D.mu / d;
+    const double L = D.L_fs > 0 ? D.L_fs : D.b * D.b / kdr;
+    for (int j = 0; j < 4; ++j) s.cm[j] = (j < nl) ? h->tc.alpha[j] * (1.0 / D.M + L) : 0.0;
+    P->pdg.push_back(s);
+    P->pdg_max = std::max(P->pdg_max, np);
+  }
+  P->pdg_total = off;
+  // ---- pressure cell levels (uniform depth across the batch)
+  std::vector<std::array<int, 3>> n(cnt);
+  for (int k = 0; k < cnt; ++k) n[k] = {h->inst[k].n[0], h->inst[k].n[1], h->inst[k].n[2]};
+  P->pc.clear(); P->pc_total.clear(); P->pc_max.clear();
+  while (true) {
+    std::vector<PCellSeg> lev;
+    long long voff = 0, coff = 0, doff = 0, mx = 0;
+    for (int k = 0; k < cnt; ++k) {
+      PCellSeg s;
+      std::memset(&s, 0, sizeof(s));
+      s.dim = d;
+      for (int e = 0; e < 3; ++e) s.n[e] = e < d ? n[k][e] : 1;
+      s.ncells = (long long)s.n[0] * s.n[1] * s.n[2];
+      s.voff = voff; s.vjstride = s.ncells; voff += nl * s.ncells;
+      s.coff = coff; coff += 5 * s.ncells;
+      s.doff = doff; s.djstride = s.ncells; doff += nl * s.ncells;
+      for (int j = 0; j < 4; ++j) s.cm[j] = P->pdg[k].cm[j];
+      lev.push_back(s);
+      mx = std::max(mx, s.ncells);
+    }
+    P->pc.push_back(lev);
+    P->pc_total.push_back(voff / nl);
+    P->pc_max.push_back(mx);
+    if (mx <= kPCoarseCells) break;
+    for (int k = 0; k < cnt; ++k)
+      for (int e = 0; e < d; ++e) n[k][e] = half(n[k][e]);
+  }
+  P->npl = (int)P->pc.size();
+  // ---- elasticity levels
+  for (int k = 0; k < cnt; ++k) n[k] = {h->inst[k].n[0], h->inst[k].n[1], h->inst[k].n[2]};
+  P->ug.clear(); P->u_total.clear(); P->u_max.clear(); P->ul.clear();
+  P->ug0c.clear(); P->ul0c.clear();
+  int level = 0;
+  long long dinv_off = 0;
+  std::vector<long long> dinv_base;
+  while (true) {
+    std::vector<UGridSeg> lev;
+    std::vector<LSeg> ls;
+    long long voff = 0, mx = 0, lvtot = 0;
+    for (int k = 0; k < cnt; ++k) {
+      const auto& D = h->descs[k];
+      UGridSeg g;
+      std::memset(&g, 0, sizeof(g));
+      g.dim = d;
+      for (int e = 0; e < 3; ++e) {
+        g.n[e] = e < d ? n[k][e] : 1;
+        g.su[e] = e < d ? 2 * n[k][e] + 1 : 1;
+        g.h[e] = e < d ? D.length[e] / n[k][e] : 1.0;
+      }
+      g.tau = D.tau; g.lam = D.lambda; g.mu = D.mu;
+      g.nu = (long long)d * g.su[0] * g.su[1] * g.su[2];
+      g.doff = dinv_off + lvtot;
+      if (level == 0) { g.voff = h->inst[k].x_off + h->inst[k].off_u[0]; g.vjstride = h->inst[k].N; }
+      else { g.voff = voff; g.vjstride = g.nu; voff += nl * g.nu; }
+      lev.push_back(g);
+      LSeg l;
+      l.off = g.voff; l.jstride = g.vjstride; l.len = g.nu; l.doff = g.doff; l.djstride = 0;
+      ls.push_back(l);
+      if (level == 0) {
+        UGridSeg gc = g;
+        gc.voff = lvtot; gc.vjstride = g.nu;
+        P->ug0c.push_back(gc);
+        LSeg lc = l;
+        lc.off = gc.voff; lc.jstride = gc.vjstride;
+        P->ul0c.push_back(lc);
+      }
+      lvtot += g.nu;
+      mx = std::max(mx, g.nu);
+    }
+    dinv_base.push_back(dinv_off);
+    dinv_off += lvtot;
+    P->ug.push_back(lev);
+    P->ul.push_back(ls);
+    P->u_total.push_back(lvtot);
+    P->u_max.push_back(mx);
+    ++level;
+    if (mx <= kUCoarseDofs) break;
+    for (int k = 0; k < cnt; ++k)
+      for (int e = 0; e < d; ++e) n[k][e] = half(n[k][e]);
+  }
+  P->nul = (int)P->ug.size();
+  // work lists per u level
+  P->uwork.assign(P->nul, {});
+  const int t = uapply_tile(d);
+  for (int l = 0; l < P->nul; ++l)
+    for (int k = 0; k < cnt; ++k) {
+      const UGridSeg& g = P->ug[l][k];
+      if (d == 2) {
+        for (int ty = 0; ty < (g.n[1] + t - 1) / t; ++ty)
+          for (int tx = 0; tx < (g.n[0] + t - 1) / t; ++tx) P->uwork[l].push_back(make_int4(k, tx, ty, 0));
+      } else {
+        const int txy = apply3d_tile_cells_xy(), tz = apply3d_tile_cells_z();
+        for (int z = 0; z < (g.n[2] + tz - 1) / tz; ++z)
+          for (int ty = 0; ty < (g.n[1] + txy - 1) / txy; ++ty)
+            for (int tx = 0; tx < (g.n[0] + txy - 1) / txy; ++tx) P->uwork[l].push_back(make_int4(k, tx, ty, z));
+      }
+    }
+  // transfers per transition l -> l+1
+  P->utab_h.clear();
+  P->rp.assign(std::max(0, P->nul - 1), {});
+  P->rp_max.assign(std::max(0, P->nul - 1), {});
+  P->up.assign(std::max(0, P->nul - 1), {});
+  P->t1_total.assign(std::max(0, P->nul - 1), 0);
+  P->t2_total.assign(std::max(0, P->nul - 1), 0);
+  for (int l = 0; l + 1 < P->nul; ++l) {
+    P->rp[l].assign(d, {});
+    P->rp_max[l].assign(d, 0);
+    long long t1o = 0, t2o = 0;
+    for (int k = 0; k < cnt; ++k) {
+      const UGridSeg& F = P->ug[l][k];
+      const UGridSeg& C = P->ug[l + 1][k];
+      long long tabp[3] = {0, 0, 0}, tabr[3] = {0, 0, 0};
+      int width[3] = {1, 1, 1};
+      for (int e = 0; e < d; ++e) {
+        std::vector<double> prol;
+        std::vector<std::vector<std::pair<int, double>>> rows;
+        interp_table(F.n[e], C.n[e], prol, rows);
+        tabp[e] = (long long)P->utab_h.size();
+        P->utab_h.insert(P->utab_h.end(), prol.begin(), prol.end());
+        int w = 1;
+        for (auto& rw : rows) w = std::max(w, (int)rw.size());
+        width[e] = w;
+        tabr[e] = (long long)P->utab_h.size();
+        for (auto& rw : rows) {
+          for (int q = 0; q < w; ++q) {
+            if (q < (int)rw.size()) { P->utab_h.push_back(rw[q].first); P->utab_h.push_back(rw[q].second); }
+            else { P->utab_h.push_back(0.0); P->utab_h.push_back(0.0); }
+          }
+        }
+      }
+      UProl pr;
+      std::memset(&pr, 0, sizeof(pr));
+      pr.dim = d;
+      for (int e = 0; e < 3; ++e) { pr.sf[e] = F.su[e]; pr.sc[e] = C.su[e]; pr.tab[e] = tabp[e]; }
+      pr.foff = F.voff; pr.fjstride = F.vjstride; pr.coff = C.voff; pr.cjstride = C.vjstride;
+      P->up[l].push_back(pr);
+      // separable restriction passes: axis 0 -> t1, axis 1 -> t2 (3D) / coarse (2D), axis 2 -> coarse
+      int cur[3] = {F.su[0], F.su[1], F.su[2]};
+      for (int pass = 0; pass < d; ++pass) {
+        RPass rp;
+        std::memset(&rp, 0, sizeof(rp));
+        rp.dim = d;
+        rp.axis = pass;
+        rp.width = width[pass];
+        rp.last = pass == d - 1;
+        for (int e = 0; e < 3; ++e) rp.din[e] = cur[e];
+        cur[pass] = C.su[pass];
+        for (int e = 0; e < 3; ++e) rp.dout[e] = cur[e];
+        rp.tab = tabr[pass];
+        const long long nout = (long long)d * cur[0] * cur[1] * cur[2];
+        P->rp_max[l][pass] = std::max(P->rp_max[l][pass], nout);
+        // input
+        if (pass == 0) { rp.ioff = F.voff; rp.ijstride = F.vjstride; }
+        else {
+          const auto& prev = P->rp[l][pass - 1].back();
+          rp.ioff = prev.ooff; rp.ijstride = prev.ojstride;
+        }
+        // output
+        if (rp.last) { rp.ooff = C.voff; rp.ojstride = C.vjstride; }
+        else if (pass == 0) { rp.ooff = t1o; rp.ojstride = nout; t1o += nl * nout; }
+        else { rp.ooff = t2o; rp.ojstride = nout; t2o += nl * nout; }
+        P->rp[l][pass].push_back(rp);
+      }
+    }
+    P->t1_total[l] = t1o;
+    P->t2_total[l] = t2o;
+  }
+  // dense coarse segments
+  P->ud.clear(); P->pd.clear();
+  P->u_maxn = 0; P->p_maxn = 0;
+  long long mo = 0;
+  for (int k = 0; k < cnt; ++k) {
+    const UGridSeg& g = P->ug[P->nul - 1][k];
+    DSeg s;
+    std::memset(&s, 0, sizeof(s));
+    s.off = g.voff; s.jstride = g.vjstride; s.n = (int)g.nu; s.moff = mo; s.mjstride = 0;
+    mo += g.nu * g.nu;
+    P->ud.push_back(s);
+    P->u_maxn = std::max(P->u_maxn, s.n);
+  }
+  P->uAinv_len = mo;
+  mo = 0;
+  for (int k = 0; k < cnt; ++k) {
+    const PCellSeg& c = P->pc[P->npl - 1][k];
+    DSeg s;
+    std::memset(&s, 0, sizeof(s));
+    s.off = c.voff; s.jstride = c.vjstride; s.n = (int)c.ncells; s.moff = mo; s.mjstride = c.ncells * c.ncells;
+    mo += nl * c.ncells * c.ncells;
+    P->pd.push_back(s);
+    P->p_maxn = std::max(P->p_maxn, s.n);
+  }
+  P->pAinv_len = mo;
+  // GMRES segments
+  P->gseg.clear();
+  P->gmax = 0;
+  for (auto& I : h->inst) {
+    VSeg s{I.x_off, I.N * nl};
+    P->gseg.push_back(s);
+    P->gmax = std::max(P->gmax, s.len);
+  }
+}
+
+template <typename T>
+static void carve_bufs(biot_problem_s* h, PrecData* P, PrecBufs<T>& B, Layout& L, bool fp32) {
+  const long long S = h->slab_len;
+  B.V = L.take<T>((size_t)(kMaxRestart + 1) * S);
+  B.w = L.take<T>(S); B.t = L.take<T>(S); B.r = L.take<T>(S);
+  B.xin = L.take<T>(S); B.bin = L.take<T>(S);
+  B.Wr = L.take<T>(S); B.Wz = L.take<T>(S); B.Wf = L.take<T>(S);
+  B.T1 = L.take<T>(S); B.T2 = L.take<T>(S); B.T3 = L.take<T>(S); B.T4 = L.take<T>(S);
+  B.dqinv = L.take<T>(h->state_len);
+  B.pdg_dinv = L.take<T>(P->pdg_total);
+  const int nl = h->nl;
+  B.pc_x.assign(P->npl, nullptr); B.pc_b = B.pc_x; B.pc_r = B.pc_x; B.pc_d0 = B.pc_x; B.pc_d1 = B.pc_x;
+  B.pc_coef = B.pc_x; B.pc_dinv = B.pc_x;
+  for (int l = 0; l < P->npl; ++l) {
+    const long long n = P->pc_total[l];
+    B.pc_x[l] = L.take<T>(nl * n); B.pc_b[l] = L.take<T>(nl * n); B.pc_r[l] = L.take<T>(nl * n);
+    B.pc_d0[l] = L.take<T>(nl * n); B.pc_d1[l] = L.take<T>(nl * n);
+    B.pc_coef[l] = L.take<T>(5 * n); B.pc_dinv[l] = L.take<T>(nl * n);
+  }
+  B.u_x.assign(P->nul, nullptr); B.u_b = B.u_x; B.u_r = B.u_x; B.u_d0 = B.u_x; B.u_d1 = B.u_x; B.u_y = B.u_x;
+  B.u_dinv = B.u_x; B.u_t1 = B.u_x; B.u_t2 = B.u_x;
+  long long dtot = 0;
+  for (int l = 0; l < P->nul; ++l) dtot += P->u_total[l];
+  T* dall = L.take<T>(dtot);
+  for (int l = 0; l < P->nul; ++l) {
+    B.u_dinv[l] = dall;   // every level's segments carry absolute offsets into this array
+    if (l == 0) continue;
+    const long long n = P->u_total[l];
+    B.u_x[l] = L.take<T>(nl * n); B.u_b[l] = L.take<T>(nl * n); B.u_r[l] = L.take<T>(nl * n);
+    B.u_d0[l] = L.take<T>(nl * n); B.u_d1[l] = L.take<T>(nl * n); B.u_y[l] = L.take<T>(nl * n);
+  }
+  for (int l = 0; l + 1 < P->nul; ++l) {
+    B.u_t1[l] = L.take<T>(std::max(1LL, P->t1_total[l]));
+    B.u_t2[l] = L.take<T>(std::max(1LL, P->t2_total[l]));
+  }
+  (void)fp32;
+}
+
+void plan_solver_layout(biot_problem_s* h, Layout& L, bool carve) {
+  PrecData* P = h->prec;
+  if (!P) {
+    P = new PrecData();
+    h->prec = P;
+  }
+  build_hierarchy(h, P);
+  carve_bufs<double>(h, P, P->b64, L, false);
+  carve_bufs<float>(h, P, P->b32, L, true);
+  P->b64.kinv = nullptr;
+  P->b32.kinv = nullptr;
+  P->d_pdg = L.take<PDgSeg>(P->pdg.size());
+  P->d_pc.assign(P->npl, nullptr);
+  for (int l = 0; l < P->npl; ++l) P->d_pc[l] = L.take<PCellSeg>(P->pc[l].size());
+  P->d_ug.assign(P->nul, nullptr);
+  P->d_uwork.assign(P->nul, nullptr);
+  P->d_ul.assign(P->nul, nullptr);
+  for (int l = 0; l < P->nul; ++l) {
+    P->d_ug[l] = L.take<UGridSeg>(P->ug[l].size());
+    P->d_uwork[l] = L.take<int4>(P->uwork[l].size());
+    P->d_ul[l] = L.take<LSeg>(P->ul[l].size());
+  }
+  P->d_ug0c = L.take<UGridSeg>(P->ug0c.size());
+  P->d_ul0c = L.take<LSeg>(P->ul0c.size());
+  P->d_rp.assign(std::max(0, P->nul - 1), {});
+  P->d_up.assign(std::max(0, P->nul - 1), nullptr);
+  for (int l = 0; l + 1 < P->nul; ++l) {
+    for (int pass = 0; pass < P->dim; ++pass) P->d_rp[l].push_back(L.take<RPass>(P->rp[l][pass].size()));
+    P->d_up[l] = L.take<UProl>(P->up[l].size());
+  }
+  P->d_utab = L.take<double>(std::max<size_t>(1, P->utab_h.size()));
+  P->d_ud = L.take<DSeg>(P->ud.size());
+  P->d_pd = L.take<DSeg>(P->pd.size());
+  P->uAinv = L.take<double>(P->uAinv_len);
+  P->pAinv = L.take<double>(P->pAinv_len);
+  P->d_gseg = L.take<VSeg>(P->gseg.size());
+  const size_t nsc = (size_t)std::max(h->count * h->nl, h->count) * 64;
+  P->partial = L.take<double>((size_t)std::max(h->count * h->nl, h->count) * kNChunk * 64);
+  P->dot1 = L.take<double>(nsc); P->dot2 = L.take<double>(nsc); P->dot3 = L.take<double>(nsc);
+  P->coef = L.take<double>(nsc); P->scal = L.take<double>(nsc);
+  P->lam = L.take<double>(h->slab_len);
+  P->lam_next = L.take<double>(h->slab_len);
+  P->xfwd = L.take<double>(h->slab_len);
+  P->arhs = L.take<double>(h->slab_len);
+  P->sres = L.take<double>((size_t)h->count * P->max_sens);
+  P->sobs = L.take<double>((size_t)h->count * P->max_sens);
+  P->sw = L.take<SensorW>((size_t)h->count * P->max_sens);
+  if (!carve) {
+    // sizing pass only: forget device pointers
+    P->b64 = PrecBufs<double>();
+    P->b32 = PrecBufs<float>();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host dense helpers
+// ---------------------------------------------------------------------------
+static void invert_dense(std::vector<double>& A, int n) {
+  // Gauss-Jordan with partial pivoting, in place
+  std::vector<int> piv(n);
+  std::vector<double> I(n * (size_t)n, 0.0);
+  for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(A[(size_t)i * n + k]) > std::fabs(A[(size_t)p * n + k])) p = i;
+    if (A[(size_t)p * n + k] == 0.0) throw BiotError{BIOT_ERR_ARG, "singular coarse matrix"};
+    if (p != k) {
+      for (int j = 0; j < n; ++j) {
+        std::swap(A[(size_t)k * n + j], A[(size_t)p * n + j]);
+        std::swap(I[(size_t)k * n + j], I[(size_t)p * n + j]);
+      }
+    }
+    const double inv = 1.0 / A[(size_t)k * n + k];
+    for (int j = 0; j < n; ++j) { A[(size_t)k * n + j] *= inv; I[(size_t)k * n + j] *= inv; }
+    for (int i = 0; i < n; ++i) {
+      if (i == k) continue;
+      const double f = A[(size_t)i * n + k];
+      if (f == 0.0) continue;
+      double* Ai = &A[(size_t)i * n];
+      double* Ii = &I[(size_t)i * n];
+      const double* Ak = &A[(size_t)k * n];
+      const double* Ik = &I[(size_t)k * n];
+      for (int j = 0; j < n; ++j) { Ai[j] -= f * Ak[j]; Ii[j] -= f * Ik[j]; }
+    }
+  }
+  A.swap(I);
+}
+
+// tau * Q2 elasticity element matrix on a cell of size h (local order [comp][node, x fastest])
+static std::vector<double> elast_element(int d, const double* hh, double lam, double mu, double tau) {
+  const int nn = d == 2 ? 9 : 27, nloc = d * nn;
+  std::vector<double> K((size_t)nloc * nloc, 0.0);
+  const int nq = d == 2 ? 9 : 27;
+  for (int q = 0; q < nq; ++q) {
+    const int kq[3] = {q % 3, (q / 3) % 3, d == 3 ? q / 9 : 0};
+    double W = 1.0;
+    for (int e = 0; e < d; ++e) W *= wq(kq[e]) * hh[e];
+    // gradients of the scalar nodal functions at q
+    std::vector<std::array<double, 3>> g(nn);
+    for (int a = 0; a < nn; ++a) {
+      const int aa[3] = {a % 3, (a / 3) % 3, d == 3 ? a / 9 : 0};
+      for (int e = 0; e < d; ++e) {
+        double v = 1.0;
+        for (int f = 0; f < d; ++f) v *= (f == e) ? dphi(aa[f], xq(kq[f])) / hh[f] : phi(aa[f], xq(kq[f]));
+        g[a][e] = v;
+      }
+    }
+    for (int c = 0; c < d; ++c)
+      for (int a = 0; a < nn; ++a)
+        for (int c2 = 0; c2 < d; ++c2)
+          for (int b = 0; b < nn; ++b) {
+            // a(u,v): v = phi_a e_c (test), u = phi_b e_c2 (trial)
+            double val = lam * g[a][c] * g[b][c2];
+            val += mu * g[a][c2] * g[b][c];
+            if (c == c2)
+              for (int e = 0; e < d; ++e) val += mu * g[a][e] * g[b][e];
+            K[(size_t)(c * nn + a) * nloc + (c2 * nn + b)] += tau * W * val;
+          }
+  }
+  return K;
+}
+
+static std::vector<double> coarse_elast_inverse(const UGridSeg& g) {
+  const int d = g.dim;
+  const int n = (int)g.nu;
+  const long long nn = (long long)g.su[0] * g.su[1] * g.su[2];
+  std::vector<double> A((size_t)n * n, 0.0);
+  auto Ke = elast_element(d, g.h, g.lam, g.mu, g.tau);
+  const int nnl = d == 2 ? 9 : 27, nloc = d * nnl;
+  std::vector<long long> gidx(nloc);
+  for (int k = 0; k < g.n[2]; ++k)
+    for (int j = 0; j < g.n[1]; ++j)
+      for (int i = 0; i < g.n[0]; ++i) {
+        for (int c = 0; c < d; ++c)
+          for (int a = 0; a < nnl; ++a) {
+            const int ax = a % 3, ay = (a / 3) % 3, az = d == 3 ? a / 9 : 0;
+            gidx[c * nnl + a] = c * nn + (2 * i + ax) + (long long)g.su[0] * ((2 * j + ay) + (long long)g.su[1] * (2 * k + az));
+          }
+        for (int r = 0; r < nloc; ++r)
+          for (int c = 0; c < nloc; ++c) A[(size_t)gidx[r] * n + gidx[c]] += Ke[(size_t)r * nloc + c];
+      }
+  for (int c = 0; c < d; ++c)
+    for (long long t = 0; t < nn; ++t) {
+      const int mx = t % g.su[0], my = (t / g.su[0]) % g.su[1], mz = (int)(t / ((long long)g.su[0] * g.su[1]));
+      if (!ugrid_fixed(d, g.su, c, mx, my, mz)) continue;
+      const long long row = c * nn + t;
+      for (int q = 0; q < n; ++q) { A[(size_t)row * n + q] = 0.0; A[(size_t)q * n + row] = 0.0; }
+      A[(size_t)row * n + row] = 1.0;
+    }
+  invert_dense(A, n);
+  return A;
+}
+
+// diag of tau*A on a level (host), 1 on essential rows
+static std::vector<double> elast_diag(const UGridSeg& g) {
+  const int d = g.dim;
+  const long long nn = (long long)g.su[0] * g.su[1] * g.su[2];
+  std::vector<double> D(d * nn, 0.0);
+  auto Ke = elast_element(d, g.h, g.lam, g.mu, g.tau);
+  const int nnl = d == 2 ? 9 : 27, nloc = d * nnl;
+  for (int c = 0; c < d; ++c)
+    for (long long t = 0; t < nn; ++t) {
+      const int m[3] = {(int)(t % g.su[0]), (int)((t / g.su[0]) % g.su[1]), (int)(t / ((long long)g.su[0] * g.su[1]))};
+      if (ugrid_fixed(d, g.su, c, m[0], m[1], m[2])) { D[c * nn + t] = 1.0; continue; }
+      // cells containing the node: local index per axis
+      double s = 0.0;
+      int cl[3][2], al[3][2], ncl[3];
+      for (int e = 0; e < 3; ++e) {
+        ncl[e] = 0;
+        if (e >= d) { cl[e][0] = 0; al[e][0] = 0; ncl[e] = 1; continue; }
+        if (m[e] & 1) { cl[e][0] = (m[e] - 1) / 2; al[e][0] = 1; ncl[e] = 1; }
+        else {
+          if (m[e] / 2 - 1 >= 0) { cl[e][ncl[e]] = m[e] / 2 - 1; al[e][ncl[e]] = 2; ++ncl[e]; }
+          if (m[e] / 2 < g.n[e]) { cl[e][ncl[e]] = m[e] / 2; al[e][ncl[e]] = 0; ++ncl[e]; }
+        }
+      }
+      for (int iz = 0; iz < ncl[2]; ++iz)
+        for (int iy = 0; iy < ncl[1]; ++iy)
+          for (int ix = 0; ix < ncl[0]; ++ix) {
+            const int a = al[0][ix] + 3 * al[1][iy] + 9 * al[2][iz];
+            s += Ke[(size_t)(c * nnl + a) * nloc + (c * nnl + a)];
+          }
+      D[c * nn + t] = 1.0 / s;
+    }
+  return D;
+}
+
+// ---------------------------------------------------------------------------
+// set-up
+// ---------------------------------------------------------------------------
+struct ChebSeq {
+  double s0;
+  std::vector<std::pair<double, double>> steps;   // (rho, sig) for step k
+};
+static ChebSeq cheb_seq(double lo, double hi, int deg) {
+  ChebSeq c;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  c.s0 = 1.0 / theta;
+  for (int k = 0; k < deg; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    c.steps.push_back({rn * rho, 2.0 * rn / delta});
+    rho = rn;
+  }
+  return c;
+}
+
+// host -> device copy of a host vector; waits, so the host buffer may go away afterwards
+template <typename X>
+static void upload(const std::vector<X>& v, X* d, hipStream_t s) {
+  if (v.empty()) return;
+  hip_check(hipMemcpyAsync(d, v.data(), sizeof(X) * v.size(), hipMemcpyHostToDevice, s), "upload");
+  hip_check(hipStreamSynchronize(s), "upload sync");
+}
+
+// power iteration for lambda_max(Dinv S) per segment; apply(x, y) computes y = Dinv S x
+template <typename F>
+static std::vector<double> power_max(PrecData* P, F apply, double* x, double* y, const std::vector<VSeg>& segs,
+                                     long long span, hipStream_t s, int iters = 14) {
+  const int ns = (int)segs.size();
+  VSeg* dsegs = (VSeg*)P->scal;   // reuse a scalar block for the segment list (small)
+  static_assert(sizeof(VSeg) == 16, "VSeg layout");
+  if ((size_t)ns * sizeof(VSeg) > (size_t)std::max(P->count * P->nl, P->count) * 64 * sizeof(double))
+    throw BiotError{BIOT_ERR_ARG, "too many power-iteration segments"};
+  upload(segs, dsegs, s);
+  std::vector<double> hx(span);
+  std::mt19937_64 rng(12345);
+  std::uniform_real_distribution<double> U(0.5, 1.5);
+  for (auto& v : hx) v = U(rng);
+  hip_check(hipMemcpyAsync(x, hx.data(), 8 * span, hipMemcpyHostToDevice, s), "power init");
+  hip_check(hipStreamSynchronize(s), "power init sync");
+  long long mx = 0;
+  for (auto& sg : segs) mx = std::max(mx, sg.len);
+  std::vector<double> nrm(ns * 64), lam(ns, 1.0);
+  for (int it = 0; it < iters; ++it) {
+    seg_mdot<double, double>(x, 0, 1, x, dsegs, ns, 8, P->partial, P->dot1, s);
+    seg_scale<double, double>(x, x, P->dot1, 0, 2, dsegs, ns, mx, s);   // x / ||x||
+    apply(x, y);
+    seg_mdot<double, double>(y, 0, 1, y, dsegs, ns, 8, P->partial, P->dot1, s);
+    hip_check(hipMemcpyAsync(nrm.data(), P->dot1, 8 * ns * 64, hipMemcpyDeviceToHost, s), "power norm");
+    hip_check(hipStreamSynchronize(s), "power sync");
+    for (int q = 0; q < ns; ++q) lam[q] = std::sqrt(std::max(nrm[q * 64], 0.0));
+    std::swap(x, y);
+  }
+  return lam;
+}
+
+// scale dinv segments by 1/lambda
+static void scale_dinv(PrecData* P, double* dinv, const std::vector<VSeg>& dsegs, const std::vector<double>& lam,
+                       hipStream_t s) {
+  const int ns = (int)dsegs.size();
+  std::vector<double> fac(ns * 64, 0.0);
+  for (int q = 0; q < ns; ++q) fac[q * 64] = 1.0 / lam[q];
+  VSeg* d = (VSeg*)P->scal;
+  upload(dsegs, d, s);
+  upload(fac, P->dot2, s);
+  long long mx = 0;
+  for (auto& v : dsegs) mx = std::max(mx, v.len);
+  seg_scale<double, double>(dinv, dinv, P->dot2, 0, 0, d, ns, mx, s);
+}
+
+static void cast_to_f32(const double* a, float* b, long long n, hipStream_t s) { vcast(a, b, n, s); }
+
+// pressure coefficients, diagonals, spectral normalisation and coarse inverses (depend on K)
+static void setup_pressure(biot_problem_s* h, hipStream_t s) {
+  PrecData* P = h->prec;
+  auto& B = P->b64;
+  const int nl = h->nl, cnt = h->count, d = h->dim;
+  launch_dq(h->d_inst, cnt, P->maxN, h->d_kinv64, B.dqinv, s);
+  launch_pdg_diag(d, h->d_inst, P->d_pdg, cnt, nl, P->pdg_max, B.dqinv, B.pdg_dinv, s);
+  launch_pcoef_first(h->d_inst, P->d_pdg, P->d_pc[0], cnt, P->pc_max[0], B.dqinv, B.pc_coef[0], s);
+  for (int l = 0; l + 1 < P->npl; ++l)
+    launch_pcoef_coarsen(P->d_pc[l], P->d_pc[l + 1], cnt, P->pc_max[l + 1], B.pc_coef[l], B.pc_coef[l + 1], s);
+  for (int l = 0; l < P->npl; ++l) launch_pcell_diag(P->d_pc[l], cnt, nl, P->pc_max[l], B.pc_coef[l], B.pc_dinv[l], s);
+  // power iterations: DG level per (instance, level j)
+  {
+    std::vector<VSeg> segs, dsegs;
+    for (int k = 0; k < cnt; ++k)
+      for (int j = 0; j < nl; ++j) {
+        const PDgSeg& g = P->pdg[k];
+        const long long np = (long long)h->inst[k].sp[0] * h->inst[k].sp[1] * h->inst[k].sp[2];
+        segs.push_back({g.voff + j * g.vjstride, np});
+        dsegs.push_back({g.doff + j * g.djstride, np});
+      }
+    auto apply = [&](double* x, double* y) {
+      launch_pdg<double>(d, h->d_inst, P->d_pdg, cnt, nl, P->pdg_max, kApplyDinv, ChebCoef{0, 0, 0, 1}, B.dqinv,
+                         B.pdg_dinv, nullptr, nullptr, nullptr, x, y, s);
+    };
+    auto lam = power_max(P, apply, B.T1, B.T2, segs, h->slab_len, s);
+    scale_dinv(P, B.pdg_dinv, dsegs, lam, s);
+  }
+  for (int l = 0; l < P->npl; ++l) {
+    std::vector<VSeg> segs;
+    for (int k = 0; k < cnt; ++k)
+      for (int j = 0; j < nl; ++j) {
+        const PCellSeg& c = P->pc[l][k];
+        segs.push_back({c.voff + j * c.vjstride, c.ncells});
+      }
+    auto apply = [&](double* x, double* y) {
+      launch_pcell<double>(P->d_pc[l], cnt, nl, P->pc_max[l], kApplyDinv, ChebCoef{0, 0, 0, 1}, B.pc_coef[l],
+                           B.pc_dinv[l], nullptr, nullptr, nullptr, x, y, s);
+    };
+    auto lam = power_max(P, apply, B.pc_x[l], B.pc_r[l], segs, nl * P->pc_total[l], s);
+    std::vector<VSeg> dsegs;
+    for (int k = 0; k < cnt; ++k)
+      for (int j = 0; j < nl; ++j) dsegs.push_back({P->pc[l][k].doff + j * P->pc[l][k].djstride, P->pc[l][k].ncells});
+    scale_dinv(P, B.pc_dinv[l], dsegs, lam, s);
+  }
+  // coarse dense inverses per (instance, level j) from the coarsest coefficients
+  {
+    const int l = P->npl - 1;
+    std::vector<double> coef(5 * P->pc_total[l]);
+    hip_check(hipMemcpyAsync(coef.data(), B.pc_coef[l], 8 * coef.size(), hipMemcpyDeviceToHost, s), "coef read");
+    hip_check(hipStreamSynchronize(s), "coef sync");
+    std::vector<double> all(P->pAinv_len);
+    for (int k = 0; k < cnt; ++k) {
+      const PCellSeg& c = P->pc[l][k];
+      const long long nc = c.ncells;
+      const double* C = coef.data() + c.coff;
+      for (int j = 0; j < nl; ++j) {
+        std::vector<double> A(nc * nc, 0.0);
+        const long long str[3] = {1, (long long)c.n[0], (long long)c.n[0] * c.n[1]};
+        for (long long q = 0; q < nc; ++q) {
+          const int ce[3] = {(int)(q % c.n[0]), (int)((q / c.n[0]) % c.n[1]), (int)(q / ((long long)c.n[0] * c.n[1]))};
+          double dg = c.cm[j] * C[4 * nc + q] + C[3 * nc + q];
+          for (int e = 0; e < d; ++e) {
+            if (ce[e] > 0) { const double t = C[e * nc + q]; dg += t; A[q * nc + q - str[e]] -= t; }
+            if (ce[e] + 1 < c.n[e]) { const double t = C[e * nc + q + str[e]]; dg += t; A[q * nc + q + str[e]] -= t; }
+          }
+          A[q * nc + q] += dg;
+        }
+        invert_dense(A, (int)nc);
+        std::copy(A.begin(), A.end(), all.begin() + P->pd[k].moff + j * P->pd[k].mjstride);
+      }
+    }
+    upload(all, P->pAinv, s);
+  }
+  // FP32 copies
+  auto& F = P->b32;
+  cast_to_f32(B.dqinv, F.dqinv, h->state_len, s);
+  cast_to_f32(B.pdg_dinv, F.pdg_dinv, P->pdg_total, s);
+  for (int l = 0; l < P->npl; ++l) {
+    cast_to_f32(B.pc_coef[l], F.pc_coef[l], 5 * P->pc_total[l], s);
+    cast_to_f32(B.pc_dinv[l], F.pc_dinv[l], nl * P->pc_total[l], s);
+  }
+}
+
+static void setup_elasticity(biot_problem_s* h, hipStream_t s) {
+  PrecData* P = h->prec;
+  auto& B = P->b64;
+  const int cnt = h->count, d = h->dim;
+  // diagonals (host), all levels into one array
+  long long dtot = 0;
+  for (int l = 0; l < P->nul; ++l) dtot += P->u_total[l];
+  std::vector<double> diag(dtot);
+  for (int l = 0; l < P->nul; ++l)
+    for (int k = 0; k < cnt; ++k) {
+      auto D = elast_diag(P->ug[l][k]);
+      std::copy(D.begin(), D.end(), diag.begin() + P->ug[l][k].doff);
+    }
+  upload(diag, B.u_dinv[0], s);
+  // power iterations per level (compact layout, one time level)
+  for (int l = 0; l < P->nul - 1; ++l) {
+    std::vector<VSeg> segs;
+    const UGridSeg* dseg;
+    const LSeg* dls;
+    double *x, *y;
+    if (l == 0) {
+      for (auto& g : P->ug0c) segs.push_back({g.voff, g.nu});
+      dseg = P->d_ug0c; dls = P->d_ul0c; x = B.T1; y = B.T2;
+    } else {
+      for (auto& g : P->ug[l]) segs.push_back({g.voff, g.nu});
+      dseg = P->d_ug[l]; dls = P->d_ul[l]; x = B.u_x[l]; y = B.u_y[l];
+    }
+    const int4* work = P->d_uwork[l];
+    const int nwork = (int)P->uwork[l].size();
+    const long long mx = P->u_max[l];
+    auto apply = [&](double* xx, double* yy) {
+      launch_uapply<double>(d, dseg, work, nwork, 1, 0, xx, nullptr, yy, s);
+      launch_mul_dinv<double>(dls, cnt, 1, mx, B.u_dinv[0], yy, yy, s);
+    };
+    auto lam = power_max(P, apply, x, y, segs, P->u_total[l], s);
+    std::vector<VSeg> dsegs;
+    for (auto& g : P->ug[l]) dsegs.push_back({g.doff, g.nu});
+    scale_dinv(P, B.u_dinv[0], dsegs, lam, s);
+  }
+  // coarse dense inverses
+  std::vector<double> all(P->uAinv_len);
+  for (int k = 0; k < cnt; ++k) {
+    auto A = coarse_elast_inverse(P->ug[P->nul - 1][k]);
+    std::copy(A.begin(), A.end(), all.begin() + P->ud[k].moff);
+  }
+  upload(all, P->uAinv, s);
+  long long dt = 0;
+  for (int l = 0; l < P->nul; ++l) dt += P->u_total[l];
+  cast_to_f32(B.u_dinv[0], P->b32.u_dinv[0], dt, s);
+}
+
+void setup_solver(biot_problem_s* h, hipStream_t s) {
+  PrecData* P = h->prec;
+  // descriptors
+  upload(P->pdg, P->d_pdg, s);
+  for (int l = 0; l < P->npl; ++l) upload(P->pc[l], P->d_pc[l], s);
+  for (int l = 0; l < P->nul; ++l) {
+    upload(P->ug[l], P->d_ug[l], s);
+    upload(P->uwork[l], P->d_uwork[l], s);
+    upload(P->ul[l], P->d_ul[l], s);
+  }
+  upload(P->ug0c, P->d_ug0c, s);
+  upload(P->ul0c, P->d_ul0c, s);
+  for (int l = 0; l + 1 < P->nul; ++l) {
+    for (int pass = 0; pass < P->dim; ++pass) upload(P->rp[l][pass], P->d_rp[l][pass], s);
+    upload(P->up[l], P->d_up[l], s);
+  }
+  upload(P->utab_h, P->d_utab, s);
+  upload(P->ud, P->d_ud, s);
+  upload(P->pd, P->d_pd, s);
+  upload(P->gseg, P->d_gseg, s);
+  for (int j = 0; j < 16; ++j) { P->Q.m[j] = h->tc.Q[j]; P->Qi.m[j] = h->tc.Qi[j]; }
+  P->b64.kinv = h->d_kinv64;
+  P->b32.kinv = h->d_kinv32;
+  setup_elasticity(h, s);
+  setup_pressure(h, s);
+  hip_check(hipStreamSynchronize(s), "solver setup");
+}
+
+void refresh_solver(biot_problem_s* h, hipStream_t s) {
+  setup_pressure(h, s);
+  hip_check(hipStreamSynchronize(s), "solver refresh");
+}
+
+void destroy_solver(biot_problem_s* h) {
+  delete h->prec;
+  h->prec = nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// the preconditioner  z = P^-1 r  (vectors of type T)
+// ---------------------------------------------------------------------------
+template <typename T>
+static void p_vcycle(biot_problem_s* h, int l, hipStream_t s) {
+  PrecData* P = h->prec;
+  auto& B = bufs<T>(P);
+  const int nl = h->nl, cnt = h->count;
+  static const ChebSeq cs = cheb_seq(kPLo, kPHi, kPDeg);
+  if (l == P->npl - 1) {
+    dense_solve<T>(P->d_pd, cnt, nl, P->p_maxn, P->pAinv, B.pc_b[l], B.pc_x[l], s);
+    return;
+  }
+  const PCellSeg* sg = P->d_pc[l];
+  const long long mx = P->pc_max[l];
+  T *x = B.pc_x[l], *b = B.pc_b[l], *r = B.pc_r[l], *d0 = B.pc_d0[l], *d1 = B.pc_d1[l];
+  launch_pcell<T>(sg, cnt, nl, mx, kResInitZero, ChebCoef{cs.s0, 0, 0, 1}, B.pc_coef[l], B.pc_dinv[l], b, x, r,
+                  nullptr, d0, s);
+  for (int k = 0; k < kPDeg; ++k) {
+    launch_pcell<T>(sg, cnt, nl, mx, kStep, ChebCoef{0, cs.steps[k].first, cs.steps[k].second, 1}, B.pc_coef[l],
+                    B.pc_dinv[l], b, x, r, (k & 1) ? d1 : d0, (k & 1) ? d0 : d1, s);
+  }
+  launch_p_restrict_cell<T>(sg, P->d_pc[l + 1], cnt, nl, P->pc_max[l + 1], r, B.pc_b[l + 1], s);
+  p_vcycle<T>(h, l + 1, s);
+  launch_p_prolong_cell<T>(sg, P->d_pc[l + 1], cnt, nl, mx, kOmegaP, B.pc_x[l + 1], x, s);
+  launch_pcell<T>(sg, cnt, nl, mx, kResInit, ChebCoef{cs.s0, 0, 0, 1}, B.pc_coef[l], B.pc_dinv[l], b, x, r, nullptr,
+                  d0, s);
+  for (int k = 0; k < kPDeg; ++k) {
+    launch_pcell<T>(sg, cnt, nl, mx, kStep, ChebCoef{0, cs.steps[k].first, cs.steps[k].second, 1}, B.pc_coef[l],
+                    B.pc_dinv[l], b, x, r, (k & 1) ? d1 : d0, (k & 1) ? d0 : d1, s);
+  }
+}
+
+// S_j y = bsign * b on the DG level (x, b: slab layout p-blocks)
+template <typename T>
+static void p_solve(biot_problem_s* h, const T* b, T* x, hipStream_t s) {
+  PrecData* P = h->prec;
+  auto& B = bufs<T>(P);
+  const int nl = h->nl, cnt = h->count, d = h->dim;
+  static const ChebSeq cs = cheb_seq(kPLo, kPHi, kPDeg);
+  T *r = B.T1, *d0 = B.T2, *d1 = B.T3;
+  launch_pdg<T>(d, h->d_inst, P->d_pdg, cnt, nl, P->pdg_max, kResInitZero, ChebCoef{cs.s0, 0, 0, -1}, B.dqinv,
+                B.pdg_dinv, b, x, r, nullptr, d0, s);
+  for (int k = 0; k < kPDeg; ++k)
+    launch_pdg<T>(d, h->d_inst, P->d_pdg, cnt, nl, P->pdg_max, kStep,
+                  ChebCoef{0, cs.steps[k].first, cs.steps[k].second, -1}, B.dqinv, B.pdg_dinv, b, x, r,
+                  (k & 1) ? d1 : d0, (k & 1) ? d0 : d1, s);
+  launch_p_restrict_dg<T>(h->d_inst, P->d_pdg, P->d_pc[0], cnt, nl, P->pc_max[0], r, B.pc_b[0], s);
+  p_vcycle<T>(h, 0, s);
+  launch_p_prolong_dg<T>(h->d_inst, P->d_pdg, P->d_pc[0], cnt, nl, P->pdg_max, kOmegaP, B.pc_x[0], x, s);
+  launch_pdg<T>(d, h->d_inst, P->d_pdg, cnt, nl, P->pdg_max, kResInit, ChebCoef{cs.s0, 0, 0, -1}, B.dqinv,
+                B.pdg_dinv, b, x, r, nullptr, d0, s);
+  for (int k = 0; k < kPDeg; ++k)
+    launch_pdg<T>(d, h->d_inst, P->d_pdg, cnt, nl, P->pdg_max, kStep,
+                  ChebCoef{0, cs.steps[k].first, cs.steps[k].second, -1}, B.dqinv, B.pdg_dinv, b, x, r,
+                  (k & 1) ? d1 : d0, (k & 1) ? d0 : d1, s);
+}
+
+// one V-cycle for tau A_l x = b at u level l (level 0: slab layout buffers given)
+template <typename T>
+static void u_vcycle(biot_problem_s* h, int l, T* x, const T* b, T* r, T* d0, T* y, hipStream_t s) {
+  PrecData* P = h->prec;
+  auto& B = bufs<T>(P);
+  const int nl = h->nl, cnt = h->count, d = h->dim;
+  static const ChebSeq cs = cheb_seq(kULo, kUHi, kUDeg);
+  if (l == P->nul - 1) {
+    dense_solve<T>(P->d_ud, cnt, nl, P->u_maxn, P->uAinv, b, x, s);
+    return;
+  }
+  const LSeg* ls = P->d_ul[l];
+  const long long mx = P->u_max[l];
+  const UGridSeg* gs = P->d_ug[l];
+  const int4* work = P->d_uwork[l];
+  const int nwork = (int)P->uwork[l].size();
+  const T* dinv = B.u_dinv[0];
+  // pre-smoothing from x = 0
+  cheb_update<T>(ls, cnt, nl, mx, 2, 0.0, cs.s0, x, r, d0, nullptr, dinv, b, s);
+  for (int k = 0; k < kUDeg; ++k) {
+    launch_uapply<T>(d, gs, work, nwork, nl, 0, d0, nullptr, y, s);
+    cheb_update<T>(ls, cnt, nl, mx, 1, cs.steps[k].first, cs.steps[k].second, x, r, d0, y, dinv, nullptr, s);
+  }
+  // restriction of r
+  const T* in = r;
+  for (int pass = 0; pass < d; ++pass) {
+    T* out = (pass == d - 1) ? B.u_b[l + 1] : (pass == 0 ? B.u_t1[l] : B.u_t2[l]);
+    launch_rpass<T>(P->d_rp[l][pass], cnt, nl, P->rp_max[l][pass], P->d_utab, in, out, s);
+    in = out;
+  }
+  u_vcycle<T>(h, l + 1, B.u_x[l + 1], B.u_b[l + 1], B.u_r[l + 1], B.u_d0[l + 1], B.u_y[l + 1], s);
+  launch_uprolong<T>(P->d_up[l], cnt, nl, mx, P->d_utab, B.u_x[l + 1], x, s);
+  // post-smoothing
+  launch_uapply<T>(d, gs, work, nwork, nl, 1, x, b, r, s);
+  cheb_update<T>(ls, cnt, nl, mx, 0, 0.0, cs.s0, x, r, d0, nullptr, dinv, nullptr, s);
+  for (int k = 0; k < kUDeg; ++k) {
+    launch_uapply<T>(d, gs, work, nwork, nl, 0, d0, nullptr, y, s);
+    cheb_update<T>(ls, cnt, nl, mx, 1, cs.steps[k].first, cs.steps[k].second, x, r, d0, y, dinv, nullptr, s);
+  }
+}
+
+template <typename T>
+static void apply_prec(biot_problem_s* h, const T* rin, T* z, int qdeg, hipStream_t s) {
+  PrecData* P = h->prec;
+  auto& B = bufs<T>(P);
+  const int nl = h->nl, cnt = h->count, d = h->dim;
+  // into the real block eigenbasis of T
+  time_transform<T>(h->d_inst, cnt, P->maxN, nl, P->Qi, rin, B.Wr, s);
+  // 1) pressure: S_j p = -r_p
+  p_solve<T>(h, B.Wr, B.Wz, s);
+  // 2) coupling right-hand sides
+  launch_coupling<T>(d, h->d_inst, cnt, nl, P->maxN, B.Wr, B.Wz, B.Wf, B.Wf, s);
+  // 3) flux: tau Mq q = f_q  (Chebyshev-Jacobi on the Gershgorin interval)
+  {
+    const ChebSeq cs = cheb_seq(kQLo, kQHi, qdeg);
+    launch_mq<T>(d, h->d_inst, cnt, nl, P->maxN, kResInitZero, ChebCoef{cs.s0, 0, 0, 1}, B.kinv, nullptr, B.Wf, B.Wz,
+                 B.T1, nullptr, B.T2, s);
+    for (int k = 0; k < qdeg; ++k)
+      launch_mq<T>(d, h->d_inst, cnt, nl, P->maxN, kStep, ChebCoef{0, cs.steps[k].first, cs.steps[k].second, 1},
+                   B.kinv, nullptr, B.Wf, B.Wz, B.T1, (k & 1) ? B.T3 : B.T2, (k & 1) ? B.T2 : B.T3, s);
+  }
+  // 4) mechanics: tau A u = f_u  (one V-cycle)
+  u_vcycle<T>(h, 0, B.Wz, B.Wf, B.T1, B.T2, B.T4, s);
+  // back to the nodal time basis; essential rows pass through
+  launch_prec_finalize<T>(h->d_inst, cnt, P->maxN, nl, P->Q, B.Wz, rin, z, s);
+}
+
+// ---------------------------------------------------------------------------
+// GMRES (right preconditioned, restarted, CGS2), batched over instances
+// ---------------------------------------------------------------------------
+struct SolveCtl {
+  double rtol;
+  int maxit, restart, qdeg;
+};
+
+// y = b - A x into r (type T)
+template <typename T>
+static void residual(biot_problem_s* h, const T* b, const T* x, T* r, int transpose, hipStream_t s) {
+  launch_apply(h, x, r, transpose, std::is_same<T, float>::value ? 1 : 0, s);
+  vaxpby<T>(1.0, b, -1.0, r, h->slab_len, s);
+}
+
+template <typename T>
+static void seg_norms(PrecData* P, const T* v, int cnt, hipStream_t s, std::vector<double>& out) {
+  seg_mdot<T, T>(v, 0, 1, v, P->d_gseg, cnt, kNChunk, P->partial, P->dot3, s);
+  std::vector<double> tmp(cnt * 64);
+  hip_check(hipMemcpyAsync(tmp.data(), P->dot3, 8 * cnt * 64, hipMemcpyDeviceToHost, s), "norm read");
+  hip_check(hipStreamSynchronize(s), "norm sync");
+  out.resize(cnt);
+  for (int k = 0; k < cnt; ++k) out[k] = std::sqrt(std::max(tmp[k * 64], 0.0));
+}
+
+template <typename T>
+static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const SolveCtl& ctl, std::vector<int>& its,
+                  std::vector<int>& rst, std::vector<double>& relres, std::vector<int>& status, hipStream_t s) {
+  PrecData* P = h->prec;
+  auto& B = bufs<T>(P);
+  const int cnt = h->count;
+  const long long S = h->slab_len;
+  const int m = std::min(std::max(ctl.restart, 1), kMaxRestart);
+  its.assign(cnt, 0); rst.assign(cnt, 0); relres.assign(cnt, 0.0); status.assign(cnt, BIOT_OK);
+  std::vector<double> bn, beta;
+  seg_norms<T>(P, b, cnt, s, bn);
+  for (int k = 0; k < cnt; ++k)
+    if (!std::isfinite(bn[k])) throw BiotError{BIOT_ERR_NONFINITE, "right-hand side is not finite"};
+  residual<T>(h, b, x, B.r, transpose, s);
+  seg_norms<T>(P, B.r, cnt, s, beta);
+  std::vector<char> done(cnt, 0);
+  for (int k = 0; k < cnt; ++k) {
+    relres[k] = bn[k] > 0 ? beta[k] / bn[k] : 0.0;
+    if (bn[k] == 0.0 || beta[k] <= ctl.rtol * bn[k]) done[k] = 1;
+  }
+  std::vector<double> H((size_t)cnt * (kMaxRestart + 1) * kMaxRestart), cs(cnt * kMaxRestart), sn(cnt * kMaxRestart),
+      g(cnt * (kMaxRestart + 1));
+  std::vector<double> h1(cnt * 64), h2(cnt * 64), hn(cnt * 64), coef(cnt * 64);
+  int total = 0;
+  while (true) {
+    bool all = true;
+    for (int k = 0; k < cnt; ++k) all = all && done[k];
+    if (all || total >= ctl.maxit) break;
+    // v0 = r / ||r||  (dot3 still holds ||r||^2 per instance from seg_norms)
+    seg_scale<T, T>(B.r, B.V, P->dot3, 0, 2, P->d_gseg, cnt, P->gmax, s);
+    std::vector<int> jk(cnt, 0);
+    std::vector<char> act(cnt);
+    for (int k = 0; k < cnt; ++k) {
+      act[k] = !done[k];
+      g[k * (kMaxRestart + 1)] = beta[k];
+      ++rst[k];
+    }
+    int jj = 0;
+    for (; jj < m && total < ctl.maxit; ++jj) {
+      T* vj = B.V + (long long)jj * S;
+      T* vn = B.V + (long long)(jj + 1) * S;
+      apply_prec<T>(h, vj, B.t, ctl.qdeg, s);
+      launch_apply(h, B.t, vn, transpose, std::is_same<T, float>::value ? 1 : 0, s);
+      seg_mdot<T, T>(B.V, S, jj + 1, vn, P->d_gseg, cnt, kNChunk, P->partial, P->dot1, s);
+      seg_maxpy<T, T>(B.V, S, jj + 1, P->dot1, -1.0, vn, P->d_gseg, cnt, P->gmax, s);
+      seg_mdot<T, T>(B.V, S, jj + 1, vn, P->d_gseg, cnt, kNChunk, P->partial, P->dot2, s);
+      seg_maxpy<T, T>(B.V, S, jj + 1, P->dot2, -1.0, vn, P->d_gseg, cnt, P->gmax, s);
+      seg_mdot<T, T>(vn, 0, 1, vn, P->d_gseg, cnt, kNChunk, P->partial, P->dot3, s);
+      hip_check(hipMemcpyAsync(h1.data(), P->dot1, 8 * cnt * 64, hipMemcpyDeviceToHost, s), "h read");
+      hip_check(hipMemcpyAsync(h2.data(), P->dot2, 8 * cnt * 64, hipMemcpyDeviceToHost, s), "h read");
+      hip_check(hipMemcpyAsync(hn.data(), P->dot3, 8 * cnt * 64, hipMemcpyDeviceToHost, s), "h read");
+      hip_check(hipStreamSynchronize(s), "gmres sync");
+      // v_{j+1} = w / ||w|| on the device (0 for a zero norm)
+      seg_scale<T, T>(vn, vn, P->dot3, 0, 2, P->d_gseg, cnt, P->gmax, s);
+      for (int k = 0; k < cnt; ++k) {
+        const double nrm = std::sqrt(std::max(hn[k * 64], 0.0));
+        if (!std::isfinite(nrm)) throw BiotError{BIOT_ERR_NONFINITE, "non-finite Krylov vector"};
+        if (!act[k]) continue;
+        double* Hk = &H[(size_t)k * (kMaxRestart + 1) * kMaxRestart];
+        double col[kMaxRestart + 1];
+        for (int i = 0; i <= jj; ++i) col[i] = h1[k * 64 + i] + h2[k * 64 + i];
+        col[jj + 1] = nrm;
+        // previous rotations
+        for (int i = 0; i < jj; ++i) {
+          const double c = cs[k * kMaxRestart + i], sv = sn[k * kMaxRestart + i];
+          const double t0 = c * col[i] + sv * col[i + 1];
+          col[i + 1] = -sv * col[i] + c * col[i + 1];
+          col[i] = t0;
+        }
+        const double den = std::hypot(col[jj], col[jj + 1]);
+        const double c = den > 0 ? col[jj] / den : 1.0, sv = den > 0 ? col[jj + 1] / den : 0.0;
+        cs[k * kMaxRestart + jj] = c;
+        sn[k * kMaxRestart + jj] = sv;
+        col[jj] = den;
+        col[jj + 1] = 0.0;
+        for (int i = 0; i <= jj; ++i) Hk[i * kMaxRestart + jj] = col[i];
+        double* gk = &g[k * (kMaxRestart + 1)];
+        gk[jj + 1] = -sv * gk[jj];
+        gk[jj] = c * gk[jj];
+        jk[k] = jj + 1;
+        ++its[k];
+        const double est = std::fabs(gk[jj + 1]);
+        if (est <= ctl.rtol * bn[k] || nrm == 0.0) act[k] = 0;
+      }
+      ++total;
+      bool any = false;
+      for (int k = 0; k < cnt; ++k) any = any || act[k];
+      if (!any) { ++jj; break; }
+    }
+    // x += P^-1 (V y)
+    std::fill(coef.begin(), coef.end(), 0.0);
+    int kmax = 0;
+    for (int k = 0; k < cnt; ++k) {
+      if (jk[k] == 0) continue;
+      const double* Hk = &H[(size_t)k * (kMaxRestart + 1) * kMaxRestart];
+      const double* gk = &g[k * (kMaxRestart + 1)];
+      const int n = jk[k];
+      std::vector<double> y(n);
+      for (int i = n - 1; i >= 0; --i) {
+        double v = gk[i];
+        for (int q = i + 1; q < n; ++q) v -= Hk[i * kMaxRestart + q] * y[q];
+        y[i] = v / Hk[i * kMaxRestart + i];
+      }
+      for (int i = 0; i < n; ++i) coef[k * 64 + i] = y[i];
+      kmax = std::max(kmax, n);
+    }
+    if (kmax > 0) {
+      upload(coef, P->coef, s);
+      hip_check(hipMemsetAsync(B.w, 0, sizeof(T) * S, s), "zero");
+      seg_maxpy<T, T>(B.V, S, kmax, P->coef, 1.0, B.w, P->d_gseg, cnt, P->gmax, s);
+      apply_prec<T>(h, B.w, B.t, ctl.qdeg, s);
+      vaxpby<T>(1.0, B.t, 1.0, x, S, s);
+    }
+    residual<T>(h, b, x, B.r, transpose, s);
+    seg_norms<T>(P, B.r, cnt, s, beta);
+    for (int k = 0; k < cnt; ++k) {
+      if (!std::isfinite(beta[k])) throw BiotError{BIOT_ERR_NONFINITE, "non-finite residual"};
+      relres[k] = bn[k] > 0 ? beta[k] / bn[k] : 0.0;
+      if (bn[k] == 0.0 || beta[k] <= ctl.rtol * bn[k]) done[k] = 1;
+    }
+  }
+  for (int k = 0; k < cnt; ++k) status[k] = done[k] ? BIOT_OK : BIOT_ERR_NOCONV;
+}
+
+
+
+// FP64 or mixed solve of A x = b (device double vectors)
+static void solve_impl(biot_problem_s* h, const double* b, double* x, int transpose, const biot_solve_opts* o,
+                       biot_solve_info* info, hipStream_t s) {
+  biot_solve_opts opts;
+  opts.rtol = 1e-13; opts.maxit = 1000; opts.restart = 40; opts.precision = BIOT_FP64;
+  opts.inner_rtol = 1e-5; opts.max_refine = 20; opts.cheb_degree = 8;
+  if (o) opts = *o;
+  if (!(opts.rtol > 0) || !std::isfinite(opts.rtol)) throw BiotError{BIOT_ERR_ARG, "rtol must be > 0"};
+  if (opts.maxit < 1) throw BiotError{BIOT_ERR_ARG, "maxit must be >= 1"};
+  if (opts.restart < 1 || opts.restart > kMaxRestart) throw BiotError{BIOT_ERR_ARG, "restart must be in 1..64"};
+  if (opts.precision != BIOT_FP64 && opts.precision != BIOT_MIXED) throw BiotError{BIOT_ERR_ARG, "unknown precision"};
+  if (opts.cheb_degree < 1 || opts.cheb_degree > 64) throw BiotError{BIOT_ERR_ARG, "cheb_degree must be in 1..64"};
+  const int cnt = h->count;
+  std::vector<int> its, rst, st;
+  std::vector<double> rr;
+  if (opts.precision == BIOT_FP64) {
+    SolveCtl ctl{opts.rtol, opts.maxit, opts.restart, opts.cheb_degree};
+    gmres<double>(h, b, x, transpose, ctl, its, rst, rr, st, s);
+    for (int k = 0; k < cnt; ++k) {
+      info[k].iterations = its[k]; info[k].restarts = rst[k]; info[k].ir_sweeps = 0;
+      info[k].status = st[k]; info[k].rel_residual = rr[k];
+    }
+  } else {
+    if (!(opts.inner_rtol > 0) || opts.max_refine < 1) throw BiotError{BIOT_ERR_ARG, "bad mixed-precision controls"};
+    PrecData* P = h->prec;
+    auto& B64 = P->b64;
+    auto& B32 = P->b32;
+    std::vector<double> bn, rn;
+    seg_norms<double>(P, b, cnt, s, bn);
+    std::vector<int> tot(cnt, 0), totr(cnt, 0), sweeps(cnt, 0);
+    std::vector<char> done(cnt, 0);
+    for (int sw = 0; sw <= opts.max_refine; ++sw) {
+      residual<double>(h, b, x, B64.r, transpose, s);
+      seg_norms<double>(P, B64.r, cnt, s, rn);
+      bool all = true;
+      for (int k = 0; k < cnt; ++k) {
+        if (!std::isfinite(rn[k])) throw BiotError{BIOT_ERR_NONFINITE, "non-finite residual"};
+        if (bn[k] == 0.0 || rn[k] <= opts.rtol * bn[k]) done[k] = 1;
+        all = all && done[k];
+      }
+      if (all || sw == opts.max_refine) break;
+      vcast(B64.r, B32.bin, h->slab_len, s);
+      hip_check(hipMemsetAsync(B32.xin, 0, sizeof(float) * h->slab_len, s), "zero");
+      SolveCtl ctl{opts.inner_rtol, opts.maxit, opts.restart, opts.cheb_degree};
+      float* d32 = B32.xin;
+      gmres<float>(h, B32.bin, d32, transpose, ctl, its, rst, rr, st, s);
+      vacc(d32, x, h->slab_len, s);
+      for (int k = 0; k < cnt; ++k) { tot[k] += its[k]; totr[k] += rst[k]; if (!done[k]) ++sweeps[k]; }
+    }
+    for (int k = 0; k < cnt; ++k) {
+      info[k].iterations = tot[k]; info[k].restarts = totr[k]; info[k].ir_sweeps = sweeps[k];
+      info[k].status = done[k] ? BIOT_OK : BIOT_ERR_NOCONV;
+      info[k].rel_residual = bn[k] > 0 ? rn[k] / bn[k] : 0.0;
+    }
+  }
+}
 
 static long long max_cells(const biot_problem_s* h) {
   long long m = 0;
@@ -23,6 +1189,7 @@ void launch_slab_rhs(const biot_problem_s* h, const double* state, double t_star
   launch_rhs(h->d_inst, h->count, max_cells(h), h->tm, h->nl, t_start, state, rhs, s);
   hip_check(hipGetLastError(), "rhs launch");
 }
+
 }  // namespace bt
 
 using namespace bt;
@@ -44,6 +1211,13 @@ static void need(bool c, const char* m) {
   if (!c) throw BiotError{BIOT_ERR_ARG, m};
 }
 
+static biot_status worst(const biot_solve_info* info, int n) {
+  int st = BIOT_OK;
+  for (int k = 0; k < n; ++k)
+    if (info[k].status != BIOT_OK) st = info[k].status;
+  return (biot_status)st;
+}
+
 extern "C" {
 
 biot_status slab_rhs(biot_problem h, const double* state, double t_start, double* rhs, void* stream) {
@@ -55,23 +1229,156 @@ biot_status slab_rhs(biot_problem h, const double* state, double t_start, double
   BIOT_CATCH
 }
 
-biot_status solve_slab(biot_problem, const double*, double*, const biot_solve_opts*, biot_solve_info*, void*) {
-  set_error("solve_slab: not built yet");
-  return BIOT_ERR_ARG;
+static biot_status solve_common(biot_problem h, const double* rhs, double* x, int transpose,
+                                const biot_solve_opts* opts, biot_solve_info* info, void* stream) {
+  try {
+    need(h, "handle is null");
+    need(rhs && x, "rhs and x must be device pointers");
+    need(info, "info is null");
+    need((const void*)rhs != (const void*)x, "rhs and x must not alias");
+    solve_impl(h, rhs, x, transpose, opts, info, (hipStream_t)stream);
+    biot_status st = worst(info, h->count);
+    if (st != BIOT_OK) set_error("GMRES did not reach the tolerance within maxit");
+    return st;
+  } catch (const BiotError& e) {
+    set_error(e.msg);
+    return e.st;
+  } catch (const std::exception& e) {
+    set_error(std::string("internal error: ") + e.what());
+    return BIOT_ERR_ARG;
+  }
 }
-biot_status solve_slab_transposed(biot_problem, const double*, double*, const biot_solve_opts*, biot_solve_info*,
-                                  void*) {
-  set_error("solve_slab_transposed: not built yet");
-  return BIOT_ERR_ARG;
+
+biot_status solve_slab(biot_problem h, const double* rhs, double* x, const biot_solve_opts* opts,
+                       biot_solve_info* info, void* stream) {
+  return solve_common(h, rhs, x, 0, opts, info, stream);
 }
-biot_status step(biot_problem, int32_t, double, double*, double*, double*, const biot_solve_opts*, biot_solve_info*,
-                 void*) {
-  set_error("step: not built yet");
-  return BIOT_ERR_ARG;
+
+biot_status solve_slab_transposed(biot_problem h, const double* rhs, double* x, const biot_solve_opts* opts,
+                                  biot_solve_info* info, void* stream) {
+  return solve_common(h, rhs, x, 1, opts, info, stream);
 }
-biot_status adjoint_sweep(biot_problem, int32_t, double, const double*, const double*, int32_t, const double*,
-                          const biot_solve_opts*, double*, double*, void*) {
-  set_error("adjoint_sweep: not built yet");
-  return BIOT_ERR_ARG;
+
+biot_status step(biot_problem h, int32_t nslabs, double t_start, double* state, double* slabs_out,
+                 double* checkpoints, const biot_solve_opts* opts, biot_solve_info* infos, void* stream) {
+  try {
+    need(h, "handle is null");
+    need(nslabs >= 0, "nslabs must be >= 0");
+    need(state, "state must be a device pointer");
+    need(infos || nslabs == 0, "infos is null");
+    need(std::isfinite(t_start), "t_start must be finite");
+    hipStream_t s = (hipStream_t)stream;
+    PrecData* P = h->prec;
+    double* rhs = P->arhs;
+    double* x = P->xfwd;
+    biot_status worst_st = BIOT_OK;
+    for (int n = 0; n < nslabs; ++n) {
+      if (checkpoints)
+        hip_check(hipMemcpyAsync(checkpoints + (long long)n * h->state_len, state, 8 * h->state_len,
+                                 hipMemcpyDeviceToDevice, s), "checkpoint");
+      const double tn = t_start + n * h->descs[0].tau;
+      launch_slab_rhs(h, state, tn, rhs, s);
+      launch_bcast(h->d_inst, h->count, P->maxN, h->nl, state, x, s);
+      solve_impl(h, rhs, x, 0, opts, infos + (long long)n * h->count, s);
+      biot_status st = worst(infos + (long long)n * h->count, h->count);
+      if (st != BIOT_OK) worst_st = st;
+      if (slabs_out)
+        hip_check(hipMemcpyAsync(slabs_out + (long long)n * h->slab_len, x, 8 * h->slab_len, hipMemcpyDeviceToDevice,
+                                 s), "slab out");
+      launch_extract(h->d_inst, h->count, P->maxN, h->nl - 1, x, state, s);
+    }
+    hip_check(hipStreamSynchronize(s), "step sync");
+    if (worst_st != BIOT_OK) set_error("a slab solve did not reach the tolerance");
+    return worst_st;
+  } catch (const BiotError& e) {
+    set_error(e.msg);
+    return e.st;
+  } catch (const std::exception& e) {
+    set_error(std::string("internal error: ") + e.what());
+    return BIOT_ERR_ARG;
+  }
 }
+
+biot_status adjoint_sweep(biot_problem h, int32_t nslabs, double t_start, const double* checkpoints,
+                          const double* sensors_xyz, int32_t nsens, const double* p_obs, const biot_solve_opts* opts,
+                          double* J, double* grad_log_k, void* stream) {
+  try {
+    need(h, "handle is null");
+    need(nslabs >= 1, "nslabs must be >= 1");
+    need(checkpoints && p_obs && grad_log_k, "checkpoints, p_obs and grad_log_k must be device pointers");
+    need(sensors_xyz && J, "sensors_xyz and J must be host pointers");
+    PrecData* P = h->prec;
+    need(nsens >= 1 && nsens <= P->max_sens, "nsens must be in 1..256");
+    hipStream_t s = (hipStream_t)stream;
+    const int cnt = h->count, d = h->dim, nl = h->nl;
+    // sensor weights (host): containing cell (floor, clipped), DG-Q1 Lagrange weights
+    std::vector<SensorW> sw((size_t)cnt * nsens);
+    for (int k = 0; k < cnt; ++k) {
+      const InstDev& I = h->inst[k];
+      for (int q = 0; q < nsens; ++q) {
+        SensorW w;
+        std::memset(&w, 0, sizeof(w));
+        int ce[3] = {0, 0, 0};
+        double sl[3] = {0, 0, 0};
+        for (int e = 0; e < d; ++e) {
+          const double xv = sensors_xyz[q * d + e];
+          need(std::isfinite(xv), "sensor coordinates must be finite");
+          int c = (int)std::floor(xv / I.h[e]);
+          c = std::min(std::max(c, 0), I.n[e] - 1);
+          ce[e] = c;
+          sl[e] = xv / I.h[e] - c;
+        }
+        for (int g = 0; g < (d == 3 ? 8 : 4); ++g) {
+          const int gg[3] = {g & 1, (g >> 1) & 1, (g >> 2) & 1};
+          double wt = 1.0;
+          for (int e = 0; e < d; ++e) wt *= psi(gg[e], sl[e]);
+          w.idx[g] = (2 * ce[0] + gg[0]) + (long long)I.sp[0] * ((2 * ce[1] + gg[1]) + (long long)I.sp[1] * (d == 3 ? 2 * ce[2] + gg[2] : 0));
+          w.w[g] = wt;
+        }
+        sw[(size_t)k * nsens + q] = w;
+      }
+    }
+    upload(sw, P->sw, s);
+    hip_check(hipMemsetAsync(grad_log_k, 0, 8 * h->ncells, s), "grad clear");
+    std::vector<double> Jk(cnt, 0.0), res((size_t)cnt * nsens);
+    std::vector<biot_solve_info> info(cnt);
+    // p_obs is instance-major [k][n][s]: gather slab n into a compact [k][s] block
+    for (int n = nslabs - 1; n >= 0; --n) {
+      const double* st = checkpoints + (long long)n * h->state_len;
+      const double tn = t_start + n * h->descs[0].tau;
+      // recompute the forward slab from its checkpoint
+      launch_slab_rhs(h, st, tn, P->arhs, s);
+      launch_bcast(h->d_inst, cnt, P->maxN, nl, st, P->xfwd, s);
+      solve_impl(h, P->arhs, P->xfwd, 0, opts, info.data(), s);
+      for (int k = 0; k < cnt; ++k)
+        if (info[k].status != BIOT_OK) throw BiotError{(biot_status)info[k].status, "forward recompute did not converge"};
+      for (int k = 0; k < cnt; ++k)
+        hip_check(hipMemcpyAsync(P->sobs + (long long)k * nsens, p_obs + ((long long)k * nslabs + n) * nsens,
+                                 8 * nsens, hipMemcpyDeviceToDevice, s), "obs gather");
+      launch_sensor(h->d_inst, cnt, nl - 1, nsens, P->sw, P->xfwd, P->sobs, P->sres, s);
+      hip_check(hipMemcpyAsync(res.data(), P->sres, 8 * res.size(), hipMemcpyDeviceToHost, s), "res read");
+      hip_check(hipStreamSynchronize(s), "adjoint sync");
+      for (int k = 0; k < cnt; ++k)
+        for (int q = 0; q < nsens; ++q) Jk[k] += 0.5 * res[(size_t)k * nsens + q] * res[(size_t)k * nsens + q];
+      launch_adjrhs(h->d_inst, cnt, P->maxN, h->tm, nl, n < nslabs - 1, P->lam_next, nsens, P->sw, P->sres, P->arhs,
+                    s);
+      hip_check(hipMemsetAsync(P->lam, 0, 8 * h->slab_len, s), "lam clear");
+      solve_impl(h, P->arhs, P->lam, 1, opts, info.data(), s);
+      for (int k = 0; k < cnt; ++k)
+        if (info[k].status != BIOT_OK) throw BiotError{(biot_status)info[k].status, "adjoint solve did not converge"};
+      launch_grad(h->d_inst, cnt, P->maxcells, nl, h->d_kinv64, P->lam, P->xfwd, grad_log_k, s);
+      std::swap(P->lam, P->lam_next);
+    }
+    hip_check(hipStreamSynchronize(s), "adjoint end");
+    for (int k = 0; k < cnt; ++k) J[k] = Jk[k];
+    return BIOT_OK;
+  } catch (const BiotError& e) {
+    set_error(e.msg);
+    return e.st;
+  } catch (const std::exception& e) {
+    set_error(std::string("internal error: ") + e.what());
+    return BIOT_ERR_ARG;
+  }
 }
+
+}  // extern "C"

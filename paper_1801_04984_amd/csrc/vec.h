@@ -1,0 +1,50 @@
+// Segmented vector kernels (vec.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "common.h"
+
+namespace bt {
+
+struct VSeg {          // a contiguous segment of a vector (one instance)
+  long long off, len;
+};
+struct LSeg {          // a multigrid-level field segment with r+1 time levels
+  long long off, jstride, len;
+  long long doff, djstride;  // matching diagonal-inverse segment
+};
+struct DSeg {          // dense coarse solve segment
+  long long off, jstride;
+  int n, pad;
+  long long moff, mjstride;
+};
+struct Mat4 { double m[16]; };
+
+template <typename T> void vfill(T* x, T v, long long n, hipStream_t s);
+void vcast(const double* x, float* y, long long n, hipStream_t s);
+void vcast(const float* x, double* y, long long n, hipStream_t s);
+template <typename T>
+void vaxpby(double a, const T* x, double b, T* y, long long n, hipStream_t s);
+void vacc(const float* x, double* y, long long n, hipStream_t s);
+template <typename TV, typename TW>
+void seg_mdot(const TV* V, long long ldv, int nk, const TW* w, const VSeg* segs, int nseg, int nchunk,
+              double* partial, double* out, hipStream_t s);
+template <typename TV, typename TW>
+void seg_maxpy(const TV* V, long long ldv, int nk, const double* c, double csign, TW* w, const VSeg* segs, int nseg,
+               long long maxlen, hipStream_t s);
+template <typename TX, typename TY>
+void seg_scale(const TX* x, TY* y, const double* sc, int idx, int inv, const VSeg* segs, int nseg, long long maxlen,
+               hipStream_t s);
+template <typename T>
+void time_transform(const InstDev* insts, int count, long long maxN, int nl, const Mat4& M, const T* x, T* y,
+                    hipStream_t s);
+template <typename T>
+void cheb_update(const LSeg* segs, int nseg, int nj, long long maxlen, int mode, double rho, double sig, T* x, T* r,
+                 T* d, const T* y, const T* dinv, const T* b, hipStream_t s);
+template <typename T>
+void seg_add(const LSeg* segs, int nseg, int nj, long long maxlen, const T* d, T* x, double a, hipStream_t s);
+template <typename T>
+void seg_zero(const LSeg* segs, int nseg, int nj, long long maxlen, T* x, hipStream_t s);
+template <typename T>
+void dense_solve(const DSeg* segs, int nseg, int nj, int maxn, const double* Ainv, const T* b, T* x, hipStream_t s);
+
+}  // namespace bt

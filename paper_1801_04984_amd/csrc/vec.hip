@@ -1,0 +1,309 @@
+// Segmented vector kernels: every vector is a concatenation of segments
+// (one per instance, or per instance and multigrid level), each with r+1
+// time levels at a fixed stride.  Reductions are two-stage with a fixed
+// partition (deterministic: the same inputs give the same bits).
+#include "vec.h"
+
+namespace bt {
+
+// ---- fill / copy / cast ------------------------------------------------------
+template <typename T>
+__global__ void fill_kernel(T* __restrict__ x, T v, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+template <typename A, typename B>
+__global__ void cast_kernel(const A* __restrict__ x, B* __restrict__ y, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = (B)x[i];
+}
+static unsigned nblocks(long long n) {
+  long long b = (n + 255) / 256;
+  return (unsigned)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
+}
+template <typename T>
+void vfill(T* x, T v, long long n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(fill_kernel<T>, dim3(nblocks(n)), dim3(256), 0, s, x, v, n);
+}
+template void vfill<double>(double*, double, long long, hipStream_t);
+template void vfill<float>(float*, float, long long, hipStream_t);
+void vcast(const double* x, float* y, long long n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL((cast_kernel<double, float>), dim3(nblocks(n)), dim3(256), 0, s, x, y, n);
+}
+void vcast(const float* x, double* y, long long n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL((cast_kernel<float, double>), dim3(nblocks(n)), dim3(256), 0, s, x, y, n);
+}
+
+// ---- y = a x + b y over whole vectors ---------------------------------------------
+template <typename T>
+__global__ void axpby_kernel(T a, const T* __restrict__ x, T b, T* __restrict__ y, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = a * x[i] + b * y[i];
+}
+template <typename T>
+void vaxpby(double a, const T* x, double b, T* y, long long n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL((axpby_kernel<T>), dim3(nblocks(n)), dim3(256), 0, s, T(a), x, T(b), y, n);
+}
+template void vaxpby<double>(double, const double*, double, double*, long long, hipStream_t);
+template void vaxpby<float>(double, const float*, double, float*, long long, hipStream_t);
+// y += x (mixed precision accumulate: double += float)
+__global__ void acc_f32_kernel(const float* __restrict__ x, double* __restrict__ y, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] += (double)x[i];
+}
+void vacc(const float* x, double* y, long long n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(acc_f32_kernel, dim3(nblocks(n)), dim3(256), 0, s, x, y, n);
+}
+
+// ---- segmented multi-dot: out[seg][k] = <V_k, w> over segment seg ------------
+// stage 1: block b of segment s reduces a fixed chunk for KB vectors
+constexpr int kDotThreads = 256;
+constexpr int kKB = 8;
+template <typename TV, typename TW>
+__global__ __launch_bounds__(kDotThreads) void mdot_stage1(const TV* __restrict__ V, long long ldv, int k0, int nk,
+                                                           const TW* __restrict__ w, const VSeg* __restrict__ segs,
+                                                           int nchunk, double* __restrict__ partial) {
+  const VSeg sg = segs[blockIdx.y];
+  const int chunk = blockIdx.x;
+  const long long len = sg.len;
+  const long long per = (len + nchunk - 1) / nchunk;
+  const long long beg = chunk * per, end = beg + per < len ? beg + per : len;
+  double acc[kKB];
+#pragma unroll
+  for (int k = 0; k < kKB; ++k) acc[k] = 0.0;
+  for (long long i = beg + threadIdx.x; i < end; i += kDotThreads) {
+    const double wi = (double)w[sg.off + i];
+#pragma unroll
+    for (int k = 0; k < kKB; ++k)
+      if (k < nk) acc[k] += (double)V[(long long)(k0 + k) * ldv + sg.off + i] * wi;
+  }
+  __shared__ double red[kKB][kDotThreads / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kKB; ++k) {
+    double v = acc[k];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if (lane == 0) red[k][wv] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kKB && threadIdx.x < nk) {
+    double v = 0.0;
+    for (int q = 0; q < kDotThreads / 64; ++q) v += red[threadIdx.x][q];
+    partial[((long long)blockIdx.y * nchunk + chunk) * 64 + k0 + threadIdx.x] = v;
+  }
+}
+__global__ void mdot_stage2(const double* __restrict__ partial, int nseg, int nchunk, int nk,
+                            double* __restrict__ out) {
+  const int s = blockIdx.x;
+  const int k = threadIdx.x;
+  if (k >= nk) return;
+  double v = 0.0;
+  for (int c = 0; c < nchunk; ++c) v += partial[((long long)s * nchunk + c) * 64 + k];
+  out[s * 64 + k] = v;
+}
+
+template <typename TV, typename TW>
+void seg_mdot(const TV* V, long long ldv, int nk, const TW* w, const VSeg* segs, int nseg, int nchunk,
+              double* partial, double* out, hipStream_t s) {
+  for (int k0 = 0; k0 < nk; k0 += kKB) {
+    int kk = nk - k0 < kKB ? nk - k0 : kKB;
+    hipLaunchKernelGGL((mdot_stage1<TV, TW>), dim3(nchunk, nseg), dim3(kDotThreads), 0, s, V, ldv, k0, kk, w, segs,
+                       nchunk, partial);
+  }
+  hipLaunchKernelGGL(mdot_stage2, dim3(nseg), dim3(64), 0, s, partial, nseg, nchunk, nk, out);
+}
+template void seg_mdot<double, double>(const double*, long long, int, const double*, const VSeg*, int, int, double*,
+                                       double*, hipStream_t);
+template void seg_mdot<float, float>(const float*, long long, int, const float*, const VSeg*, int, int, double*,
+                                     double*, hipStream_t);
+
+// ---- segmented multi-axpy: w[seg] += sum_k c[seg][k] V_k[seg] -----------------
+template <typename TV, typename TW>
+__global__ void maxpy_kernel(const TV* __restrict__ V, long long ldv, int nk, const double* __restrict__ c,
+                             double csign, TW* __restrict__ w, const VSeg* __restrict__ segs) {
+  const VSeg sg = segs[blockIdx.y];
+  const double* cs = c + blockIdx.y * 64;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < sg.len;
+       i += (long long)gridDim.x * blockDim.x) {
+    double v = (double)w[sg.off + i];
+    for (int k = 0; k < nk; ++k) v += csign * cs[k] * (double)V[(long long)k * ldv + sg.off + i];
+    w[sg.off + i] = (TW)v;
+  }
+}
+template <typename TV, typename TW>
+void seg_maxpy(const TV* V, long long ldv, int nk, const double* c, double csign, TW* w, const VSeg* segs, int nseg,
+               long long maxlen, hipStream_t s) {
+  long long b = (maxlen + 255) / 256;
+  unsigned gx = (unsigned)(b > 2048 ? 2048 : (b < 1 ? 1 : b));
+  hipLaunchKernelGGL((maxpy_kernel<TV, TW>), dim3(gx, nseg), dim3(256), 0, s, V, ldv, nk, c, csign, w, segs);
+}
+template void seg_maxpy<double, double>(const double*, long long, int, const double*, double, double*, const VSeg*,
+                                        int, long long, hipStream_t);
+template void seg_maxpy<float, float>(const float*, long long, int, const double*, double, float*, const VSeg*, int,
+                                      long long, hipStream_t);
+
+// ---- segmented scale: y[seg] = s[seg*64 + idx] * x[seg] (idx-th coefficient) ----------
+template <typename TX, typename TY>
+__global__ void sscale_kernel(const TX* __restrict__ x, TY* __restrict__ y, const double* __restrict__ sc, int idx,
+                              int inv, const VSeg* __restrict__ segs) {
+  const VSeg sg = segs[blockIdx.y];
+  double f = sc[blockIdx.y * 64 + idx];
+  if (inv == 1) f = f > 0.0 ? 1.0 / f : 0.0;
+  else if (inv == 2) f = f > 0.0 ? 1.0 / sqrt(f) : 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < sg.len;
+       i += (long long)gridDim.x * blockDim.x)
+    y[sg.off + i] = (TY)(f * (double)x[sg.off + i]);
+}
+template <typename TX, typename TY>
+void seg_scale(const TX* x, TY* y, const double* sc, int idx, int inv, const VSeg* segs, int nseg, long long maxlen,
+               hipStream_t s) {
+  long long b = (maxlen + 255) / 256;
+  unsigned gx = (unsigned)(b > 2048 ? 2048 : (b < 1 ? 1 : b));
+  hipLaunchKernelGGL((sscale_kernel<TX, TY>), dim3(gx, nseg), dim3(256), 0, s, x, y, sc, idx, inv, segs);
+}
+template void seg_scale<double, double>(const double*, double*, const double*, int, int, const VSeg*, int, long long,
+                                        hipStream_t);
+template void seg_scale<float, float>(const float*, float*, const double*, int, int, const VSeg*, int, long long,
+                                      hipStream_t);
+template void seg_scale<double, float>(const double*, float*, const double*, int, int, const VSeg*, int, long long,
+                                       hipStream_t);
+
+// ---- time transform: y_i = sum_j M_ij x_j per spatial DoF (all instances) -----
+template <typename T, int NL>
+__global__ void ttrans_kernel(const InstDev* __restrict__ insts, const T* __restrict__ x, T* __restrict__ y, Mat4 M) {
+  const InstDev& I = insts[blockIdx.y];
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < I.N; k += (long long)gridDim.x * blockDim.x) {
+    T v[NL];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) v[j] = x[I.x_off + j * I.N + k];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      T s = 0;
+#pragma unroll
+      for (int j = 0; j < NL; ++j) s += T(M.m[i * 4 + j]) * v[j];
+      y[I.x_off + i * I.N + k] = s;
+    }
+  }
+}
+template <typename T>
+void time_transform(const InstDev* insts, int count, long long maxN, int nl, const Mat4& M, const T* x, T* y,
+                    hipStream_t s) {
+  long long b = (maxN + 255) / 256;
+  dim3 g((unsigned)(b > 4096 ? 4096 : b), count);
+  switch (nl) {
+    case 1: hipLaunchKernelGGL((ttrans_kernel<T, 1>), g, dim3(256), 0, s, insts, x, y, M); break;
+    case 2: hipLaunchKernelGGL((ttrans_kernel<T, 2>), g, dim3(256), 0, s, insts, x, y, M); break;
+    case 3: hipLaunchKernelGGL((ttrans_kernel<T, 3>), g, dim3(256), 0, s, insts, x, y, M); break;
+    default: hipLaunchKernelGGL((ttrans_kernel<T, 4>), g, dim3(256), 0, s, insts, x, y, M); break;
+  }
+}
+template void time_transform<double>(const InstDev*, int, long long, int, const Mat4&, const double*, double*,
+                                     hipStream_t);
+template void time_transform<float>(const InstDev*, int, long long, int, const Mat4&, const float*, float*,
+                                    hipStream_t);
+
+// ---- Chebyshev update on level segments -------------------------------------------
+// x += d; r -= y; d = rho d + sig Dinv r      (y = A d computed by the caller)
+// first step (init != 0): r = b - y0 is not touched; d = sig Dinv r; x untouched.
+template <typename T>
+__global__ void cheb_kernel(const LSeg* __restrict__ segs, int mode, double rho, double sig, T* __restrict__ x,
+                            T* __restrict__ r, T* __restrict__ d, const T* __restrict__ y,
+                            const T* __restrict__ dinv, const T* __restrict__ b) {
+  const LSeg sg = segs[blockIdx.y];
+  const int j = blockIdx.z;
+  const long long off = sg.off + j * sg.jstride, doff = sg.doff + j * sg.djstride;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < sg.len;
+       i += (long long)gridDim.x * blockDim.x) {
+    const T di = dinv[doff + i];
+    if (mode == 0) {         // init: d = sig Dinv r
+      d[off + i] = T(sig) * di * r[off + i];
+    } else if (mode == 2) {  // init from x = 0: x = 0, r = b, d = sig Dinv b
+      const T bb = b[off + i];
+      x[off + i] = T(0);
+      r[off + i] = bb;
+      d[off + i] = T(sig) * di * bb;
+    } else {                 // regular step
+      const T dd = d[off + i];
+      x[off + i] += dd;
+      const T rr = r[off + i] - y[off + i];
+      r[off + i] = rr;
+      d[off + i] = T(rho) * dd + T(sig) * di * rr;
+    }
+  }
+}
+// final: x += d
+template <typename T>
+__global__ void addseg_kernel(const LSeg* __restrict__ segs, const T* __restrict__ d, T* __restrict__ x, double a) {
+  const LSeg sg = segs[blockIdx.y];
+  const long long off = sg.off + blockIdx.z * sg.jstride;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < sg.len;
+       i += (long long)gridDim.x * blockDim.x)
+    x[off + i] += T(a) * d[off + i];
+}
+static dim3 lgrid(long long maxlen, int nseg, int nj) {
+  long long b = (maxlen + 255) / 256;
+  return dim3((unsigned)(b > 2048 ? 2048 : (b < 1 ? 1 : b)), nseg, nj);
+}
+template <typename T>
+void cheb_update(const LSeg* segs, int nseg, int nj, long long maxlen, int mode, double rho, double sig, T* x, T* r,
+                 T* d, const T* y, const T* dinv, const T* b, hipStream_t s) {
+  hipLaunchKernelGGL((cheb_kernel<T>), lgrid(maxlen, nseg, nj), dim3(256), 0, s, segs, mode, rho, sig, x, r, d, y,
+                     dinv, b);
+}
+template <typename T>
+void seg_add(const LSeg* segs, int nseg, int nj, long long maxlen, const T* d, T* x, double a, hipStream_t s) {
+  hipLaunchKernelGGL((addseg_kernel<T>), lgrid(maxlen, nseg, nj), dim3(256), 0, s, segs, d, x, a);
+}
+template void cheb_update<double>(const LSeg*, int, int, long long, int, double, double, double*, double*, double*,
+                                  const double*, const double*, const double*, hipStream_t);
+template void cheb_update<float>(const LSeg*, int, int, long long, int, double, double, float*, float*, float*,
+                                 const float*, const float*, const float*, hipStream_t);
+template void seg_add<double>(const LSeg*, int, int, long long, const double*, double*, double, hipStream_t);
+template void seg_add<float>(const LSeg*, int, int, long long, const float*, float*, double, hipStream_t);
+
+// zero a level segment set
+template <typename T>
+__global__ void zseg_kernel(const LSeg* __restrict__ segs, T* __restrict__ x) {
+  const LSeg sg = segs[blockIdx.y];
+  const long long off = sg.off + blockIdx.z * sg.jstride;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < sg.len;
+       i += (long long)gridDim.x * blockDim.x)
+    x[off + i] = T(0);
+}
+template <typename T>
+void seg_zero(const LSeg* segs, int nseg, int nj, long long maxlen, T* x, hipStream_t s) {
+  hipLaunchKernelGGL((zseg_kernel<T>), lgrid(maxlen, nseg, nj), dim3(256), 0, s, segs, x);
+}
+template void seg_zero<double>(const LSeg*, int, int, long long, double*, hipStream_t);
+template void seg_zero<float>(const LSeg*, int, int, long long, float*, hipStream_t);
+
+// ---- dense coarse solve: x_seg = Ainv_seg b_seg (FP64 matrices, any T vectors) -----
+// one block per (segment, time level); Ainv row-major n x n at segs[].moff (+ j*mjstride)
+template <typename T>
+__global__ __launch_bounds__(256) void dense_kernel(const DSeg* __restrict__ segs, const double* __restrict__ Ainv,
+                                                    const T* __restrict__ b, T* __restrict__ x) {
+  const DSeg sg = segs[blockIdx.y];
+  const int j = blockIdx.z;
+  const double* A = Ainv + sg.moff + (long long)j * sg.mjstride;
+  const long long vo = sg.off + j * sg.jstride;
+  const int n = sg.n;
+  extern __shared__ double sb[];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sb[i] = (double)b[vo + i];
+  __syncthreads();
+  for (int row = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); row < n; row += gridDim.x * (blockDim.x / 64)) {
+    double s = 0.0;
+    for (int c = threadIdx.x & 63; c < n; c += 64) s += A[(long long)row * n + c] * sb[c];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if ((threadIdx.x & 63) == 0) x[vo + row] = (T)s;
+  }
+}
+template <typename T>
+void dense_solve(const DSeg* segs, int nseg, int nj, int maxn, const double* Ainv, const T* b, T* x, hipStream_t s) {
+  unsigned gx = (unsigned)((maxn + 3) / 4);
+  if (gx > 64) gx = 64;
+  hipLaunchKernelGGL((dense_kernel<T>), dim3(gx, nseg, nj), dim3(256), maxn * sizeof(double), s, segs, Ainv, b, x);
+}
+template void dense_solve<double>(const DSeg*, int, int, int, const double*, const double*, double*, hipStream_t);
+template void dense_solve<float>(const DSeg*, int, int, int, const double*, const float*, float*, hipStream_t);
+
+}  // namespace bt

@@ -1,0 +1,168 @@
+"""Parity of the HIP slab solver (solve_slab / step / adjoint_sweep through
+the C ABI) with the oracle's direct sparse LU solves, per field."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_common import field_rel, make_pair, small_workload, torch_cuda
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def _rhs(prob, seed=1, t=0.1):
+    state = np.random.default_rng(seed).standard_normal(prob.N)
+    state[prob.mask] = 0.0
+    return prob.rhs(t, state)
+
+
+@pytest.mark.parametrize("n", [(12, 10), (33, 20)])
+@pytest.mark.parametrize("r", [0, 1, 2])
+def test_solve_fp64(n, r):
+    torch = torch_cuda()
+    wl = small_workload(2, n, r, seed=3 + r)
+    h, (prob,) = make_pair([wl])
+    b = _rhs(prob)
+    ref = prob.solve(b)
+    x, info, st = h.solve(torch.tensor(b, device="cuda"))
+    assert st == 0 and info[0]["status"] == 0, info
+    err = field_rel(prob, x.cpu().numpy(), ref)
+    assert max(err.values()) < TOL, err
+    assert info[0]["iterations"] < 120
+    h.close()
+
+
+@pytest.mark.parametrize("r", [0, 1])
+def test_solve_mixed_refined(r):
+    torch = torch_cuda()
+    wl = small_workload(2, (24, 17), r, seed=9)
+    h, (prob,) = make_pair([wl])
+    b = _rhs(prob, seed=2)
+    ref = prob.solve(b)
+    x, info, st = h.solve(torch.tensor(b, device="cuda"), precision=1)
+    assert st == 0 and info[0]["ir_sweeps"] >= 1, info
+    err = field_rel(prob, x.cpu().numpy(), ref)
+    assert max(err.values()) < TOL, err
+    # one refinement sweep only: the FP32 inner solve alone is good to the
+    # single-precision level (the mixed path before refinement)
+    x1, info1, st1 = h.solve(torch.tensor(b, device="cuda"), precision=1, max_refine=1, inner_rtol=1e-6)
+    err1 = field_rel(prob, x1.cpu().numpy(), ref)
+    assert max(err1.values()) < 1e-4, err1
+    h.close()
+
+
+def test_solve_batched_uneven_matches_single():
+    torch = torch_cuda()
+    wls = [small_workload(2, n, 1, seed=20 + i, b=0.6 + 0.1 * i) for i, n in enumerate([(9, 9), (21, 14), (16, 16)])]
+    h, probs = make_pair(wls)
+    bs = [_rhs(p, seed=5 + i) for i, p in enumerate(probs)]
+    b = np.concatenate(bs)
+    x, info, st = h.solve(torch.tensor(b, device="cuda"))
+    assert st == 0, info
+    xv = x.cpu().numpy()
+    for k, (p, bk) in enumerate(zip(probs, bs)):
+        got = xv[h.slab_offsets[k]: h.slab_offsets[k] + p.L * p.N]
+        err = field_rel(p, got, p.solve(bk))
+        assert max(err.values()) < TOL, (k, err)
+    h.close()
+
+
+def test_solve_transposed():
+    torch = torch_cuda()
+    wl = small_workload(2, (14, 11), 1, seed=31)
+    h, (prob,) = make_pair([wl])
+    b = np.random.default_rng(8).standard_normal(prob.L * prob.N)
+    ref = prob.solve(b, transpose=True)
+    x, info, st = h.solve(torch.tensor(b, device="cuda"), transpose=True)
+    assert st == 0, info
+    err = field_rel(prob, x.cpu().numpy(), ref)
+    assert max(err.values()) < TOL, err
+    h.close()
+
+
+@pytest.mark.parametrize("r", [0, 1])
+def test_step_matches_oracle_march_and_resumes(r):
+    torch = torch_cuda()
+    wl = small_workload(2, (13, 9), r, seed=41, load_kind=W.LOAD_RAMP)
+    h, (prob,) = make_pair([wl])
+    ns = 4
+    ref = prob.march(ns)
+    state = h.zeros_state()
+    slabs = torch.zeros(ns * h.slab_len, dtype=torch.float64, device="cuda")
+    chk = torch.zeros(ns * h.state_len, dtype=torch.float64, device="cuda")
+    infos, st = h.step(ns, 0.0, state, slabs_out=slabs, checkpoints=chk)
+    assert st == 0, infos
+    sv = slabs.cpu().numpy().reshape(ns, -1)
+    for n in range(ns):
+        err = field_rel(prob, sv[n], ref[n])
+        assert max(err.values()) < TOL, (n, err)
+    cv = chk.cpu().numpy().reshape(ns, -1)
+    assert np.all(cv[0] == 0.0)
+    for n in range(1, ns):
+        np.testing.assert_array_equal(cv[n], sv[n - 1][r * prob.N:(r + 1) * prob.N])
+    # resume: 2 + 2 slabs from the saved state equals 4 straight (bitwise)
+    s2 = h.zeros_state()
+    h.step(2, 0.0, s2)
+    h.step(2, 2 * wl.tau, s2)
+    np.testing.assert_array_equal(s2.cpu().numpy(), state.cpu().numpy())
+    h.close()
+
+
+def test_terzaghi_workload_on_gpu():
+    torch = torch_cuda()
+    wl = W.c1_terzaghi()
+    h, (prob,) = make_pair([wl])
+    ref = prob.march(wl.nslabs)
+    state = h.zeros_state()
+    slabs = torch.zeros(wl.nslabs * h.slab_len, dtype=torch.float64, device="cuda")
+    infos, st = h.step(wl.nslabs, 0.0, state, slabs_out=slabs)
+    assert st == 0
+    sv = slabs.cpu().numpy().reshape(wl.nslabs, -1)
+    for n in range(wl.nslabs):
+        err = field_rel(prob, sv[n], ref[n])
+        assert max(err.values()) < TOL, (n, err)
+    # x-invariance of the GPU pressure (1D consolidation)
+    p = sv[-1][prob.mesh.off_p:prob.N].reshape(prob.mesh.sp[1], prob.mesh.sp[0])
+    assert np.abs(p - p[:, :1]).max() < 1e-9 * np.abs(p).max()
+    h.close()
+
+
+def test_error_paths():
+    torch = torch_cuda()
+    wl = small_workload(2, (10, 10), 1, seed=2)
+    h, (prob,) = make_pair([wl])
+    b = _rhs(prob)
+    x, info, st = h.solve(torch.tensor(b, device="cuda"), maxit=1)
+    assert st == 4 and info[0]["status"] == 4 and info[0]["iterations"] == 1
+    assert np.isfinite(info[0]["rel_residual"]) and info[0]["rel_residual"] > 1e-13
+    bad = b.copy()
+    bad[5] = np.nan
+    x, info, st = h.solve(torch.tensor(bad, device="cuda"))
+    assert st == 6
+    x, info, st = h.solve(torch.tensor(b, device="cuda"), restart=0)
+    assert st == 1
+    h.close()
+
+
+@pytest.mark.parametrize("r", [0, 1])
+def test_adjoint_gradient_matches_oracle(r):
+    torch = torch_cuda()
+    from oracle import adjoint, fe
+    wl = small_workload(2, (8, 7), r, seed=51, load_kind=W.LOAD_RAMP)
+    theta = wl.log_k()
+    h, (prob,) = make_pair([wl], [theta])
+    ns = 3
+    sens = W.sensors(7, 2, 61)
+    P = fe.pressure_point_matrix(prob.mesh, sens)
+    p_obs = 0.05 * np.random.default_rng(3).standard_normal((ns, len(sens)))
+    Jref, gref, _ = adjoint.gradient(prob, ns, P, p_obs)
+    state = h.zeros_state()
+    chk = torch.zeros(ns * h.state_len, dtype=torch.float64, device="cuda")
+    infos, st = h.step(ns, 0.0, state, checkpoints=chk)
+    assert st == 0
+    J, g, st = h.adjoint(ns, 0.0, chk, sens, torch.tensor(p_obs.reshape(-1), device="cuda"))
+    assert st == 0
+    assert abs(J[0] - Jref) <= 1e-9 * abs(Jref)
+    gv = g.cpu().numpy()
+    assert np.linalg.norm(gv - gref) <= 1e-8 * np.linalg.norm(gref), (np.abs(gv - gref).max(), np.abs(gref).max())
+    h.close()
