@@ -89,7 +89,7 @@ typedef struct {
 
 /* Solver controls (nullable: defaults in brackets). */
 typedef struct {
-  double rtol;          /* stop when ||b - A x|| <= rtol ||b||          [1e-13]   */
+  double rtol;          /* stop when ||b - A x|| <= rtol ||b||          [1e-12]   */
   int32_t maxit;        /* total GMRES iterations                         [1000]   */
   int32_t restart;      /* GMRES(m) restart length, <= 64                   [40]   */
   int32_t precision;    /* biot_precision                                [FP64]   */
@@ -144,8 +144,11 @@ biot_status slab_rhs(biot_problem h, const double* state, double t_start, double
 
 /* Solve A x = rhs (device vectors; x: initial guess in, solution out) with
  * right-preconditioned restarted GMRES and the level-blockwise fixed-stress
- * preconditioner (section "Preconditioning technology").  Synchronises
- * `stream` once per restart cycle.  info: host, one entry per instance. */
+ * preconditioner (section "Preconditioning technology").  Stops per instance
+ * when the true relative residual is <= rtol, or when two restart cycles in a
+ * row fail to halve it (the FP64 rounding floor of b - A x); the latter counts
+ * as converged if the residual is within 100 rtol, else BIOT_ERR_NOCONV.
+ * Synchronises `stream` once per iteration.  info: host, one per instance. */
 biot_status solve_slab(biot_problem h, const double* rhs, double* x,
                        const biot_solve_opts* opts, biot_solve_info* info, void* stream);
 

@@ -1018,6 +1018,7 @@ static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const Solv
   std::vector<double> H((size_t)cnt * (kMaxRestart + 1) * kMaxRestart), cs(cnt * kMaxRestart), sn(cnt * kMaxRestart),
       g(cnt * (kMaxRestart + 1));
   std::vector<double> h1(cnt * 64), h2(cnt * 64), hn(cnt * 64), coef(cnt * 64);
+  std::vector<int> stall(cnt, 0);
   int total = 0;
   while (true) {
     bool all = true;
@@ -1108,15 +1109,25 @@ static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const Solv
       apply_prec<T>(h, B.w, B.t, ctl.qdeg, s);
       vaxpby<T>(1.0, B.t, 1.0, x, S, s);
     }
+    std::vector<double> prev = beta;
     residual<T>(h, b, x, B.r, transpose, s);
     seg_norms<T>(P, B.r, cnt, s, beta);
     for (int k = 0; k < cnt; ++k) {
       if (!std::isfinite(beta[k])) throw BiotError{BIOT_ERR_NONFINITE, "non-finite residual"};
       relres[k] = bn[k] > 0 ? beta[k] / bn[k] : 0.0;
-      if (bn[k] == 0.0 || beta[k] <= ctl.rtol * bn[k]) done[k] = 1;
+      if (bn[k] == 0.0 || beta[k] <= ctl.rtol * bn[k]) { done[k] = 1; continue; }
+      // rounding floor of b - A x: two restart cycles in a row that do not halve the true residual
+      if (!done[k] && jk[k] > 0) {
+        stall[k] = (beta[k] > 0.5 * prev[k]) ? stall[k] + 1 : 0;
+        if (stall[k] >= 2) { done[k] = 2; }
+      }
     }
   }
-  for (int k = 0; k < cnt; ++k) status[k] = done[k] ? BIOT_OK : BIOT_ERR_NOCONV;
+  for (int k = 0; k < cnt; ++k) {
+    if (done[k] == 1) status[k] = BIOT_OK;
+    else if (done[k] == 2) status[k] = (relres[k] <= 100.0 * ctl.rtol) ? BIOT_OK : BIOT_ERR_NOCONV;
+    else status[k] = BIOT_ERR_NOCONV;
+  }
 }
 
 
@@ -1125,7 +1136,7 @@ static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const Solv
 static void solve_impl(biot_problem_s* h, const double* b, double* x, int transpose, const biot_solve_opts* o,
                        biot_solve_info* info, hipStream_t s) {
   biot_solve_opts opts;
-  opts.rtol = 1e-13; opts.maxit = 1000; opts.restart = 40; opts.precision = BIOT_FP64;
+  opts.rtol = 1e-12; opts.maxit = 1000; opts.restart = 40; opts.precision = BIOT_FP64;
   opts.inner_rtol = 1e-5; opts.max_refine = 20; opts.cheb_degree = 8;
   if (o) opts = *o;
   if (!(opts.rtol > 0) || !std::isfinite(opts.rtol)) throw BiotError{BIOT_ERR_ARG, "rtol must be > 0"};
@@ -1152,6 +1163,7 @@ static void solve_impl(biot_problem_s* h, const double* b, double* x, int transp
     seg_norms<double>(P, b, cnt, s, bn);
     std::vector<int> tot(cnt, 0), totr(cnt, 0), sweeps(cnt, 0);
     std::vector<char> done(cnt, 0);
+    std::vector<double> rprev(cnt, 1e300);
     for (int sw = 0; sw <= opts.max_refine; ++sw) {
       residual<double>(h, b, x, B64.r, transpose, s);
       seg_norms<double>(P, B64.r, cnt, s, rn);
@@ -1159,6 +1171,9 @@ static void solve_impl(biot_problem_s* h, const double* b, double* x, int transp
       for (int k = 0; k < cnt; ++k) {
         if (!std::isfinite(rn[k])) throw BiotError{BIOT_ERR_NONFINITE, "non-finite residual"};
         if (bn[k] == 0.0 || rn[k] <= opts.rtol * bn[k]) done[k] = 1;
+        // refinement no longer reduces the FP64 residual: rounding floor reached
+        if (!done[k] && rn[k] > 0.5 * rprev[k] && rn[k] <= 100.0 * opts.rtol * bn[k]) done[k] = 1;
+        rprev[k] = rn[k];
         all = all && done[k];
       }
       if (all || sw == opts.max_refine) break;
