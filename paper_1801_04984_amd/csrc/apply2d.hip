@@ -12,6 +12,10 @@
 // only along the flux component's own axis because the open basis is
 // orthogonal under 2-point Gauss.
 //
+// The element u-rows use the dense element matrices tau A_e (18x18) and E_e
+// (18x4), identical for every cell of an instance: 396 FMA per cell and level,
+// fewer than the sum-factorised evaluation in 2D and far lighter on registers.
+//
 // Work decomposition: one block = one tile of 15x15 owned cells plus a
 // one-cell halo on the low sides (16x16 threads, one cell each).  Every
 // output DoF is written by exactly one block: u-rows are summed from the
@@ -29,7 +33,7 @@ constexpr int kO2 = kT2 - 1;
 template <typename T, int NL, bool TR>
 __global__ __launch_bounds__(256) void apply2d_kernel(const InstDev* __restrict__ insts,
                                                       const int4* __restrict__ work, TimeMat tm,
-                                                      const T* __restrict__ kinv_all,
+                                                      const T* __restrict__ kinv_all, const T* __restrict__ emat,
                                                       const T* __restrict__ X, T* __restrict__ Y) {
   __shared__ T E[18][kT2 * kT2];
   const int4 w = work[blockIdx.x];
@@ -122,15 +126,25 @@ __global__ __launch_bounds__(256) void apply2d_kernel(const InstDev* __restrict_
         }
       cp = bb;
     }
-    T ox_[3][3], oy_[3][3];
-    elast2d<T>(ux, uy, pc, hx, hy, tau, cp, lam, mu, ox_, oy_);
+    // element u-rows: tau A_e u - cp E_e p  (A_e, E_e identical for every cell of the instance)
+    {
+      const T* AE = emat + I.emat_off;
+      const T* EE = AE + 18 * 18;
+      T uu[18];
 #pragma unroll
-    for (int b = 0; b < 3; ++b)
+      for (int b = 0; b < 3; ++b)
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        E[b * 3 + a][tid] = ox_[b][a];
-        E[9 + b * 3 + a][tid] = oy_[b][a];
+        for (int a = 0; a < 3; ++a) { uu[b * 3 + a] = ux[b][a]; uu[9 + b * 3 + a] = uy[b][a]; }
+#pragma unroll
+      for (int rr = 0; rr < 18; ++rr) {
+        T acc = 0;
+#pragma unroll
+        for (int cc = 0; cc < 18; ++cc) acc += AE[rr * 18 + cc] * uu[cc];
+        T ep = EE[rr * 4 + 0] * pc[0][0] + EE[rr * 4 + 1] * pc[0][1] + EE[rr * 4 + 2] * pc[1][0] +
+               EE[rr * 4 + 3] * pc[1][1];
+        E[rr][tid] = acc - cp * ep;
       }
+    }
     T du[2][2], dq[2][2];
     divu2d<T>(ux, uy, hx, hy, du);
     divq2d<T>(qx, qy, hx, hy, dq);
@@ -262,10 +276,10 @@ static void launch_nl(const ApplyArgs& a, const void* x, void* y, int transpose)
   dim3 blk(kT2, kT2);
   if (transpose)
     hipLaunchKernelGGL((apply2d_kernel<T, NL, true>), dim3(a.nwork), blk, 0, a.stream, a.inst, a.work,
-                       *a.tm, (const T*)a.kinv, (const T*)x, (T*)y);
+                       *a.tm, (const T*)a.kinv, (const T*)a.emat, (const T*)x, (T*)y);
   else
     hipLaunchKernelGGL((apply2d_kernel<T, NL, false>), dim3(a.nwork), blk, 0, a.stream, a.inst, a.work,
-                       *a.tm, (const T*)a.kinv, (const T*)x, (T*)y);
+                       *a.tm, (const T*)a.kinv, (const T*)a.emat, (const T*)x, (T*)y);
 }
 
 template <typename T>

@@ -12,6 +12,7 @@ struct ApplyArgs {
   int nl;                // r + 1
   const TimeMat* tm;     // host copy, passed by value to kernels
   const void* kinv;      // device per-cell eta/K (double or float, matching dtype)
+  const void* emat;      // device element matrices (2D), matching dtype
   hipStream_t stream;
 };
 

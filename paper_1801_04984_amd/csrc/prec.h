@@ -96,6 +96,7 @@ struct UGridSeg {
   long long voff, vjstride;    // u block of time level j: voff + j*vjstride, components contiguous
   long long doff;              // Dinv (normalised), shared by all time levels
   long long nu;                // dim * prod(su)
+  long long emat_off;          // 2D: tau*A_e (18x18) in the element-matrix array
 };
 // one separable restriction pass along `axis` (input dims din -> output dims dout)
 struct RPass {
@@ -113,7 +114,7 @@ struct UProl {
 };
 template <typename T>
 void launch_uapply(int dim, const UGridSeg* segs, const int4* work, int nwork, int nj, int mode, const T* x,
-                   const T* b, T* y, hipStream_t s);
+                   const T* b, T* y, const T* emat, hipStream_t s);
 int uapply_tile(int dim);
 template <typename T>
 void launch_uapply3d(const UGridSeg* segs, const int4* work, int nwork, int nj, int mode, const T* x, const T* b,

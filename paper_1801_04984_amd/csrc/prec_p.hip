@@ -80,50 +80,137 @@ __device__ __forceinline__ void pdg_eval(const InstDev& I, const T* __restrict__
   }
 }
 
+// S x on the 2^DIM pressure DoFs of cell ce (x: p-block of one level).  Per
+// axis e and per line through the cell along e, the three flux nodes of the
+// cell are shared by the two DoFs of the line.
 template <typename T, int DIM>
-__global__ void pdg_kernel(const InstDev* __restrict__ insts, const PDgSeg* __restrict__ segs, int mode, ChebCoef cc,
+__device__ __forceinline__ void pdg_cell(const InstDev& I, const T* __restrict__ x, const T* __restrict__ dqi,
+                                         const int ce[3], T cm, T Sx[1 << DIM]) {
+  constexpr int NG = 1 << DIM;
+  const long long pstr[3] = {1, (long long)I.sp[0], (long long)I.sp[0] * I.sp[1]};
+  long long base = 0;
+#pragma unroll
+  for (int e = 0; e < DIM; ++e) base += (long long)(2 * ce[e]) * pstr[e];
+  T wp = 1;
+#pragma unroll
+  for (int e = 0; e < DIM; ++e) wp *= T(0.5 * I.h[e]);
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    long long o = base;
+#pragma unroll
+    for (int e = 0; e < DIM; ++e) o += ((g >> e) & 1) * pstr[e];
+    Sx[g] = cm * wp * x[o];
+  }
+#pragma unroll
+  for (int e = 0; e < DIM; ++e) {
+    T hp = 1;
+#pragma unroll
+    for (int f = 0; f < DIM; ++f)
+      if (f != e) hp *= T(0.5 * I.h[f]);
+    const T c2 = T(I.tau) * hp * hp;
+    // flux node strides of q_e: closed along e, open elsewhere
+    long long qs[3], sacc = 1;
+#pragma unroll
+    for (int f = 0; f < DIM; ++f) { qs[f] = sacc; sacc *= I.sq[e][f]; }
+    const bool has_lo = ce[e] > 0, has_hi = ce[e] + 1 < I.n[e];
+#pragma unroll
+    for (int line = 0; line < (NG >> 1); ++line) {
+      // DoF index of the line's low DoF: insert a 0 bit for axis e into `line`
+      const int g0 = ((line >> e) << (e + 1)) | (line & ((1 << e) - 1));
+      long long lb = base, qb = I.off_q[e];
+#pragma unroll
+      for (int f = 0; f < DIM; ++f)
+        if (f != e) {
+          const int gf = (g0 >> f) & 1;
+          lb += gf * pstr[f];
+          qb += (long long)(2 * ce[f] + gf) * qs[f];
+        }
+      const T x0 = x[lb], x1 = x[lb + pstr[e]];
+      const T xl0 = has_lo ? x[lb - 2 * pstr[e]] : T(0), xl1 = has_lo ? x[lb - pstr[e]] : T(0);
+      const T xh0 = has_hi ? x[lb + 2 * pstr[e]] : T(0), xh1 = has_hi ? x[lb + 3 * pstr[e]] : T(0);
+      const long long qn = qb + (long long)(2 * ce[e]) * qs[e];
+      const T d0 = dqi[qn], d1 = dqi[qn + qs[e]], d2 = dqi[qn + 2 * qs[e]];
+      const T own2 = T(GB(2, 0)) * x0 + T(GB(2, 1)) * x1, own0 = T(GB(0, 0)) * x0 + T(GB(0, 1)) * x1;
+      const T b0 = (T(GB(2, 0)) * xl0 + T(GB(2, 1)) * xl1) + own0;     // node 2ce   (cells ce-1, ce)
+      const T b1 = T(GB(1, 0)) * x0 + T(GB(1, 1)) * x1;                // node 2ce+1 (cell ce)
+      const T b2 = own2 + (T(GB(0, 0)) * xh0 + T(GB(0, 1)) * xh1);     // node 2ce+2 (cells ce, ce+1)
+      const T f0 = d0 * b0, f1 = d1 * b1, f2 = d2 * b2;
+      Sx[g0] += c2 * (T(GB(0, 0)) * f0 + T(GB(1, 0)) * f1 + T(GB(2, 0)) * f2);
+      Sx[g0 | (1 << e)] += c2 * (T(GB(0, 1)) * f0 + T(GB(1, 1)) * f1 + T(GB(2, 1)) * f2);
+    }
+  }
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void pdg_kernel(const InstDev* __restrict__ insts, const PDgSeg* __restrict__ segs, int mode, ChebCoef cc,
                            const T* __restrict__ dqinv, const T* __restrict__ dinv,
                            const T* __restrict__ b, T* __restrict__ x, T* __restrict__ r,
                            const T* __restrict__ din, T* __restrict__ dout) {
+  constexpr int NG = 1 << DIM;
   const PDgSeg sg = segs[blockIdx.y];
   const InstDev& I = insts[sg.inst];
   const int j = blockIdx.z;
-  const long long np = (long long)I.sp[0] * I.sp[1] * I.sp[2];
   const long long vo = sg.voff + j * sg.vjstride;
   const long long dof = sg.doff + j * sg.djstride;
   const T* dqi = dqinv + sg.dqoff;
   const T cm = T(sg.cm[j]);
-  for (long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x; o < np; o += (long long)gridDim.x * blockDim.x) {
-    const T di = dinv[dof + o];
+  const long long pstr[3] = {1, (long long)I.sp[0], (long long)I.sp[0] * I.sp[1]};
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < I.ncells;
+       c += (long long)gridDim.x * blockDim.x) {
+    int ce[3];
+    ce[0] = (int)(c % I.n[0]);
+    ce[1] = (int)((c / I.n[0]) % I.n[1]);
+    ce[2] = DIM == 3 ? (int)(c / ((long long)I.n[0] * I.n[1])) : 0;
+    long long base = 0;
+#pragma unroll
+    for (int e = 0; e < DIM; ++e) base += (long long)(2 * ce[e]) * pstr[e];
+    long long oo[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      long long o = base;
+#pragma unroll
+      for (int e = 0; e < DIM; ++e) o += ((g >> e) & 1) * pstr[e];
+      oo[g] = o;
+    }
     if (mode == kResInitZero) {            // x = 0: r = bsign b, d = s0 Dinv r
-      const T rr = T(cc.bsign) * b[vo + o];
-      x[vo + o] = 0;
-      r[vo + o] = rr;
-      dout[vo + o] = T(cc.s0) * di * rr;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const T rr = T(cc.bsign) * b[vo + oo[g]];
+        x[vo + oo[g]] = 0;
+        r[vo + oo[g]] = rr;
+        dout[vo + oo[g]] = T(cc.s0) * dinv[dof + oo[g]] * rr;
+      }
     } else if (mode == kResInit) {         // r = bsign b - S x, d = s0 Dinv r
-      T Sx, dg;
-      pdg_eval<T, DIM>(I, x + vo, dqi, o, cm, Sx, dg);
-      const T rr = T(cc.bsign) * b[vo + o] - Sx;
-      r[vo + o] = rr;
-      dout[vo + o] = T(cc.s0) * di * rr;
+      T Sx[NG];
+      pdg_cell<T, DIM>(I, x + vo, dqi, ce, cm, Sx);
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const T rr = T(cc.bsign) * b[vo + oo[g]] - Sx[g];
+        r[vo + oo[g]] = rr;
+        dout[vo + oo[g]] = T(cc.s0) * dinv[dof + oo[g]] * rr;
+      }
     } else if (mode == kStep) {            // x += d; r -= S d; d' = rho d + sig Dinv r
-      T Sd, dg;
-      pdg_eval<T, DIM>(I, din + vo, dqi, o, cm, Sd, dg);
-      const T dd = din[vo + o];
-      x[vo + o] += dd;
-      const T rr = r[vo + o] - Sd;
-      r[vo + o] = rr;
-      dout[vo + o] = T(cc.rho) * dd + T(cc.sig) * di * rr;
+      T Sd[NG];
+      pdg_cell<T, DIM>(I, din + vo, dqi, ce, cm, Sd);
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const T dd = din[vo + oo[g]];
+        x[vo + oo[g]] += dd;
+        const T rr = r[vo + oo[g]] - Sd[g];
+        r[vo + oo[g]] = rr;
+        dout[vo + oo[g]] = T(cc.rho) * dd + T(cc.sig) * dinv[dof + oo[g]] * rr;
+      }
     } else {                               // y = Dinv S x  (power iteration)
-      T Sx, dg;
-      pdg_eval<T, DIM>(I, din + vo, dqi, o, cm, Sx, dg);
-      dout[vo + o] = di * Sx;
+      T Sx[NG];
+      pdg_cell<T, DIM>(I, din + vo, dqi, ce, cm, Sx);
+#pragma unroll
+      for (int g = 0; g < NG; ++g) dout[vo + oo[g]] = dinv[dof + oo[g]] * Sx[g];
     }
   }
 }
 
 template <int DIM>
-__global__ void pdg_diag_kernel(const InstDev* __restrict__ insts, const PDgSeg* __restrict__ segs,
+__global__ __launch_bounds__(256) void pdg_diag_kernel(const InstDev* __restrict__ insts, const PDgSeg* __restrict__ segs,
                                 const double* __restrict__ dqinv, double* __restrict__ dinv) {
   const PDgSeg sg = segs[blockIdx.y];
   const InstDev& I = insts[sg.inst];
@@ -141,11 +228,12 @@ template <typename T>
 void launch_pdg(int dim, const InstDev* insts, const PDgSeg* segs, int nseg, int nj, long long maxnp, int mode,
                 ChebCoef cc, const T* dqinv, const T* dinv, const T* b, T* x, T* r, const T* din, T* dout,
                 hipStream_t s) {
+  const long long maxc = maxnp >> dim;      // one thread per cell
   if (dim == 2)
-    hipLaunchKernelGGL((pdg_kernel<T, 2>), grid3(maxnp, nseg, nj), dim3(256), 0, s, insts, segs, mode, cc, dqinv, dinv,
+    hipLaunchKernelGGL((pdg_kernel<T, 2>), grid3(maxc, nseg, nj), dim3(256), 0, s, insts, segs, mode, cc, dqinv, dinv,
                        b, x, r, din, dout);
   else
-    hipLaunchKernelGGL((pdg_kernel<T, 3>), grid3(maxnp, nseg, nj), dim3(256), 0, s, insts, segs, mode, cc, dqinv, dinv,
+    hipLaunchKernelGGL((pdg_kernel<T, 3>), grid3(maxc, nseg, nj), dim3(256), 0, s, insts, segs, mode, cc, dqinv, dinv,
                        b, x, r, din, dout);
 }
 template void launch_pdg<double>(int, const InstDev*, const PDgSeg*, int, int, long long, int, ChebCoef,
@@ -193,7 +281,7 @@ __device__ __forceinline__ void pcell_eval(const PCellSeg& sg, const T* __restri
 }
 
 template <typename T>
-__global__ void pcell_kernel(const PCellSeg* __restrict__ segs, int mode, ChebCoef cc, const T* __restrict__ coef,
+__global__ __launch_bounds__(256) void pcell_kernel(const PCellSeg* __restrict__ segs, int mode, ChebCoef cc, const T* __restrict__ coef,
                              const T* __restrict__ dinv, const T* __restrict__ b, T* __restrict__ x,
                              T* __restrict__ r, const T* __restrict__ din, T* __restrict__ dout) {
   const PCellSeg sg = segs[blockIdx.y];
@@ -230,7 +318,7 @@ __global__ void pcell_kernel(const PCellSeg* __restrict__ segs, int mode, ChebCo
     }
   }
 }
-__global__ void pcell_diag_kernel(const PCellSeg* __restrict__ segs, const double* __restrict__ coef,
+__global__ __launch_bounds__(256) void pcell_diag_kernel(const PCellSeg* __restrict__ segs, const double* __restrict__ coef,
                                   double* __restrict__ dinv) {
   const PCellSeg sg = segs[blockIdx.y];
   const int j = blockIdx.z;
@@ -257,7 +345,7 @@ void launch_pcell_diag(const PCellSeg* segs, int nseg, int nj, long long maxc, c
 }
 
 // ---- Galerkin coefficients ----------------------------------------------------------------
-__global__ void pcoef_first_kernel(const InstDev* __restrict__ insts, const PDgSeg* __restrict__ fine,
+__global__ __launch_bounds__(256) void pcoef_first_kernel(const InstDev* __restrict__ insts, const PDgSeg* __restrict__ fine,
                                    const PCellSeg* __restrict__ lev1, const double* __restrict__ dqinv,
                                    double* __restrict__ coef) {
   const PDgSeg fs = fine[blockIdx.y];
@@ -311,7 +399,7 @@ void launch_pcoef_first(const InstDev* insts, const PDgSeg* fine, const PCellSeg
   hipLaunchKernelGGL(pcoef_first_kernel, grid3(maxc, nseg, 1), dim3(256), 0, s, insts, fine, lev1, dqinv, coef);
 }
 
-__global__ void pcoef_coarsen_kernel(const PCellSeg* __restrict__ fine, const PCellSeg* __restrict__ coarse,
+__global__ __launch_bounds__(256) void pcoef_coarsen_kernel(const PCellSeg* __restrict__ fine, const PCellSeg* __restrict__ coarse,
                                      const double* __restrict__ coef_f, double* __restrict__ coef_c) {
   const PCellSeg fs = fine[blockIdx.y];
   const PCellSeg cs = coarse[blockIdx.y];
@@ -348,7 +436,7 @@ void launch_pcoef_coarsen(const PCellSeg* fine, const PCellSeg* coarse, int nseg
 
 // ---- transfers ------------------------------------------------------------------------------
 template <typename T>
-__global__ void p_restrict_dg_kernel(const InstDev* __restrict__ insts, const PDgSeg* __restrict__ fine,
+__global__ __launch_bounds__(256) void p_restrict_dg_kernel(const InstDev* __restrict__ insts, const PDgSeg* __restrict__ fine,
                                      const PCellSeg* __restrict__ coarse, const T* __restrict__ r,
                                      T* __restrict__ b) {
   const PDgSeg fs = fine[blockIdx.y];
@@ -372,7 +460,7 @@ __global__ void p_restrict_dg_kernel(const InstDev* __restrict__ insts, const PD
   }
 }
 template <typename T>
-__global__ void p_prolong_dg_kernel(const InstDev* __restrict__ insts, const PDgSeg* __restrict__ fine,
+__global__ __launch_bounds__(256) void p_prolong_dg_kernel(const InstDev* __restrict__ insts, const PDgSeg* __restrict__ fine,
                                     const PCellSeg* __restrict__ coarse, double w, const T* __restrict__ e,
                                     T* __restrict__ x) {
   const PDgSeg fs = fine[blockIdx.y];
@@ -390,7 +478,7 @@ __global__ void p_prolong_dg_kernel(const InstDev* __restrict__ insts, const PDg
   }
 }
 template <typename T>
-__global__ void p_restrict_cell_kernel(const PCellSeg* __restrict__ fine, const PCellSeg* __restrict__ coarse,
+__global__ __launch_bounds__(256) void p_restrict_cell_kernel(const PCellSeg* __restrict__ fine, const PCellSeg* __restrict__ coarse,
                                        const T* __restrict__ r, T* __restrict__ b) {
   const PCellSeg fs = fine[blockIdx.y];
   const PCellSeg cs = coarse[blockIdx.y];
@@ -414,7 +502,7 @@ __global__ void p_restrict_cell_kernel(const PCellSeg* __restrict__ fine, const 
   }
 }
 template <typename T>
-__global__ void p_prolong_cell_kernel(const PCellSeg* __restrict__ fine, const PCellSeg* __restrict__ coarse, double w,
+__global__ __launch_bounds__(256) void p_prolong_cell_kernel(const PCellSeg* __restrict__ fine, const PCellSeg* __restrict__ coarse, double w,
                                       const T* __restrict__ e, T* __restrict__ x) {
   const PCellSeg fs = fine[blockIdx.y];
   const PCellSeg cs = coarse[blockIdx.y];
@@ -462,7 +550,7 @@ BT_INST_P(float)
 
 // ---- Dq^-1 ---------------------------------------------------------------------------------
 // Dq(q_e node) = sum over the cells sharing the node along e of eta/K_c h_e MC(a,a) prod_{f!=e} h_f/2
-__global__ void dq_kernel(const InstDev* __restrict__ insts, const double* __restrict__ kinv, double* __restrict__ dqinv) {
+__global__ __launch_bounds__(256) void dq_kernel(const InstDev* __restrict__ insts, const double* __restrict__ kinv, double* __restrict__ dqinv) {
   const InstDev& I = insts[blockIdx.y];
   const int d = I.dim;
   double* out = dqinv + I.state_off;

@@ -103,7 +103,7 @@ __device__ T ep_at(const InstDev& I, const T* P, int c, const int co[3]) {
 }
 
 template <typename T>
-__global__ void coupling_kernel(const InstDev* __restrict__ insts, const T* __restrict__ rt, const T* __restrict__ zp,
+__global__ __launch_bounds__(256) void coupling_kernel(const InstDev* __restrict__ insts, const T* __restrict__ rt, const T* __restrict__ zp,
                                 T* __restrict__ fu, T* __restrict__ fq) {
   const InstDev& I = insts[blockIdx.y];
   const int j = blockIdx.z;
@@ -175,7 +175,7 @@ __device__ __forceinline__ T mq_at(const InstDev& I, const T* kc, const T* X, in
 }
 
 template <typename T>
-__global__ void mq_kernel(const InstDev* __restrict__ insts, int mode, ChebCoef cc, const T* __restrict__ kinv,
+__global__ __launch_bounds__(256) void mq_kernel(const InstDev* __restrict__ insts, int mode, ChebCoef cc, const T* __restrict__ kinv,
                           const T* __restrict__ b, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ din,
                           T* __restrict__ dout) {
   const InstDev& I = insts[blockIdx.y];
@@ -228,7 +228,7 @@ template void launch_mq<float>(int, const InstDev*, int, int, long long, int, Ch
 
 // ---- finalize -----------------------------------------------------------------------------------
 template <typename T, int NL>
-__global__ void finalize_kernel(const InstDev* __restrict__ insts, Mat4 Q, const T* __restrict__ zt,
+__global__ __launch_bounds__(256) void finalize_kernel(const InstDev* __restrict__ insts, Mat4 Q, const T* __restrict__ zt,
                                 const T* __restrict__ r, T* __restrict__ z) {
   const InstDev& I = insts[blockIdx.y];
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < I.N; t += (long long)gridDim.x * blockDim.x) {

@@ -22,7 +22,7 @@ int uapply_tile(int dim) { return dim == 2 ? kUO : -1; }
 template <typename T>
 __global__ __launch_bounds__(256) void uapply2d_kernel(const UGridSeg* __restrict__ segs, const int4* __restrict__ work,
                                                        int mode, const T* __restrict__ X, const T* __restrict__ Bv,
-                                                       T* __restrict__ Y) {
+                                                       T* __restrict__ Y, const T* __restrict__ emat) {
   __shared__ T E[18][kUT * kUT];
   const int4 w = work[blockIdx.x];
   const UGridSeg& G = segs[w.x];
@@ -38,7 +38,6 @@ __global__ __launch_bounds__(256) void uapply2d_kernel(const UGridSeg* __restric
   const bool valid = (i >= 0) && (i < nx) && (jc >= 0) && (jc < ny);
   const int sux = G.su[0];
   const long long nu1 = (long long)G.su[0] * G.su[1];
-  const T hx = T(G.h[0]), hy = T(G.h[1]);
   T ux[3][3], uy[3][3];
 #pragma unroll
   for (int b = 0; b < 3; ++b)
@@ -49,16 +48,21 @@ __global__ __launch_bounds__(256) void uapply2d_kernel(const UGridSeg* __restric
       ux[b][a] = (valid && !ugrid_fixed(2, G.su, 0, mx, my, 0)) ? Xl[o] : T(0);
       uy[b][a] = (valid && !ugrid_fixed(2, G.su, 1, mx, my, 0)) ? Xl[nu1 + o] : T(0);
     }
-  const T pc[2][2] = {{0, 0}, {0, 0}};
-  T ox[3][3], oy[3][3];
-  elast2d<T>(ux, uy, pc, hx, hy, T(G.tau), T(0), T(G.lam), T(G.mu), ox, oy);
+  {
+    const T* AE = emat + G.emat_off;   // tau A_e of this level (18x18)
+    T uu[18];
 #pragma unroll
-  for (int b = 0; b < 3; ++b)
+    for (int b = 0; b < 3; ++b)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      E[b * 3 + a][tid] = ox[b][a];
-      E[9 + b * 3 + a][tid] = oy[b][a];
+      for (int a = 0; a < 3; ++a) { uu[b * 3 + a] = ux[b][a]; uu[9 + b * 3 + a] = uy[b][a]; }
+#pragma unroll
+    for (int rr = 0; rr < 18; ++rr) {
+      T acc = 0;
+#pragma unroll
+      for (int cc = 0; cc < 18; ++cc) acc += AE[rr * 18 + cc] * uu[cc];
+      E[rr][tid] = acc;
     }
+  }
   __syncthreads();
   const int mxe = (i0 + kUO >= nx) ? 2 * nx + 1 : 2 * i0 + 2 * kUO;
   const int mye = (j0 + kUO >= ny) ? 2 * ny + 1 : 2 * j0 + 2 * kUO;
@@ -91,21 +95,21 @@ __global__ __launch_bounds__(256) void uapply2d_kernel(const UGridSeg* __restric
 
 template <typename T>
 void launch_uapply(int dim, const UGridSeg* segs, const int4* work, int nwork, int nj, int mode, const T* x,
-                   const T* b, T* y, hipStream_t s) {
+                   const T* b, T* y, const T* emat, hipStream_t s) {
   if (dim == 2) {
-    hipLaunchKernelGGL((uapply2d_kernel<T>), dim3(nwork, nj), dim3(kUT, kUT), 0, s, segs, work, mode, x, b, y);
+    hipLaunchKernelGGL((uapply2d_kernel<T>), dim3(nwork, nj), dim3(kUT, kUT), 0, s, segs, work, mode, x, b, y, emat);
   } else {
     launch_uapply3d<T>(segs, work, nwork, nj, mode, x, b, y, s);
   }
 }
 template void launch_uapply<double>(int, const UGridSeg*, const int4*, int, int, int, const double*, const double*,
-                                    double*, hipStream_t);
+                                    double*, const double*, hipStream_t);
 template void launch_uapply<float>(int, const UGridSeg*, const int4*, int, int, int, const float*, const float*,
-                                   float*, hipStream_t);
+                                   float*, const float*, hipStream_t);
 
 // ---- restriction pass ------------------------------------------------------------------------
 template <typename T>
-__global__ void rpass_kernel(const RPass* __restrict__ segs, const double* __restrict__ tab, const T* __restrict__ in,
+__global__ __launch_bounds__(256) void rpass_kernel(const RPass* __restrict__ segs, const double* __restrict__ tab, const T* __restrict__ in,
                              T* __restrict__ out) {
   const RPass P = segs[blockIdx.y];
   const int j = blockIdx.z;
@@ -150,7 +154,7 @@ template void launch_rpass<float>(const RPass*, int, int, long long, const doubl
 
 // ---- prolongation: x_fine += P e_coarse ---------------------------------------------------------
 template <typename T>
-__global__ void uprolong_kernel(const UProl* __restrict__ segs, const double* __restrict__ tab,
+__global__ __launch_bounds__(256) void uprolong_kernel(const UProl* __restrict__ segs, const double* __restrict__ tab,
                                 const T* __restrict__ e, T* __restrict__ x) {
   const UProl P = segs[blockIdx.y];
   const int j = blockIdx.z;
@@ -201,7 +205,7 @@ template void launch_uprolong<float>(const UProl*, int, int, long long, const do
 
 // ---- y = Dinv x on level segments -------------------------------------------------------------------
 template <typename T>
-__global__ void muldinv_kernel(const LSeg* __restrict__ segs, const T* __restrict__ dinv, const T* __restrict__ x,
+__global__ __launch_bounds__(256) void muldinv_kernel(const LSeg* __restrict__ segs, const T* __restrict__ dinv, const T* __restrict__ x,
                                T* __restrict__ y) {
   const LSeg sg = segs[blockIdx.y];
   const long long off = sg.off + blockIdx.z * sg.jstride, doff = sg.doff + blockIdx.z * sg.djstride;

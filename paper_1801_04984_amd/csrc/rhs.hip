@@ -47,7 +47,7 @@ __device__ void divu_cell(const InstDev& I, const double* S, int i, int j, int k
   }
 }
 
-__global__ void rhs_kernel(const InstDev* __restrict__ insts, TimeMat tm, int nl, double t_start,
+__global__ __launch_bounds__(256) void rhs_kernel(const InstDev* __restrict__ insts, TimeMat tm, int nl, double t_start,
                            const double* __restrict__ state, double* __restrict__ rhs) {
   const InstDev& I = insts[blockIdx.y];
   const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -104,7 +104,7 @@ void launch_rhs(const InstDev* d_inst, int count, long long max_cells, const Tim
 namespace bt {
 
 // x_l = state for every time level l (initial guess of a slab)
-__global__ void bcast_kernel(const InstDev* __restrict__ insts, int nl, const double* __restrict__ state,
+__global__ __launch_bounds__(256) void bcast_kernel(const InstDev* __restrict__ insts, int nl, const double* __restrict__ state,
                              double* __restrict__ x) {
   const InstDev& I = insts[blockIdx.y];
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < I.N; t += (long long)gridDim.x * blockDim.x) {
@@ -113,7 +113,7 @@ __global__ void bcast_kernel(const InstDev* __restrict__ insts, int nl, const do
   }
 }
 // state = level `lev` of x
-__global__ void extract_kernel(const InstDev* __restrict__ insts, int lev, const double* __restrict__ x,
+__global__ __launch_bounds__(256) void extract_kernel(const InstDev* __restrict__ insts, int lev, const double* __restrict__ x,
                                double* __restrict__ state) {
   const InstDev& I = insts[blockIdx.y];
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < I.N; t += (long long)gridDim.x * blockDim.x)
@@ -132,7 +132,7 @@ void launch_extract(const InstDev* insts, int count, long long maxN, int lev, co
 }
 
 // sensor residuals: res[k][s] = sum_g w_g p_g (level `lev` of X) - obs[k][s]
-__global__ void sensor_kernel(const InstDev* __restrict__ insts, int lev, int nsens, const SensorW* __restrict__ sw,
+__global__ __launch_bounds__(256) void sensor_kernel(const InstDev* __restrict__ insts, int lev, int nsens, const SensorW* __restrict__ sw,
                               const double* __restrict__ X, const double* __restrict__ obs, double* __restrict__ res) {
   const int k = blockIdx.y;
   const InstDev& I = insts[k];
@@ -154,7 +154,7 @@ void launch_sensor(const InstDev* insts, int count, int lev, int nsens, const Se
 //                    - (1/M) w_p c_p
 //   level r u-rows:  - b E c_p   (free rows)
 // with c_p = sum_i g_i lam_next_i (p-block), the transpose of the dG jump coupling.
-__global__ void adjrhs_jump_kernel(const InstDev* __restrict__ insts, TimeMat tm, int nl, int has_next,
+__global__ __launch_bounds__(256) void adjrhs_jump_kernel(const InstDev* __restrict__ insts, TimeMat tm, int nl, int has_next,
                                    const double* __restrict__ lam_next, double* __restrict__ a) {
   const InstDev& I = insts[blockIdx.y];
   const int d = I.dim;
@@ -213,7 +213,7 @@ __global__ void adjrhs_jump_kernel(const InstDev* __restrict__ insts, TimeMat tm
     a[lo + t] = v;
   }
 }
-__global__ void adjrhs_sensor_kernel(const InstDev* __restrict__ insts, int nl, int nsens, const SensorW* __restrict__ sw,
+__global__ __launch_bounds__(256) void adjrhs_sensor_kernel(const InstDev* __restrict__ insts, int nl, int nsens, const SensorW* __restrict__ sw,
                                      const double* __restrict__ res, double* __restrict__ a) {
   const int k = blockIdx.x;
   const InstDev& I = insts[k];
@@ -235,7 +235,7 @@ void launch_adjrhs(const InstDev* insts, int count, long long maxN, const TimeMa
 }
 
 // grad_c += tau eta/K_c sum_i lam_i^T Mq1_c X_i  (free flux DoFs), K == 1 flux mass Mq1
-__global__ void grad_kernel(const InstDev* __restrict__ insts, int nl, const double* __restrict__ kinv,
+__global__ __launch_bounds__(256) void grad_kernel(const InstDev* __restrict__ insts, int nl, const double* __restrict__ kinv,
                             const double* __restrict__ lam, const double* __restrict__ X, double* __restrict__ grad) {
   const InstDev& I = insts[blockIdx.y];
   const int d = I.dim;

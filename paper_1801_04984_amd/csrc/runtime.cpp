@@ -3,10 +3,12 @@
 // solver.cpp.
 #include "runtime.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <sstream>
 
+#include "element.h"
 #include "kernels.h"
 #include "solver.h"
 
@@ -85,9 +87,11 @@ static void plan_layout(biot_problem_s* h, Layout& L, bool carve) {
   auto* kinv64 = L.take<double>(h->ncells);
   auto* kinv32 = L.take<float>(h->ncells);
   auto* theta = L.take<double>(h->ncells);
+  auto* em64 = L.take<double>(std::max(1LL, h->emat_len));
+  auto* em32 = L.take<float>(std::max(1LL, h->emat_len));
   if (carve) {
     h->d_inst = d_inst; h->d_work_apply = d_work; h->d_kinv64 = kinv64; h->d_kinv32 = kinv32;
-    h->d_theta = theta;
+    h->d_theta = theta; h->d_emat64 = em64; h->d_emat32 = em32;
   }
   plan_solver_layout(h, L, carve);
 }
@@ -103,9 +107,11 @@ static void build_host_state(biot_problem_s* h, const biot_problem_desc* descs, 
   for (int k = 0; k < count; ++k) {
     InstDev I = make_inst(descs[k]);
     I.x_off = xo; I.state_off = so; I.cell_off = co;
+    I.emat_off = descs[0].dim == 2 ? (long long)k * (18 * 18 + 18 * 4) : 0;
     xo += I.N * h->nl; so += I.N; co += I.ncells;
     h->inst.push_back(I);
   }
+  h->emat_len = descs[0].dim == 2 ? (long long)count * (18 * 18 + 18 * 4) : 0;
   h->slab_len = xo; h->state_len = so; h->ncells = co;
   // apply work list
   int nw = 0;
@@ -182,6 +188,7 @@ ApplyArgs apply_args(const biot_problem_s* h, int dtype, hipStream_t s) {
   a.nl = h->nl;
   a.tm = &h->tm;
   a.kinv = dtype ? (const void*)h->d_kinv32 : (const void*)h->d_kinv64;
+  a.emat = dtype ? (const void*)h->d_emat32 : (const void*)h->d_emat64;
   a.stream = s;
   return a;
 }
@@ -270,6 +277,22 @@ biot_status create_slab_problem(const biot_problem_desc* descs, int32_t count, c
     hip_check(hipMemcpyAsync(h->d_work_apply, w.data(), sizeof(int4) * w.size(), hipMemcpyHostToDevice, s),
               "upload work list");
     upload_log_k(h, log_k, s);
+    if (h->emat_len > 0) {
+      std::vector<double> em(h->emat_len);
+      std::vector<float> em32(h->emat_len);
+      for (int k = 0; k < h->count; ++k) {
+        const auto& D = h->descs[k];
+        const double hh[3] = {h->inst[k].h[0], h->inst[k].h[1], h->inst[k].h[2]};
+        auto A = elast_element(2, hh, D.lambda, D.mu, D.tau);
+        auto E = coupling_element(2, hh);
+        std::copy(A.begin(), A.end(), em.begin() + h->inst[k].emat_off);
+        std::copy(E.begin(), E.end(), em.begin() + h->inst[k].emat_off + 18 * 18);
+      }
+      for (long long q = 0; q < h->emat_len; ++q) em32[q] = (float)em[q];
+      hip_check(hipMemcpyAsync(h->d_emat64, em.data(), 8 * em.size(), hipMemcpyHostToDevice, s), "emat");
+      hip_check(hipMemcpyAsync(h->d_emat32, em32.data(), 4 * em32.size(), hipMemcpyHostToDevice, s), "emat");
+      hip_check(hipStreamSynchronize(s), "emat sync");
+    }
     setup_solver(h, s);
     hip_check(hipStreamSynchronize(s), "create sync");
     *out = h;

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "element.h"
 #include "kernels_aux.h"
 #include "prec.h"
 #include "vec.h"
@@ -27,7 +28,6 @@
 namespace bt {
 
 constexpr int kMaxRestart = 64;
-constexpr int kNChunk = 96;
 constexpr double kOmegaP = 1.6;          // coarse-correction over-relaxation of the aggregation multigrid
 constexpr int kPDeg = 3;                 // Chebyshev smoothing degree, pressure levels
 constexpr double kPLo = 1.0 / 8.0, kPHi = 1.1;
@@ -81,6 +81,9 @@ struct PrecData {
   LSeg* d_ul0c = nullptr;
   std::vector<double> utab_h;
   double* d_utab = nullptr;
+  long long uemat_len = 0;
+  double* d_uemat64 = nullptr;
+  float* d_uemat32 = nullptr;
   // coarse dense solves
   std::vector<DSeg> ud, pd;
   DSeg *d_ud = nullptr, *d_pd = nullptr;
@@ -105,10 +108,16 @@ struct PrecData {
 
 template <typename T>
 PrecBufs<T>& bufs(PrecData* P);
+template <typename T>
+const T* uemat(PrecData* P);
 template <>
 PrecBufs<double>& bufs<double>(PrecData* P) { return P->b64; }
 template <>
 PrecBufs<float>& bufs<float>(PrecData* P) { return P->b32; }
+template <>
+const double* uemat<double>(PrecData* P) { return P->d_uemat64; }
+template <>
+const float* uemat<float>(PrecData* P) { return P->d_uemat32; }
 
 // ---------------------------------------------------------------------------
 // hierarchy description (host), identical for sizing and carving
@@ -202,6 +211,7 @@ static void build_hierarchy(biot_problem_s* h, PrecData* P) {
   P->ug0c.clear(); P->ul0c.clear();
   int level = 0;
   long long dinv_off = 0;
+  long long uemat_off = 0;
   std::vector<long long> dinv_base;
   while (true) {
     std::vector<UGridSeg> lev;
@@ -219,6 +229,8 @@ static void build_hierarchy(biot_problem_s* h, PrecData* P) {
       }
       g.tau = D.tau; g.lam = D.lambda; g.mu = D.mu;
       g.nu = (long long)d * g.su[0] * g.su[1] * g.su[2];
+      g.emat_off = d == 2 ? uemat_off : 0;
+      if (d == 2) uemat_off += 18 * 18;
       g.doff = dinv_off + lvtot;
       if (level == 0) { g.voff = h->inst[k].x_off + h->inst[k].off_u[0]; g.vjstride = h->inst[k].N; }
       else { g.voff = voff; g.vjstride = g.nu; voff += nl * g.nu; }
@@ -249,6 +261,7 @@ static void build_hierarchy(biot_problem_s* h, PrecData* P) {
       for (int e = 0; e < d; ++e) n[k][e] = half(n[k][e]);
   }
   P->nul = (int)P->ug.size();
+  P->uemat_len = uemat_off;
   // work lists per u level
   P->uwork.assign(P->nul, {});
   const int t = uapply_tile(d);
@@ -439,13 +452,15 @@ void plan_solver_layout(biot_problem_s* h, Layout& L, bool carve) {
     P->d_up[l] = L.take<UProl>(P->up[l].size());
   }
   P->d_utab = L.take<double>(std::max<size_t>(1, P->utab_h.size()));
+  P->d_uemat64 = L.take<double>(std::max(1LL, P->uemat_len));
+  P->d_uemat32 = L.take<float>(std::max(1LL, P->uemat_len));
   P->d_ud = L.take<DSeg>(P->ud.size());
   P->d_pd = L.take<DSeg>(P->pd.size());
   P->uAinv = L.take<double>(P->uAinv_len);
   P->pAinv = L.take<double>(P->pAinv_len);
   P->d_gseg = L.take<VSeg>(P->gseg.size());
   const size_t nsc = (size_t)std::max(h->count * h->nl, h->count) * 64;
-  P->partial = L.take<double>((size_t)std::max(h->count * h->nl, h->count) * kNChunk * 64);
+  P->partial = L.take<double>((size_t)std::max(h->count * h->nl, h->count) * kMaxChunks * 64);
   P->dot1 = L.take<double>(nsc); P->dot2 = L.take<double>(nsc); P->dot3 = L.take<double>(nsc);
   P->coef = L.take<double>(nsc); P->scal = L.take<double>(nsc);
   P->lam = L.take<double>(h->slab_len);
@@ -495,40 +510,6 @@ static void invert_dense(std::vector<double>& A, int n) {
     }
   }
   A.swap(I);
-}
-
-// tau * Q2 elasticity element matrix on a cell of size h (local order [comp][node, x fastest])
-static std::vector<double> elast_element(int d, const double* hh, double lam, double mu, double tau) {
-  const int nn = d == 2 ? 9 : 27, nloc = d * nn;
-  std::vector<double> K((size_t)nloc * nloc, 0.0);
-  const int nq = d == 2 ? 9 : 27;
-  for (int q = 0; q < nq; ++q) {
-    const int kq[3] = {q % 3, (q / 3) % 3, d == 3 ? q / 9 : 0};
-    double W = 1.0;
-    for (int e = 0; e < d; ++e) W *= wq(kq[e]) * hh[e];
-    // gradients of the scalar nodal functions at q
-    std::vector<std::array<double, 3>> g(nn);
-    for (int a = 0; a < nn; ++a) {
-      const int aa[3] = {a % 3, (a / 3) % 3, d == 3 ? a / 9 : 0};
-      for (int e = 0; e < d; ++e) {
-        double v = 1.0;
-        for (int f = 0; f < d; ++f) v *= (f == e) ? dphi(aa[f], xq(kq[f])) / hh[f] : phi(aa[f], xq(kq[f]));
-        g[a][e] = v;
-      }
-    }
-    for (int c = 0; c < d; ++c)
-      for (int a = 0; a < nn; ++a)
-        for (int c2 = 0; c2 < d; ++c2)
-          for (int b = 0; b < nn; ++b) {
-            // a(u,v): v = phi_a e_c (test), u = phi_b e_c2 (trial)
-            double val = lam * g[a][c] * g[b][c2];
-            val += mu * g[a][c2] * g[b][c];
-            if (c == c2)
-              for (int e = 0; e < d; ++e) val += mu * g[a][e] * g[b][e];
-            K[(size_t)(c * nn + a) * nloc + (c2 * nn + b)] += tau * W * val;
-          }
-  }
-  return K;
 }
 
 static std::vector<double> coarse_elast_inverse(const UGridSeg& g) {
@@ -760,6 +741,18 @@ static void setup_elasticity(biot_problem_s* h, hipStream_t s) {
   PrecData* P = h->prec;
   auto& B = P->b64;
   const int cnt = h->count, d = h->dim;
+  if (d == 2) {
+    std::vector<double> em(P->uemat_len);
+    for (int l = 0; l < P->nul; ++l)
+      for (int k = 0; k < cnt; ++k) {
+        const UGridSeg& g = P->ug[l][k];
+        auto A = elast_element(2, g.h, g.lam, g.mu, g.tau);
+        std::copy(A.begin(), A.end(), em.begin() + g.emat_off);
+      }
+    upload(em, P->d_uemat64, s);
+    std::vector<float> e32(em.begin(), em.end());
+    upload(e32, P->d_uemat32, s);
+  }
   // diagonals (host), all levels into one array
   long long dtot = 0;
   for (int l = 0; l < P->nul; ++l) dtot += P->u_total[l];
@@ -787,7 +780,7 @@ static void setup_elasticity(biot_problem_s* h, hipStream_t s) {
     const int nwork = (int)P->uwork[l].size();
     const long long mx = P->u_max[l];
     auto apply = [&](double* xx, double* yy) {
-      launch_uapply<double>(d, dseg, work, nwork, 1, 0, xx, nullptr, yy, s);
+      launch_uapply<double>(d, dseg, work, nwork, 1, 0, xx, nullptr, yy, P->d_uemat64, s);
       launch_mul_dinv<double>(dls, cnt, 1, mx, B.u_dinv[0], yy, yy, s);
     };
     auto lam = power_max(P, apply, x, y, segs, P->u_total[l], s);
@@ -923,7 +916,7 @@ static void u_vcycle(biot_problem_s* h, int l, T* x, const T* b, T* r, T* d0, T*
   // pre-smoothing from x = 0
   cheb_update<T>(ls, cnt, nl, mx, 2, 0.0, cs.s0, x, r, d0, nullptr, dinv, b, s);
   for (int k = 0; k < kUDeg; ++k) {
-    launch_uapply<T>(d, gs, work, nwork, nl, 0, d0, nullptr, y, s);
+    launch_uapply<T>(d, gs, work, nwork, nl, 0, d0, nullptr, y, uemat<T>(P), s);
     cheb_update<T>(ls, cnt, nl, mx, 1, cs.steps[k].first, cs.steps[k].second, x, r, d0, y, dinv, nullptr, s);
   }
   // restriction of r
@@ -936,10 +929,10 @@ static void u_vcycle(biot_problem_s* h, int l, T* x, const T* b, T* r, T* d0, T*
   u_vcycle<T>(h, l + 1, B.u_x[l + 1], B.u_b[l + 1], B.u_r[l + 1], B.u_d0[l + 1], B.u_y[l + 1], s);
   launch_uprolong<T>(P->d_up[l], cnt, nl, mx, P->d_utab, B.u_x[l + 1], x, s);
   // post-smoothing
-  launch_uapply<T>(d, gs, work, nwork, nl, 1, x, b, r, s);
+  launch_uapply<T>(d, gs, work, nwork, nl, 1, x, b, r, uemat<T>(P), s);
   cheb_update<T>(ls, cnt, nl, mx, 0, 0.0, cs.s0, x, r, d0, nullptr, dinv, nullptr, s);
   for (int k = 0; k < kUDeg; ++k) {
-    launch_uapply<T>(d, gs, work, nwork, nl, 0, d0, nullptr, y, s);
+    launch_uapply<T>(d, gs, work, nwork, nl, 0, d0, nullptr, y, uemat<T>(P), s);
     cheb_update<T>(ls, cnt, nl, mx, 1, cs.steps[k].first, cs.steps[k].second, x, r, d0, y, dinv, nullptr, s);
   }
 }
@@ -987,7 +980,7 @@ static void residual(biot_problem_s* h, const T* b, const T* x, T* r, int transp
 
 template <typename T>
 static void seg_norms(PrecData* P, const T* v, int cnt, hipStream_t s, std::vector<double>& out) {
-  seg_mdot<T, T>(v, 0, 1, v, P->d_gseg, cnt, kNChunk, P->partial, P->dot3, s);
+  seg_mdot<T, T>(v, 0, 1, v, P->d_gseg, cnt, dot_chunks(P->gmax), P->partial, P->dot3, s);
   std::vector<double> tmp(cnt * 64);
   hip_check(hipMemcpyAsync(tmp.data(), P->dot3, 8 * cnt * 64, hipMemcpyDeviceToHost, s), "norm read");
   hip_check(hipStreamSynchronize(s), "norm sync");
@@ -1039,11 +1032,11 @@ static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const Solv
       T* vn = B.V + (long long)(jj + 1) * S;
       apply_prec<T>(h, vj, B.t, ctl.qdeg, s);
       launch_apply(h, B.t, vn, transpose, std::is_same<T, float>::value ? 1 : 0, s);
-      seg_mdot<T, T>(B.V, S, jj + 1, vn, P->d_gseg, cnt, kNChunk, P->partial, P->dot1, s);
+      seg_mdot<T, T>(B.V, S, jj + 1, vn, P->d_gseg, cnt, dot_chunks(P->gmax), P->partial, P->dot1, s);
       seg_maxpy<T, T>(B.V, S, jj + 1, P->dot1, -1.0, vn, P->d_gseg, cnt, P->gmax, s);
-      seg_mdot<T, T>(B.V, S, jj + 1, vn, P->d_gseg, cnt, kNChunk, P->partial, P->dot2, s);
+      seg_mdot<T, T>(B.V, S, jj + 1, vn, P->d_gseg, cnt, dot_chunks(P->gmax), P->partial, P->dot2, s);
       seg_maxpy<T, T>(B.V, S, jj + 1, P->dot2, -1.0, vn, P->d_gseg, cnt, P->gmax, s);
-      seg_mdot<T, T>(vn, 0, 1, vn, P->d_gseg, cnt, kNChunk, P->partial, P->dot3, s);
+      seg_mdot<T, T>(vn, 0, 1, vn, P->d_gseg, cnt, dot_chunks(P->gmax), P->partial, P->dot3, s);
       hip_check(hipMemcpyAsync(h1.data(), P->dot1, 8 * cnt * 64, hipMemcpyDeviceToHost, s), "h read");
       hip_check(hipMemcpyAsync(h2.data(), P->dot2, 8 * cnt * 64, hipMemcpyDeviceToHost, s), "h read");
       hip_check(hipMemcpyAsync(hn.data(), P->dot3, 8 * cnt * 64, hipMemcpyDeviceToHost, s), "h read");

@@ -19,6 +19,9 @@ struct DSeg {          // dense coarse solve segment
 };
 struct Mat4 { double m[16]; };
 
+constexpr int kMaxChunks = 2048;  // dot-product partial sums per segment (upper bound)
+int dot_chunks(long long maxlen);
+
 template <typename T> void vfill(T* x, T v, long long n, hipStream_t s);
 void vcast(const double* x, float* y, long long n, hipStream_t s);
 void vcast(const float* x, double* y, long long n, hipStream_t s);

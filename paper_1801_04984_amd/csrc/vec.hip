@@ -8,12 +8,12 @@ namespace bt {
 
 // ---- fill / copy / cast ------------------------------------------------------
 template <typename T>
-__global__ void fill_kernel(T* __restrict__ x, T v, long long n) {
+__global__ __launch_bounds__(256) void fill_kernel(T* __restrict__ x, T v, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     x[i] = v;
 }
 template <typename A, typename B>
-__global__ void cast_kernel(const A* __restrict__ x, B* __restrict__ y, long long n) {
+__global__ __launch_bounds__(256) void cast_kernel(const A* __restrict__ x, B* __restrict__ y, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     y[i] = (B)x[i];
 }
@@ -36,7 +36,7 @@ void vcast(const float* x, double* y, long long n, hipStream_t s) {
 
 // ---- y = a x + b y over whole vectors ---------------------------------------------
 template <typename T>
-__global__ void axpby_kernel(T a, const T* __restrict__ x, T b, T* __restrict__ y, long long n) {
+__global__ __launch_bounds__(256) void axpby_kernel(T a, const T* __restrict__ x, T b, T* __restrict__ y, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     y[i] = a * x[i] + b * y[i];
 }
@@ -47,7 +47,7 @@ void vaxpby(double a, const T* x, double b, T* y, long long n, hipStream_t s) {
 template void vaxpby<double>(double, const double*, double, double*, long long, hipStream_t);
 template void vaxpby<float>(double, const float*, double, float*, long long, hipStream_t);
 // y += x (mixed precision accumulate: double += float)
-__global__ void acc_f32_kernel(const float* __restrict__ x, double* __restrict__ y, long long n) {
+__global__ __launch_bounds__(256) void acc_f32_kernel(const float* __restrict__ x, double* __restrict__ y, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     y[i] += (double)x[i];
 }
@@ -89,17 +89,26 @@ __global__ __launch_bounds__(kDotThreads) void mdot_stage1(const TV* __restrict_
   if (threadIdx.x < kKB && threadIdx.x < nk) {
     double v = 0.0;
     for (int q = 0; q < kDotThreads / 64; ++q) v += red[threadIdx.x][q];
-    partial[((long long)blockIdx.y * nchunk + chunk) * 64 + k0 + threadIdx.x] = v;
+    partial[((long long)blockIdx.y * 64 + k0 + threadIdx.x) * nchunk + chunk] = v;
   }
 }
-__global__ void mdot_stage2(const double* __restrict__ partial, int nseg, int nchunk, int nk,
-                            double* __restrict__ out) {
-  const int s = blockIdx.x;
-  const int k = threadIdx.x;
-  if (k >= nk) return;
+// stage 2: one block per (vector k, segment); fixed-order tree over the chunk partials
+__global__ __launch_bounds__(256) void mdot_stage2(const double* __restrict__ partial, int nchunk,
+                                                   double* __restrict__ out) {
+  const int k = blockIdx.x, s = blockIdx.y;
+  const double* p = partial + ((long long)s * 64 + k) * nchunk;
   double v = 0.0;
-  for (int c = 0; c < nchunk; ++c) v += partial[((long long)s * nchunk + c) * 64 + k];
-  out[s * 64 + k] = v;
+  for (int c = threadIdx.x; c < nchunk; c += 256) v += p[c];
+  __shared__ double red[4];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) out[s * 64 + k] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+int dot_chunks(long long maxlen) {
+  long long c = (maxlen + 1023) / 1024;
+  return (int)(c < 1 ? 1 : (c > kMaxChunks ? kMaxChunks : c));
 }
 
 template <typename TV, typename TW>
@@ -110,7 +119,7 @@ void seg_mdot(const TV* V, long long ldv, int nk, const TW* w, const VSeg* segs,
     hipLaunchKernelGGL((mdot_stage1<TV, TW>), dim3(nchunk, nseg), dim3(kDotThreads), 0, s, V, ldv, k0, kk, w, segs,
                        nchunk, partial);
   }
-  hipLaunchKernelGGL(mdot_stage2, dim3(nseg), dim3(64), 0, s, partial, nseg, nchunk, nk, out);
+  hipLaunchKernelGGL(mdot_stage2, dim3(nk, nseg), dim3(256), 0, s, partial, nchunk, out);
 }
 template void seg_mdot<double, double>(const double*, long long, int, const double*, const VSeg*, int, int, double*,
                                        double*, hipStream_t);
@@ -119,7 +128,7 @@ template void seg_mdot<float, float>(const float*, long long, int, const float*,
 
 // ---- segmented multi-axpy: w[seg] += sum_k c[seg][k] V_k[seg] -----------------
 template <typename TV, typename TW>
-__global__ void maxpy_kernel(const TV* __restrict__ V, long long ldv, int nk, const double* __restrict__ c,
+__global__ __launch_bounds__(256) void maxpy_kernel(const TV* __restrict__ V, long long ldv, int nk, const double* __restrict__ c,
                              double csign, TW* __restrict__ w, const VSeg* __restrict__ segs) {
   const VSeg sg = segs[blockIdx.y];
   const double* cs = c + blockIdx.y * 64;
@@ -144,7 +153,7 @@ template void seg_maxpy<float, float>(const float*, long long, int, const double
 
 // ---- segmented scale: y[seg] = s[seg*64 + idx] * x[seg] (idx-th coefficient) ----------
 template <typename TX, typename TY>
-__global__ void sscale_kernel(const TX* __restrict__ x, TY* __restrict__ y, const double* __restrict__ sc, int idx,
+__global__ __launch_bounds__(256) void sscale_kernel(const TX* __restrict__ x, TY* __restrict__ y, const double* __restrict__ sc, int idx,
                               int inv, const VSeg* __restrict__ segs) {
   const VSeg sg = segs[blockIdx.y];
   double f = sc[blockIdx.y * 64 + idx];
@@ -170,7 +179,7 @@ template void seg_scale<double, float>(const double*, float*, const double*, int
 
 // ---- time transform: y_i = sum_j M_ij x_j per spatial DoF (all instances) -----
 template <typename T, int NL>
-__global__ void ttrans_kernel(const InstDev* __restrict__ insts, const T* __restrict__ x, T* __restrict__ y, Mat4 M) {
+__global__ __launch_bounds__(256) void ttrans_kernel(const InstDev* __restrict__ insts, const T* __restrict__ x, T* __restrict__ y, Mat4 M) {
   const InstDev& I = insts[blockIdx.y];
   for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < I.N; k += (long long)gridDim.x * blockDim.x) {
     T v[NL];
@@ -206,7 +215,7 @@ template void time_transform<float>(const InstDev*, int, long long, int, const M
 // x += d; r -= y; d = rho d + sig Dinv r      (y = A d computed by the caller)
 // first step (init != 0): r = b - y0 is not touched; d = sig Dinv r; x untouched.
 template <typename T>
-__global__ void cheb_kernel(const LSeg* __restrict__ segs, int mode, double rho, double sig, T* __restrict__ x,
+__global__ __launch_bounds__(256) void cheb_kernel(const LSeg* __restrict__ segs, int mode, double rho, double sig, T* __restrict__ x,
                             T* __restrict__ r, T* __restrict__ d, const T* __restrict__ y,
                             const T* __restrict__ dinv, const T* __restrict__ b) {
   const LSeg sg = segs[blockIdx.y];
@@ -233,7 +242,7 @@ __global__ void cheb_kernel(const LSeg* __restrict__ segs, int mode, double rho,
 }
 // final: x += d
 template <typename T>
-__global__ void addseg_kernel(const LSeg* __restrict__ segs, const T* __restrict__ d, T* __restrict__ x, double a) {
+__global__ __launch_bounds__(256) void addseg_kernel(const LSeg* __restrict__ segs, const T* __restrict__ d, T* __restrict__ x, double a) {
   const LSeg sg = segs[blockIdx.y];
   const long long off = sg.off + blockIdx.z * sg.jstride;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < sg.len;
@@ -263,7 +272,7 @@ template void seg_add<float>(const LSeg*, int, int, long long, const float*, flo
 
 // zero a level segment set
 template <typename T>
-__global__ void zseg_kernel(const LSeg* __restrict__ segs, T* __restrict__ x) {
+__global__ __launch_bounds__(256) void zseg_kernel(const LSeg* __restrict__ segs, T* __restrict__ x) {
   const LSeg sg = segs[blockIdx.y];
   const long long off = sg.off + blockIdx.z * sg.jstride;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < sg.len;
