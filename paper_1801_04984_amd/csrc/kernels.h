@@ -13,6 +13,9 @@ struct ApplyArgs {
   const TimeMat* tm;     // host copy, passed by value to kernels
   const void* kinv;      // device per-cell eta/K (double or float, matching dtype)
   const void* emat;      // device element matrices (2D), matching dtype
+  int count;             // instances
+  long long maxN;        // largest spatial level size
+  long long maxc;        // largest cell count
   hipStream_t stream;
 };
 

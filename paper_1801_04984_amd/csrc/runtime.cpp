@@ -189,6 +189,10 @@ ApplyArgs apply_args(const biot_problem_s* h, int dtype, hipStream_t s) {
   a.tm = &h->tm;
   a.kinv = dtype ? (const void*)h->d_kinv32 : (const void*)h->d_kinv64;
   a.emat = dtype ? (const void*)h->d_emat32 : (const void*)h->d_emat64;
+  a.count = h->count;
+  a.maxN = 0;
+  a.maxc = 0;
+  for (auto& I : h->inst) { a.maxN = std::max(a.maxN, I.N); a.maxc = std::max(a.maxc, I.ncells); }
   a.stream = s;
   return a;
 }

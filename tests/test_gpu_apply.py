@@ -71,3 +71,36 @@ def test_slab_rhs_2d(r):
         ref = prob.rhs(t0, state)
         assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
     h.close()
+
+
+SHAPES_3D = [(1, 1, 1), (2, 3, 2), (9, 8, 10), (15, 7, 9)]
+
+
+@pytest.mark.parametrize("n", SHAPES_3D)
+@pytest.mark.parametrize("r", [0, 1, 2])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_apply3d_fp64(n, r, transpose):
+    torch = torch_cuda()
+    _check_apply([small_workload(3, n, r, seed=7 + r)], torch.float64, transpose)
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_apply3d_fp32_and_batched(transpose):
+    torch = torch_cuda()
+    wls = [small_workload(3, n, 1, seed=30 + i) for i, n in enumerate([(3, 3, 3), (9, 8, 10)])]
+    _check_apply(wls, torch.float32, transpose)
+    _check_apply(wls, torch.float64, transpose)
+
+
+@pytest.mark.parametrize("r", [0, 2])
+def test_slab_rhs_3d(r):
+    torch = torch_cuda()
+    wl = small_workload(3, (5, 4, 6), r, seed=2)
+    h, (prob,) = make_pair([wl])
+    state = np.random.default_rng(4).standard_normal(prob.N)
+    state[prob.mask] = 0.0
+    for t0 in (0.0, 0.31):
+        got = h.rhs(torch.tensor(state, device="cuda"), t0).cpu().numpy()
+        ref = prob.rhs(t0, state)
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    h.close()

@@ -167,3 +167,50 @@ def test_adjoint_gradient_matches_oracle(r):
     gv = g.cpu().numpy()
     assert np.linalg.norm(gv - gref) <= 1e-8 * np.linalg.norm(gref), (np.abs(gv - gref).max(), np.abs(gref).max())
     h.close()
+
+
+@pytest.mark.parametrize("n,r", [((4, 4, 4), 1), ((9, 7, 8), 1), ((5, 5, 5), 2)])
+def test_solve3d_fp64_and_mixed(n, r):
+    torch = torch_cuda()
+    wl = small_workload(3, n, r, seed=70 + r)
+    h, (prob,) = make_pair([wl])
+    b = _rhs(prob, seed=3)
+    ref = prob.solve(b)
+    x, info, st = h.solve(torch.tensor(b, device="cuda"), rtol=RT)
+    assert st == 0 and info[0]["iterations"] < 150, info
+    err = field_rel(prob, x.cpu().numpy(), ref)
+    assert max(err.values()) < TOL, err
+    x, info, st = h.solve(torch.tensor(b, device="cuda"), precision=1)
+    assert st == 0, info
+    err = field_rel(prob, x.cpu().numpy(), ref)
+    assert max(err.values()) < TOL, err
+    h.close()
+
+
+def test_step3d_and_adjoint():
+    torch = torch_cuda()
+    from oracle import adjoint, fe
+    wl = small_workload(3, (4, 3, 4), 1, seed=81, load_kind=W.LOAD_RAMP)
+    theta = wl.log_k()
+    h, (prob,) = make_pair([wl], [theta])
+    ns = 2
+    ref = prob.march(ns)
+    state = h.zeros_state()
+    slabs = torch.zeros(ns * h.slab_len, dtype=torch.float64, device="cuda")
+    chk = torch.zeros(ns * h.state_len, dtype=torch.float64, device="cuda")
+    infos, st = h.step(ns, 0.0, state, slabs_out=slabs, checkpoints=chk)
+    assert st == 0
+    sv = slabs.cpu().numpy().reshape(ns, -1)
+    for k in range(ns):
+        err = field_rel(prob, sv[k], ref[k])
+        assert max(err.values()) < TOL, err
+    sens = W.sensors(5, 3, 91)
+    P = fe.pressure_point_matrix(prob.mesh, sens)
+    p_obs = 0.05 * np.random.default_rng(5).standard_normal((ns, len(sens)))
+    Jref, gref, _ = adjoint.gradient(prob, ns, P, p_obs)
+    J, g, st = h.adjoint(ns, 0.0, chk, sens, torch.tensor(p_obs.reshape(-1), device="cuda"))
+    assert st == 0
+    assert abs(J[0] - Jref) <= 1e-9 * abs(Jref)
+    gv = g.cpu().numpy()
+    assert np.linalg.norm(gv - gref) <= 1e-8 * np.linalg.norm(gref)
+    h.close()
