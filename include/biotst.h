@@ -95,7 +95,9 @@ typedef struct {
   int32_t precision;    /* biot_precision                                [FP64]   */
   double inner_rtol;    /* mixed: inner FP32 solve tolerance              [1e-5]   */
   int32_t max_refine;   /* mixed: outer refinement sweeps                   [20]   */
-  int32_t cheb_degree;  /* Chebyshev degree of the pressure/flux blocks     [8]    */
+  int32_t cheb_degree;  /* Chebyshev degree of the flux-mass block          [8]    */
+  int32_t graph;        /* 1: replay the preconditioner as a captured      [1]
+                           hipGraph (captured on first use); 0: eager     */
 } biot_solve_opts;
 
 typedef struct {
@@ -175,6 +177,15 @@ biot_status adjoint_sweep(biot_problem h, int32_t nslabs, double t_start,
                           const double* checkpoints, const double* sensors_xyz,
                           int32_t nsens, const double* p_obs, const biot_solve_opts* opts,
                           double* J, double* grad_log_k, void* stream);
+
+/* Pressure misfit of a forward march: J[k] = 1/2 sum_n sum_s (p_h(x_s) - p_obs)^2
+ * with p_h the DG-Q1 pressure of the state after slab n (end of slab n, the
+ * last Radau level).  states: device, nslabs states (one spatial level per
+ * instance each, e.g. the checkpoints written by step shifted by one slab plus
+ * the final state, stored contiguously); sensors_xyz: host, nsens * dim;
+ * p_obs: device, count * nslabs * nsens (instance-major); J: host, count. */
+biot_status biot_misfit(biot_problem h, int32_t nslabs, const double* states, const double* sensors_xyz,
+                        int32_t nsens, const double* p_obs, double* J, void* stream);
 
 /* Thread-local message describing the last non-OK status. */
 const char* biot_last_error(void);

@@ -48,6 +48,7 @@ struct PrecBufs {
   std::vector<T*> u_x, u_b, u_r, u_d0, u_d1, u_y, u_dinv, u_t1, u_t2;
   T* kinv = nullptr;
   T *xin = nullptr, *bin = nullptr;   // mixed precision: inner solution / right-hand side
+  T* pin = nullptr;                   // fixed input of the captured preconditioner graph
 };
 
 struct PrecData {
@@ -103,6 +104,10 @@ struct PrecData {
   PrecBufs<double> b64;
   PrecBufs<float> b32;
   Mat4 Q, Qi;
+  // captured preconditioner graphs (per precision and flux Chebyshev degree)
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int gdeg[2] = {0, 0};
   long long maxN = 0, maxcells = 0;
 };
 
@@ -388,7 +393,7 @@ static void carve_bufs(biot_problem_s* h, PrecData* P, PrecBufs<T>& B, Layout& L
   const long long S = h->slab_len;
   B.V = L.take<T>((size_t)(kMaxRestart + 1) * S);
   B.w = L.take<T>(S); B.t = L.take<T>(S); B.r = L.take<T>(S);
-  B.xin = L.take<T>(S); B.bin = L.take<T>(S);
+  B.xin = L.take<T>(S); B.bin = L.take<T>(S); B.pin = L.take<T>(S);
   B.Wr = L.take<T>(S); B.Wz = L.take<T>(S); B.Wf = L.take<T>(S);
   B.T1 = L.take<T>(S); B.T2 = L.take<T>(S); B.T3 = L.take<T>(S); B.T4 = L.take<T>(S);
   B.dqinv = L.take<T>(h->state_len);
@@ -834,6 +839,12 @@ void refresh_solver(biot_problem_s* h, hipStream_t s) {
 }
 
 void destroy_solver(biot_problem_s* h) {
+  PrecData* P = h->prec;
+  if (P) {
+    for (int q = 0; q < 2; ++q)
+      if (P->gexec[q]) (void)hipGraphExecDestroy(P->gexec[q]);
+    if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+  }
   delete h->prec;
   h->prec = nullptr;
 }
@@ -963,12 +974,44 @@ static void apply_prec(biot_problem_s* h, const T* rin, T* z, int qdeg, hipStrea
   launch_prec_finalize<T>(h->d_inst, cnt, P->maxN, nl, P->Q, B.Wz, rin, z, s);
 }
 
+// z = P^-1 r through a captured graph: r is staged in a fixed buffer, the
+// graph (captured once on a private stream, replayed on the caller's stream)
+// runs the whole preconditioner and writes B.t.
+template <typename T>
+static void apply_prec_graph(biot_problem_s* h, const T* rin, T* z, int qdeg, bool use_graph, hipStream_t s) {
+  PrecData* P = h->prec;
+  auto& B = bufs<T>(P);
+  if (!use_graph || z != B.t) {
+    apply_prec<T>(h, rin, z, qdeg, s);
+    return;
+  }
+  const int q = std::is_same<T, float>::value ? 1 : 0;
+  if (P->gexec[q] && P->gdeg[q] != qdeg) {
+    hip_check(hipGraphExecDestroy(P->gexec[q]), "graph destroy");
+    P->gexec[q] = nullptr;
+  }
+  if (!P->gexec[q]) {
+    if (!P->cap_stream) hip_check(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking), "capture stream");
+    hip_check(hipStreamSynchronize(s), "pre-capture sync");
+    hipGraph_t g;
+    hip_check(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeRelaxed), "begin capture");
+    apply_prec<T>(h, B.pin, B.t, qdeg, P->cap_stream);
+    hip_check(hipStreamEndCapture(P->cap_stream, &g), "end capture");
+    hip_check(hipGraphInstantiate(&P->gexec[q], g, nullptr, nullptr, 0), "graph instantiate");
+    hip_check(hipGraphDestroy(g), "graph destroy");
+    P->gdeg[q] = qdeg;
+  }
+  hip_check(hipMemcpyAsync(B.pin, rin, sizeof(T) * h->slab_len, hipMemcpyDeviceToDevice, s), "graph input");
+  hip_check(hipGraphLaunch(P->gexec[q], s), "graph launch");
+}
+
 // ---------------------------------------------------------------------------
 // GMRES (right preconditioned, restarted, CGS2), batched over instances
 // ---------------------------------------------------------------------------
 struct SolveCtl {
   double rtol;
   int maxit, restart, qdeg;
+  bool graph;
 };
 
 // y = b - A x into r (type T)
@@ -1030,7 +1073,7 @@ static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const Solv
     for (; jj < m && total < ctl.maxit; ++jj) {
       T* vj = B.V + (long long)jj * S;
       T* vn = B.V + (long long)(jj + 1) * S;
-      apply_prec<T>(h, vj, B.t, ctl.qdeg, s);
+      apply_prec_graph<T>(h, vj, B.t, ctl.qdeg, ctl.graph, s);
       launch_apply(h, B.t, vn, transpose, std::is_same<T, float>::value ? 1 : 0, s);
       seg_mdot<T, T>(B.V, S, jj + 1, vn, P->d_gseg, cnt, dot_chunks(P->gmax), P->partial, P->dot1, s);
       seg_maxpy<T, T>(B.V, S, jj + 1, P->dot1, -1.0, vn, P->d_gseg, cnt, P->gmax, s);
@@ -1099,7 +1142,7 @@ static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const Solv
       upload(coef, P->coef, s);
       hip_check(hipMemsetAsync(B.w, 0, sizeof(T) * S, s), "zero");
       seg_maxpy<T, T>(B.V, S, kmax, P->coef, 1.0, B.w, P->d_gseg, cnt, P->gmax, s);
-      apply_prec<T>(h, B.w, B.t, ctl.qdeg, s);
+      apply_prec_graph<T>(h, B.w, B.t, ctl.qdeg, ctl.graph, s);
       vaxpby<T>(1.0, B.t, 1.0, x, S, s);
     }
     std::vector<double> prev = beta;
@@ -1130,7 +1173,7 @@ static void solve_impl(biot_problem_s* h, const double* b, double* x, int transp
                        biot_solve_info* info, hipStream_t s) {
   biot_solve_opts opts;
   opts.rtol = 1e-12; opts.maxit = 1000; opts.restart = 40; opts.precision = BIOT_FP64;
-  opts.inner_rtol = 1e-5; opts.max_refine = 20; opts.cheb_degree = 8;
+  opts.inner_rtol = 1e-5; opts.max_refine = 20; opts.cheb_degree = 8; opts.graph = 1;
   if (o) opts = *o;
   if (!(opts.rtol > 0) || !std::isfinite(opts.rtol)) throw BiotError{BIOT_ERR_ARG, "rtol must be > 0"};
   if (opts.maxit < 1) throw BiotError{BIOT_ERR_ARG, "maxit must be >= 1"};
@@ -1141,7 +1184,7 @@ static void solve_impl(biot_problem_s* h, const double* b, double* x, int transp
   std::vector<int> its, rst, st;
   std::vector<double> rr;
   if (opts.precision == BIOT_FP64) {
-    SolveCtl ctl{opts.rtol, opts.maxit, opts.restart, opts.cheb_degree};
+    SolveCtl ctl{opts.rtol, opts.maxit, opts.restart, opts.cheb_degree, opts.graph != 0};
     gmres<double>(h, b, x, transpose, ctl, its, rst, rr, st, s);
     for (int k = 0; k < cnt; ++k) {
       info[k].iterations = its[k]; info[k].restarts = rst[k]; info[k].ir_sweeps = 0;
@@ -1172,7 +1215,7 @@ static void solve_impl(biot_problem_s* h, const double* b, double* x, int transp
       if (all || sw == opts.max_refine) break;
       vcast(B64.r, B32.bin, h->slab_len, s);
       hip_check(hipMemsetAsync(B32.xin, 0, sizeof(float) * h->slab_len, s), "zero");
-      SolveCtl ctl{opts.inner_rtol, opts.maxit, opts.restart, opts.cheb_degree};
+      SolveCtl ctl{opts.inner_rtol, opts.maxit, opts.restart, opts.cheb_degree, opts.graph != 0};
       float* d32 = B32.xin;
       gmres<float>(h, B32.bin, d32, transpose, ctl, its, rst, rr, st, s);
       vacc(d32, x, h->slab_len, s);
@@ -1196,6 +1239,38 @@ void launch_slab_rhs(const biot_problem_s* h, const double* state, double t_star
   hip_check(hipMemsetAsync(rhs, 0, sizeof(double) * h->slab_len, s), "rhs clear");
   launch_rhs(h->d_inst, h->count, max_cells(h), h->tm, h->nl, t_start, state, rhs, s);
   hip_check(hipGetLastError(), "rhs launch");
+}
+
+// sensor weights (host): containing cell (floor, clipped), DG-Q1 Lagrange weights
+static std::vector<SensorW> sensor_weights(biot_problem_s* h, const double* sensors_xyz, int nsens) {
+  const int cnt = h->count, d = h->dim;
+  std::vector<SensorW> sw((size_t)cnt * nsens);
+  for (int k = 0; k < cnt; ++k) {
+    const InstDev& I = h->inst[k];
+    for (int q = 0; q < nsens; ++q) {
+      SensorW w;
+      std::memset(&w, 0, sizeof(w));
+      int ce[3] = {0, 0, 0};
+      double sl[3] = {0, 0, 0};
+      for (int e = 0; e < d; ++e) {
+        const double xv = sensors_xyz[q * d + e];
+        if (!std::isfinite(xv)) throw BiotError{BIOT_ERR_ARG, "sensor coordinates must be finite"};
+        int c = (int)std::floor(xv / I.h[e]);
+        c = std::min(std::max(c, 0), I.n[e] - 1);
+        ce[e] = c;
+        sl[e] = xv / I.h[e] - c;
+      }
+      for (int g = 0; g < (d == 3 ? 8 : 4); ++g) {
+        const int gg[3] = {g & 1, (g >> 1) & 1, (g >> 2) & 1};
+        double wt = 1.0;
+        for (int e = 0; e < d; ++e) wt *= psi(gg[e], sl[e]);
+        w.idx[g] = (2 * ce[0] + gg[0]) + (long long)I.sp[0] * ((2 * ce[1] + gg[1]) + (long long)I.sp[1] * (d == 3 ? 2 * ce[2] + gg[2] : 0));
+        w.w[g] = wt;
+      }
+      sw[(size_t)k * nsens + q] = w;
+    }
+  }
+  return sw;
 }
 
 }  // namespace bt
@@ -1307,6 +1382,43 @@ biot_status step(biot_problem h, int32_t nslabs, double t_start, double* state, 
   }
 }
 
+biot_status biot_misfit(biot_problem h, int32_t nslabs, const double* states, const double* sensors_xyz,
+                        int32_t nsens, const double* p_obs, double* J, void* stream) {
+  try {
+    need(h, "handle is null");
+    need(nslabs >= 1, "nslabs must be >= 1");
+    need(states && p_obs, "states and p_obs must be device pointers");
+    need(sensors_xyz && J, "sensors_xyz and J must be host pointers");
+    PrecData* P = h->prec;
+    need(nsens >= 1 && nsens <= P->max_sens, "nsens must be in 1..256");
+    hipStream_t s = (hipStream_t)stream;
+    const int cnt = h->count;
+    auto sw = sensor_weights(h, sensors_xyz, nsens);
+    upload(sw, P->sw, s);
+    std::vector<double> Jk(cnt, 0.0), res((size_t)cnt * nsens);
+    for (int n = 0; n < nslabs; ++n) {
+      // states are spatial vectors; view state n as level 0 of a slab-shaped buffer
+      launch_bcast(h->d_inst, cnt, P->maxN, 1, states + (long long)n * h->state_len, P->xfwd, s);
+      for (int k = 0; k < cnt; ++k)
+        hip_check(hipMemcpyAsync(P->sobs + (long long)k * nsens, p_obs + ((long long)k * nslabs + n) * nsens,
+                                 8 * nsens, hipMemcpyDeviceToDevice, s), "obs gather");
+      launch_sensor(h->d_inst, cnt, 0, nsens, P->sw, P->xfwd, P->sobs, P->sres, s);
+      hip_check(hipMemcpyAsync(res.data(), P->sres, 8 * res.size(), hipMemcpyDeviceToHost, s), "res read");
+      hip_check(hipStreamSynchronize(s), "misfit sync");
+      for (int k = 0; k < cnt; ++k)
+        for (int q = 0; q < nsens; ++q) Jk[k] += 0.5 * res[(size_t)k * nsens + q] * res[(size_t)k * nsens + q];
+    }
+    for (int k = 0; k < cnt; ++k) J[k] = Jk[k];
+    return BIOT_OK;
+  } catch (const BiotError& e) {
+    set_error(e.msg);
+    return e.st;
+  } catch (const std::exception& e) {
+    set_error(std::string("internal error: ") + e.what());
+    return BIOT_ERR_ARG;
+  }
+}
+
 biot_status adjoint_sweep(biot_problem h, int32_t nslabs, double t_start, const double* checkpoints,
                           const double* sensors_xyz, int32_t nsens, const double* p_obs, const biot_solve_opts* opts,
                           double* J, double* grad_log_k, void* stream) {
@@ -1319,33 +1431,7 @@ biot_status adjoint_sweep(biot_problem h, int32_t nslabs, double t_start, const 
     need(nsens >= 1 && nsens <= P->max_sens, "nsens must be in 1..256");
     hipStream_t s = (hipStream_t)stream;
     const int cnt = h->count, d = h->dim, nl = h->nl;
-    // sensor weights (host): containing cell (floor, clipped), DG-Q1 Lagrange weights
-    std::vector<SensorW> sw((size_t)cnt * nsens);
-    for (int k = 0; k < cnt; ++k) {
-      const InstDev& I = h->inst[k];
-      for (int q = 0; q < nsens; ++q) {
-        SensorW w;
-        std::memset(&w, 0, sizeof(w));
-        int ce[3] = {0, 0, 0};
-        double sl[3] = {0, 0, 0};
-        for (int e = 0; e < d; ++e) {
-          const double xv = sensors_xyz[q * d + e];
-          need(std::isfinite(xv), "sensor coordinates must be finite");
-          int c = (int)std::floor(xv / I.h[e]);
-          c = std::min(std::max(c, 0), I.n[e] - 1);
-          ce[e] = c;
-          sl[e] = xv / I.h[e] - c;
-        }
-        for (int g = 0; g < (d == 3 ? 8 : 4); ++g) {
-          const int gg[3] = {g & 1, (g >> 1) & 1, (g >> 2) & 1};
-          double wt = 1.0;
-          for (int e = 0; e < d; ++e) wt *= psi(gg[e], sl[e]);
-          w.idx[g] = (2 * ce[0] + gg[0]) + (long long)I.sp[0] * ((2 * ce[1] + gg[1]) + (long long)I.sp[1] * (d == 3 ? 2 * ce[2] + gg[2] : 0));
-          w.w[g] = wt;
-        }
-        sw[(size_t)k * nsens + q] = w;
-      }
-    }
+    auto sw = sensor_weights(h, sensors_xyz, nsens);
     upload(sw, P->sw, s);
     hip_check(hipMemsetAsync(grad_log_k, 0, 8 * h->ncells, s), "grad clear");
     std::vector<double> Jk(cnt, 0.0), res((size_t)cnt * nsens);

@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_WORKSPACE", 3: "ERR_DEVICE", 4: "
 EXPORTS = [
     "biot_workspace_bytes", "create_slab_problem", "destroy_slab_problem", "biot_set_log_k",
     "biot_sizes", "biot_totals", "apply_operator", "slab_rhs", "solve_slab",
-    "solve_slab_transposed", "step", "adjoint_sweep", "biot_last_error",
+    "solve_slab_transposed", "step", "adjoint_sweep", "biot_misfit", "biot_last_error",
 ]
 
 
@@ -42,7 +42,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [
         ("rtol", ctypes.c_double), ("maxit", ctypes.c_int32), ("restart", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
-        ("max_refine", ctypes.c_int32), ("cheb_degree", ctypes.c_int32),
+        ("max_refine", ctypes.c_int32), ("cheb_degree", ctypes.c_int32), ("graph", ctypes.c_int32),
     ]
 
 
@@ -91,6 +91,7 @@ def load_library(path: str = LIB_PATH):
     lib.step.argtypes = [P, i32, dbl, P, P, P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), P]
     lib.adjoint_sweep.argtypes = [P, i32, dbl, P, ctypes.POINTER(dbl), i32, P, ctypes.POINTER(SolveOpts),
                                   ctypes.POINTER(dbl), P, P]
+    lib.biot_misfit.argtypes = [P, i32, P, ctypes.POINTER(dbl), i32, P, ctypes.POINTER(dbl), P]
     for name in EXPORTS:
         if name != "biot_last_error":
             getattr(lib, name).restype = ctypes.c_int32
@@ -122,10 +123,10 @@ def make_desc(wl) -> Desc:
 
 
 def make_opts(rtol=1e-12, maxit=2000, restart=40, precision=0, inner_rtol=1e-5, max_refine=20,
-              cheb_degree=8) -> SolveOpts:
+              cheb_degree=8, graph=1) -> SolveOpts:
     o = SolveOpts()
     o.rtol, o.maxit, o.restart, o.precision = rtol, maxit, restart, precision
-    o.inner_rtol, o.max_refine, o.cheb_degree = inner_rtol, max_refine, cheb_degree
+    o.inner_rtol, o.max_refine, o.cheb_degree, o.graph = inner_rtol, max_refine, cheb_degree, graph
     return o
 
 
@@ -244,6 +245,14 @@ class BiotSlab:
                                     sens.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nsens,
                                     _ptr(p_obs), ctypes.byref(opts), J, _ptr(grad), self._stream())
         return list(J), grad, st
+
+    def misfit(self, nslabs, end_states, sensors_xyz, p_obs):
+        sens = np.ascontiguousarray(np.asarray(sensors_xyz, dtype=np.float64))
+        J = (ctypes.c_double * self.count)()
+        _check(self.lib.biot_misfit(self.h, int(nslabs), _ptr(end_states),
+                                    sens.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), sens.shape[0],
+                                    _ptr(p_obs), J, self._stream()))
+        return list(J)
 
     # -- layout helpers (host) ---------------------------------------------------
     def instance_slab(self, vec, k):

@@ -1,0 +1,71 @@
+"""The pressure-misfit autograd Function: J and dJ/dlog K from the HIP adjoint
+against the oracle's discrete adjoint, and against central finite differences
+of the HIP forward map (20 random unit directions, FP64)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_common import small_workload, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(wls, nslabs, nsens, seed):
+    from oracle import adjoint, fe, slab
+    from paper_1801_04984_amd import BiotSlab
+    thetas = [w.log_k() for w in wls]
+    h = BiotSlab(wls, thetas)
+    d = wls[0].dim
+    sens = W.sensors(nsens, d, seed)
+    rng = np.random.default_rng(seed + 1)
+    obs = [0.05 * rng.standard_normal((nslabs, nsens)) for _ in wls]
+    refs = []
+    for w, th, ob in zip(wls, thetas, obs):
+        prob = slab.problem_from_workload(w, theta=th)
+        P = fe.pressure_point_matrix(prob.mesh, sens)
+        refs.append(adjoint.gradient(prob, nslabs, P, ob))
+    return h, thetas, sens, obs, refs
+
+
+def test_autograd_matches_oracle_adjoint():
+    torch = torch_cuda()
+    from paper_1801_04984_amd.adjoint import PressureMisfit
+    wls = [small_workload(2, (9, 8), 1, seed=5, load_kind=W.LOAD_RAMP),
+           small_workload(2, (6, 11), 1, seed=6, load_kind=W.LOAD_RAMP)]
+    ns = 3
+    h, thetas, sens, obs, refs = _setup(wls, ns, 6, 17)
+    theta = torch.tensor(np.concatenate(thetas), device="cuda", requires_grad=True)
+    p_obs = np.concatenate([o.reshape(-1) for o in obs])
+    J = PressureMisfit.apply(theta, h, ns, sens, p_obs, {"rtol": 1e-13})
+    for k, (Jr, gr, _) in enumerate(refs):
+        assert abs(J[k].item() - Jr) <= 1e-9 * abs(Jr)
+    (2.0 * J[0] + 0.5 * J[1]).backward()
+    g = theta.grad.cpu().numpy()
+    n0 = thetas[0].size
+    gref = np.concatenate([2.0 * refs[0][1], 0.5 * refs[1][1]])
+    assert np.linalg.norm(g - gref) <= 1e-8 * np.linalg.norm(gref)
+    assert n0 == 72
+    h.close()
+
+
+def test_autograd_finite_differences_20_directions():
+    torch = torch_cuda()
+    from paper_1801_04984_amd.adjoint import PressureMisfit
+    wl = small_workload(2, (7, 6), 1, seed=9, load_kind=W.LOAD_RAMP)
+    ns = 2
+    h, thetas, sens, obs, refs = _setup([wl], ns, 5, 23)
+    th0 = thetas[0]
+    opts = {"rtol": 1e-13}
+    theta = torch.tensor(th0, device="cuda", requires_grad=True)
+    J = PressureMisfit.apply(theta, h, ns, sens, obs[0].reshape(-1), opts)
+    J.sum().backward()
+    g = theta.grad.cpu().numpy()
+    eps = 1e-5
+    for dvec in W.unit_directions(20, th0.size, 41):
+        jp = PressureMisfit.apply(torch.tensor(th0 + eps * dvec, device="cuda"), h, ns, sens, obs[0].reshape(-1),
+                                  opts).item()
+        jm = PressureMisfit.apply(torch.tensor(th0 - eps * dvec, device="cuda"), h, ns, sens, obs[0].reshape(-1),
+                                  opts).item()
+        fd = (jp - jm) / (2 * eps)
+        assert abs(fd - g @ dvec) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g).max()), (fd, g @ dvec)
+    h.close()

@@ -214,3 +214,21 @@ def test_step3d_and_adjoint():
     gv = g.cpu().numpy()
     assert np.linalg.norm(gv - gref) <= 1e-8 * np.linalg.norm(gref)
     h.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replay_matches_eager(precision):
+    """The captured preconditioner graph, replayed many times with eager work and
+    host synchronisations in between, gives bit-identical solves."""
+    torch = torch_cuda()
+    wls = [small_workload(2, n, 1, seed=90 + i) for i, n in enumerate([(17, 12), (9, 9)])]
+    h, probs = make_pair(wls)
+    b = torch.tensor(np.concatenate([_rhs(p, seed=i) for i, p in enumerate(probs)]), device="cuda")
+    xe, ie, se = h.solve(b, precision=precision, graph=0)
+    for rep in range(3):
+        xg, ig, sg = h.solve(b, precision=precision, graph=1)
+        torch.cuda.synchronize()
+        assert se == 0 and sg == 0
+        assert torch.equal(xg, xe), rep
+        assert [i["iterations"] for i in ig] == [i["iterations"] for i in ie]
+    h.close()
