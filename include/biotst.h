@@ -93,8 +93,8 @@ typedef struct {
   int32_t maxit;        /* total GMRES iterations                         [1000]   */
   int32_t restart;      /* GMRES(m) restart length, <= 64                   [40]   */
   int32_t precision;    /* biot_precision                                [FP64]   */
-  double inner_rtol;    /* mixed: inner FP32 solve tolerance              [1e-5]   */
-  int32_t max_refine;   /* mixed: outer refinement sweeps                   [20]   */
+  double inner_rtol;    /* mixed: inner FP32 solve tolerance              [1e-2]   */
+  int32_t max_refine;   /* mixed: outer refinement sweeps                   [30]   */
   int32_t cheb_degree;  /* Chebyshev degree of the flux-mass block          [8]    */
   int32_t graph;        /* 1: replay the preconditioner as a captured      [1]
                            hipGraph (captured on first use); 0: eager     */

@@ -1173,7 +1173,7 @@ static void solve_impl(biot_problem_s* h, const double* b, double* x, int transp
                        biot_solve_info* info, hipStream_t s) {
   biot_solve_opts opts;
   opts.rtol = 1e-12; opts.maxit = 1000; opts.restart = 40; opts.precision = BIOT_FP64;
-  opts.inner_rtol = 1e-5; opts.max_refine = 20; opts.cheb_degree = 8; opts.graph = 1;
+  opts.inner_rtol = 1e-2; opts.max_refine = 30; opts.cheb_degree = 8; opts.graph = 1;
   if (o) opts = *o;
   if (!(opts.rtol > 0) || !std::isfinite(opts.rtol)) throw BiotError{BIOT_ERR_ARG, "rtol must be > 0"};
   if (opts.maxit < 1) throw BiotError{BIOT_ERR_ARG, "maxit must be >= 1"};

@@ -122,7 +122,7 @@ def make_desc(wl) -> Desc:
     return d
 
 
-def make_opts(rtol=1e-12, maxit=2000, restart=40, precision=0, inner_rtol=1e-5, max_refine=20,
+def make_opts(rtol=1e-12, maxit=2000, restart=40, precision=0, inner_rtol=1e-2, max_refine=30,
               cheb_degree=8, graph=1) -> SolveOpts:
     o = SolveOpts()
     o.rtol, o.maxit, o.restart, o.precision = rtol, maxit, restart, precision
