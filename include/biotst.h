@@ -116,7 +116,8 @@ biot_status biot_workspace_bytes(const biot_problem_desc* descs, int32_t count,
  * concatenated in every vector argument, each one a full slab vector).
  * log_k[i]: host array of prod(n) cellwise log K values of instance i.
  * Validates every descriptor and log_k (finite) before touching the device;
- * uploads constants into the workspace; returns after `stream` drains. */
+ * clears the workspace and uploads constants into it; returns after
+ * `stream` drains. */
 biot_status create_slab_problem(const biot_problem_desc* descs, int32_t count,
                                 const double* const* log_k, void* workspace,
                                 size_t ws_bytes, void* stream, biot_problem* out);

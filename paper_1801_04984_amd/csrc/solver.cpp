@@ -613,13 +613,16 @@ static void upload(const std::vector<X>& v, X* d, hipStream_t s) {
 // power iteration for lambda_max(Dinv S) per segment; apply(x, y) computes y = Dinv S x
 template <typename F>
 static std::vector<double> power_max(PrecData* P, F apply, double* x, double* y, const std::vector<VSeg>& segs,
-                                     long long span, hipStream_t s, int iters = 14) {
+                                     hipStream_t s, int iters = 14) {
   const int ns = (int)segs.size();
   VSeg* dsegs = (VSeg*)P->scal;   // reuse a scalar block for the segment list (small)
   static_assert(sizeof(VSeg) == 16, "VSeg layout");
   if ((size_t)ns * sizeof(VSeg) > (size_t)std::max(P->count * P->nl, P->count) * 64 * sizeof(double))
     throw BiotError{BIOT_ERR_ARG, "too many power-iteration segments"};
   upload(segs, dsegs, s);
+  // the start vector covers every segment (segments need not be packed)
+  long long span = 0;
+  for (auto& sg : segs) span = std::max(span, sg.off + sg.len);
   std::vector<double> hx(span);
   std::mt19937_64 rng(12345);
   std::uniform_real_distribution<double> U(0.5, 1.5);
@@ -683,7 +686,7 @@ static void setup_pressure(biot_problem_s* h, hipStream_t s) {
       launch_pdg<double>(d, h->d_inst, P->d_pdg, cnt, nl, P->pdg_max, kApplyDinv, ChebCoef{0, 0, 0, 1}, B.dqinv,
                          B.pdg_dinv, nullptr, nullptr, nullptr, x, y, s);
     };
-    auto lam = power_max(P, apply, B.T1, B.T2, segs, h->slab_len, s);
+    auto lam = power_max(P, apply, B.T1, B.T2, segs, s);
     scale_dinv(P, B.pdg_dinv, dsegs, lam, s);
   }
   for (int l = 0; l < P->npl; ++l) {
@@ -697,7 +700,7 @@ static void setup_pressure(biot_problem_s* h, hipStream_t s) {
       launch_pcell<double>(P->d_pc[l], cnt, nl, P->pc_max[l], kApplyDinv, ChebCoef{0, 0, 0, 1}, B.pc_coef[l],
                            B.pc_dinv[l], nullptr, nullptr, nullptr, x, y, s);
     };
-    auto lam = power_max(P, apply, B.pc_x[l], B.pc_r[l], segs, nl * P->pc_total[l], s);
+    auto lam = power_max(P, apply, B.pc_x[l], B.pc_r[l], segs, s);
     std::vector<VSeg> dsegs;
     for (int k = 0; k < cnt; ++k)
       for (int j = 0; j < nl; ++j) dsegs.push_back({P->pc[l][k].doff + j * P->pc[l][k].djstride, P->pc[l][k].ncells});
@@ -788,7 +791,7 @@ static void setup_elasticity(biot_problem_s* h, hipStream_t s) {
       launch_uapply<double>(d, dseg, work, nwork, 1, 0, xx, nullptr, yy, P->d_uemat64, s);
       launch_mul_dinv<double>(dls, cnt, 1, mx, B.u_dinv[0], yy, yy, s);
     };
-    auto lam = power_max(P, apply, x, y, segs, P->u_total[l], s);
+    auto lam = power_max(P, apply, x, y, segs, s);
     std::vector<VSeg> dsegs;
     for (auto& g : P->ug[l]) dsegs.push_back({g.doff, g.nu});
     scale_dinv(P, B.u_dinv[0], dsegs, lam, s);

@@ -52,6 +52,26 @@ def test_solve_mixed_refined(r):
     h.close()
 
 
+@pytest.mark.parametrize("r", [1, 2])
+def test_solve_batched_deep_hierarchy(r):
+    """Equal-size and uneven instances whose elasticity multigrid has three
+    levels (two smoothed): the coarse levels store instances with a stride of
+    r+1 time levels, which the set-up must cover for every instance."""
+    torch = torch_cuda()
+    sizes = [(24, 24), (24, 24), (26, 22)]
+    wls = [small_workload(2, n, r, seed=40 + i) for i, n in enumerate(sizes)]
+    h, probs = make_pair(wls)
+    bs = [_rhs(p, seed=11 + i) for i, p in enumerate(probs)]
+    x, info, st = h.solve(torch.tensor(np.concatenate(bs), device="cuda"), rtol=RT)
+    assert st == 0, info
+    xv = x.cpu().numpy()
+    for k, (p, bk) in enumerate(zip(probs, bs)):
+        got = xv[h.slab_offsets[k]: h.slab_offsets[k] + p.L * p.N]
+        err = field_rel(p, got, p.solve(bk))
+        assert max(err.values()) < TOL, (k, err)
+    h.close()
+
+
 def test_solve_batched_uneven_matches_single():
     torch = torch_cuda()
     wls = [small_workload(2, n, 1, seed=20 + i, b=0.6 + 0.1 * i) for i, n in enumerate([(9, 9), (21, 14), (16, 16)])]
