@@ -73,7 +73,8 @@ typedef enum { BIOT_LOAD_STEP = 0, BIOT_LOAD_RAMP = 1 } biot_load_kind;
  * permeability K = exp(log_k). */
 typedef struct {
   int32_t dim;          /* 2 or 3                                                    */
-  int32_t n[3];         /* cells per axis; n[2] ignored for dim == 2                 */
+  int32_t n[3];         /* cells per axis (1..4096); n[2] ignored for dim == 2;      *
+                         * one instance's slab must hold < 2^31 unknowns             */
   double length[3];     /* box edge lengths                                          */
   int32_t r;            /* dG(r) order, 0..3; all instances of a batch share it      */
   double tau;           /* slab length > 0                                           */

@@ -1,15 +1,21 @@
 // 3D space-time slab operator Y = A X (or A^T X) and the 3D Q2 elasticity
 // operator of the multigrid levels.
 //
-// u-rows (tau A u - c_p E p, section "Poroelasticity"): one block = an xy
-// tile of 8x8 cells (7x7 owned plus a one-cell halo on the low sides) that
-// marches through a z-chunk of cell layers.  Each thread evaluates the element
-// vector of its cell by sum factorisation through the 3x3x3 Gauss points, one
-// z-slice of points at a time (registers stay bounded), and stages it in LDS.
-// Node planes are completed layer by layer: plane 2k gets the top slice of
-// layer k-1 (carried in LDS) plus the bottom slice of layer k, plane 2k+1 the
-// middle slice; every owned node is summed in a fixed order (deterministic,
-// no atomics).  q-rows and p-rows are gathers (rows.h) in their own kernels:
+// u-rows (tau A u - c_p E p, section "Poroelasticity"): on the uniform box
+// mesh every cell of an instance (or multigrid level) has the same element
+// matrices tau A_e (81x81) and E_e (81x8).  The element products of a layer
+// of cells are therefore one dense contraction
+//     [tau A_e | E_e] (81 x 89)  x  [u_e ; -c_p p_e] (89 x cells),
+// done on the matrix cores (16x16x4 MFMA, FP64 or FP32): six waves each keep
+// one 16-row tile of the element matrix in registers for the whole launch
+// and multiply the gathered element vectors staged in LDS.
+//
+// Work decomposition: one block = an xy tile of 8x8 cells (7x7 owned plus a
+// one-cell halo on the low sides) marching through a z-chunk of cell layers.
+// Per layer the element rows are staged in LDS and every owned node of planes
+// 2k (bottom slice of layer k plus the top slice of layer k-1, carried in
+// LDS) and 2k+1 (middle slice) is summed in a fixed order: deterministic, no
+// atomics.  q-rows and p-rows are gathers (rows.h) in their own kernels:
 //   q-rows: tau (Mq q + B p);   p-rows: -w [tau div q_i + sum_j T_ij (b div u_j + p_j/M)]
 //   (A^T: p-rows -w [tau div q_i + tau b div u_i + sum_j T_ji p_j / M], u-rows use sum_j T_ji p_j).
 #include "kernels.h"
@@ -18,17 +24,41 @@
 
 namespace bt {
 
-constexpr int kT3 = 8;
-constexpr int kO3 = kT3 - 1;
-constexpr int kZC = 8;
+constexpr int kT3 = 8;        // xy tile edge in cells (64 cells per layer)
+constexpr int kO3 = kT3 - 1;  // owned cells per tile edge
+constexpr int kZC = 8;        // cell layers per z-chunk
+constexpr int kW3 = 6;        // waves per block: one 16-row tile of the 96 padded element rows each
+constexpr int kLD3 = 80;      // LDS row stride (elements): 16-lane groups of one half-wave hit disjoint banks
 
 int apply3d_tile_cells_xy() { return kO3; }
 int apply3d_tile_cells_z() { return kZC; }
 
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+
+// 16x16x4 MFMA: A operand lane l holds A[l % 16][l / 16], B operand B[l / 16][l % 16];
+// output value v of lane l is D[row(l, v)][l % 16].
+template <typename T> struct Mfma16;
+template <> struct Mfma16<double> {
+  using V = mf_d4;
+  static __device__ __forceinline__ V mma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int v) { return 4 * v + (l >> 4); }
+};
+template <> struct Mfma16<float> {
+  using V = mf_f4;
+  static __device__ __forceinline__ V mma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
 template <typename T>
 struct U3Job {
   int n[3], su[3];
-  T h[3], tau, lam, mu, cp;
+  const T* A;        // element-matrix fragments: [wave][k-step][lane] (see elast_fragments3d)
+  T cp;              // coupling weight: element rows are tau A_e u - cp E_e p
   const T* X;        // u block, components at X + c * nu1
   const T* Bv;       // residual mode right-hand side (same layout) or null
   T* Y;
@@ -40,146 +70,86 @@ struct U3Job {
   int mode;          // 0: Y = A x (+ coupling); 1: Y = B - A x
 };
 
-template <typename T>
-__device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0) {
-  __shared__ T E[81][64];
-  __shared__ T C[27][64];
-  const int tid = threadIdx.x;
-  const int lx = tid % kT3, ly = tid / kT3;
+// KS = k-steps of 4 columns: 23 with the 8 coupling columns, 21 without
+template <typename T, int KS>
+__device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0, int zc) {
+  constexpr int NC = kT3 * kT3, NT = 64 * kW3, KR = 4 * KS;
+  __shared__ T Ul[KR * kLD3];     // gathered element vectors [k][cell], then element rows [row][cell]
+  __shared__ T Cc[27 * NC];       // carried top slice of the layer below [comp*9 + node][cell]
+  using M = Mfma16<T>;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nx = J.n[0], ny = J.n[1], nz = J.n[2];
-  const int i = i0 - 1 + lx, j = j0 - 1 + ly;
-  const bool vxy = i >= 0 && i < nx && j >= 0 && j < ny;
-  const long long nu1 = (long long)J.su[0] * J.su[1] * J.su[2];
-  const long long sy = J.su[0], sz = (long long)J.su[0] * J.su[1];
-  const T ihx = T(1) / J.h[0], ihy = T(1) / J.h[1], ihz = T(1) / J.h[2];
-  const T vol = J.h[0] * J.h[1] * J.h[2];
-#pragma unroll
-  for (int q = 0; q < 27; ++q) C[q][tid] = T(0);
+  const int nu1 = J.su[0] * J.su[1] * J.su[2];
+  const int sy = J.su[0], sz = J.su[0] * J.su[1];
   const int kbeg = k0 > 0 ? k0 - 1 : 0;
-  const int kend = min(k0 + kZC, nz);
-  // owned xy node ranges
+  const int kend = min(k0 + zc, nz);
   const int mxe = (i0 + kO3 >= nx) ? 2 * nx + 1 : 2 * i0 + 2 * kO3;
   const int mye = (j0 + kO3 >= ny) ? 2 * ny + 1 : 2 * j0 + 2 * kO3;
   const int nmx = mxe - 2 * i0, nmy = mye - 2 * j0;
   const int nplane = nmx * nmy;
+  // this wave's 16-row tile of the element matrix, resident for the whole launch
+  T af[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) af[s] = J.A[(wv * KS + s) * 64 + lane];
+  for (int idx = tid; idx < 27 * NC; idx += NT) Cc[idx] = T(0);
 
   for (int k = kbeg; k < kend; ++k) {
-    // ---- element vector of cell (i, j, k)
-#pragma unroll
-    for (int q = 0; q < 81; ++q) E[q][tid] = T(0);
-    if (vxy) {
-      T pc[8];
-      if (J.npl > 0) {
-#pragma unroll
-        for (int g = 0; g < 8; ++g) {
+    // ---- gather element vectors (essential u masked) and the scaled coupling pressure
+    for (int idx = tid; idx < KR * NC; idx += NT) {
+      const int kr = idx >> 6, cell = idx & 63;
+      const int i = i0 - 1 + (cell & 7), j = j0 - 1 + (cell >> 3);
+      T v = 0;
+      if (i >= 0 && i < nx && j >= 0 && j < ny) {
+        if (kr < 81) {
+          const int c2 = kr / 27, nd = kr - 27 * c2;
+          const int mx = 2 * i + nd % 3, my = 2 * j + (nd / 3) % 3, mz = 2 * k + nd / 9;
+          if (!ugrid_fixed(3, J.su, c2, mx, my, mz)) v = J.X[c2 * nu1 + mx + sy * my + sz * mz];
+        } else if (kr < 89 && J.npl > 0) {
+          const int g = kr - 81;
           const long long o = (2 * i + (g & 1)) + (long long)J.sp[0] *
                               ((2 * j + ((g >> 1) & 1)) + (long long)J.sp[1] * (2 * k + (g >> 2)));
           T s = 0;
           for (int l = 0; l < J.npl; ++l) s += J.pw[l] * J.P[l * J.plstride + o];
-          pc[g] = s;
+          v = -J.cp * s;
         }
-      } else {
-#pragma unroll
-        for (int g = 0; g < 8; ++g) pc[g] = T(0);
       }
-#pragma unroll 1
-      for (int kz = 0; kz < 3; ++kz) {
-        T zv[3][9], zd[3][9];
+      Ul[kr * kLD3 + cell] = v;
+    }
+    __syncthreads();
+    // ---- element rows of the layer: rows of tile wv x 64 cells
+    typename M::V acc[4];
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+    for (int t = 0; t < 4; ++t) acc[t] = typename M::V{0, 0, 0, 0};
 #pragma unroll
-          for (int ba = 0; ba < 9; ++ba) {
-            const int a = ba % 3, b = ba / 3;
-            const int mx = 2 * i + a, my = 2 * j + b;
-            T v = 0, dv = 0;
+    for (int s = 0; s < KS; ++s) {
+      const T* Bs = Ul + (4 * s + (lane >> 4)) * kLD3 + (lane & 15);
 #pragma unroll
-            for (int kk = 0; kk < 3; ++kk) {
-              const int mz = 2 * k + kk;
-              const T u = ugrid_fixed(3, J.su, c, mx, my, mz) ? T(0) : J.X[c * nu1 + mx + sy * my + sz * mz];
-              v += T(VQ(kz, kk)) * u;
-              dv += T(DQ(kz, kk)) * u;
-            }
-            zv[c][ba] = v;
-            zd[c][ba] = dv;
-          }
-        T av[3][9], ad[3][9];
+      for (int t = 0; t < 4; ++t) acc[t] = M::mma(af[s], Bs[16 * t], acc[t]);
+    }
+    __syncthreads();
+    {
+      const int c = wv >> 1, h = wv & 1;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+      for (int t = 0; t < 4; ++t)
 #pragma unroll
-          for (int ba = 0; ba < 9; ++ba) { av[c][ba] = 0; ad[c][ba] = 0; }
-#pragma unroll
-        for (int ky = 0; ky < 3; ++ky)
-#pragma unroll
-          for (int kx = 0; kx < 3; ++kx) {
-            T g[3][3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              T tx = 0, ty = 0, tz = 0;
-#pragma unroll
-              for (int b = 0; b < 3; ++b) {
-                T sd = 0, sv = 0, szv = 0;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                  sd += T(DQ(kx, a)) * zv[c][b * 3 + a];
-                  sv += T(VQ(kx, a)) * zv[c][b * 3 + a];
-                  szv += T(VQ(kx, a)) * zd[c][b * 3 + a];
-                }
-                tx += T(VQ(ky, b)) * sd;
-                ty += T(DQ(ky, b)) * sv;
-                tz += T(VQ(ky, b)) * szv;
-              }
-              g[c][0] = tx * ihx;
-              g[c][1] = ty * ihy;
-              g[c][2] = tz * ihz;
-            }
-            T pq = 0;
-#pragma unroll
-            for (int gg = 0; gg < 8; ++gg)
-              pq += T(PQ(kx, gg & 1) * PQ(ky, (gg >> 1) & 1)) * T(PQ(kz, gg >> 2)) * pc[gg];
-            const T W = T(wq(kx) * wq(ky)) * T(wq(kz)) * vol;
-            const T div = g[0][0] + g[1][1] + g[2][2];
-            const T diag = J.tau * J.lam * div - J.cp * pq;
-            T S[3][3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-              for (int e = 0; e < 3; ++e) {
-                T s = J.tau * J.mu * (g[c][e] + g[e][c]);
-                if (c == e) s += diag;
-                S[c][e] = W * s * (e == 0 ? ihx : (e == 1 ? ihy : ihz));
-              }
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-              for (int b = 0; b < 3; ++b)
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                  av[c][b * 3 + a] += T(VQ(ky, b) * DQ(kx, a)) * S[c][0] + T(DQ(ky, b) * VQ(kx, a)) * S[c][1];
-                  ad[c][b * 3 + a] += T(VQ(ky, b) * VQ(kx, a)) * S[c][2];
-                }
-          }
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-          for (int kk = 0; kk < 3; ++kk)
-#pragma unroll
-            for (int ba = 0; ba < 9; ++ba)
-              E[c * 27 + kk * 9 + ba][tid] += T(VQ(kz, kk)) * av[c][ba] + T(DQ(kz, kk)) * ad[c][ba];
-      }
+        for (int v = 0; v < 4; ++v) {
+          const int pr = 16 * h + M::row(lane, v);
+          if (pr < 27) Ul[(c * 27 + pr) * kLD3 + 16 * t + (lane & 15)] = acc[t][v];
+        }
     }
     __syncthreads();
     // ---- owned node planes 2k (bottom slice + carried top slice) and 2k+1
     if (k >= k0) {
-      for (int idx = tid; idx < 6 * nplane; idx += 64) {
+      for (int idx = tid; idx < 6 * nplane; idx += NT) {
         const int c = idx / (2 * nplane);
         const int rem = idx - c * 2 * nplane;
-        const int zl = rem / nplane;                  // 0: plane 2k, 1: plane 2k+1
+        const int zl = rem >= nplane;
         const int r2 = rem - zl * nplane;
         const int mx = 2 * i0 + r2 % nmx, my = 2 * j0 + r2 / nmx, mz = 2 * k + zl;
-        const long long go = c * nu1 + mx + sy * my + sz * mz;
+        const int go = c * nu1 + mx + sy * my + sz * mz;
         T v;
         if (ugrid_fixed(3, J.su, c, mx, my, mz)) {
-          v = J.mode == 0 ? J.X[go] : T(0);
+          v = J.mode == 0 ? J.X[go] : J.Bv[go];
         } else {
           const bool xo = mx & 1, yo = my & 1;
           const int cx0 = xo ? (mx - 1) / 2 : mx / 2 - 1, ax0 = xo ? 1 : 2;
@@ -192,30 +162,34 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
           for (int q = 0; q < 4; ++q) {
             const int qx = q & 1, qy = q >> 1;
             if (!((qy ? vy1 : vy0) && (qx ? vx1 : vx0))) continue;
-            const int t = (ty0 + qy) * kT3 + tx0 + qx;
-            const int a = qx ? 0 : ax0, b = qy ? 0 : ay0;
-            v += E[c * 27 + zl * 9 + b * 3 + a][t];
-            if (zl == 0) v += C[c * 9 + b * 3 + a][t];
+            const int cell = (ty0 + qy) * kT3 + tx0 + qx;
+            const int nd = (qy ? 0 : ay0) * 3 + (qx ? 0 : ax0);
+            v += Ul[(c * 27 + zl * 9 + nd) * kLD3 + cell];
+            if (zl == 0) v += Cc[(c * 9 + nd) * NC + cell];
           }
+          if (J.mode != 0) v = J.Bv[go] - v;
         }
-        J.Y[go] = J.mode == 0 ? v : J.Bv[go] - v;
+        J.Y[go] = v;
       }
     }
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 27; ++q) C[q][tid] = E[(q / 9) * 27 + 18 + q % 9][tid];
+    for (int idx = tid; idx < 27 * NC; idx += NT) {
+      const int r = idx >> 6, cell = idx & 63;     // r = comp * 9 + node of the top slice
+      const int c = r / 9;
+      Cc[idx] = Ul[(c * 27 + 18 + (r - 9 * c)) * kLD3 + cell];
+    }
+    __syncthreads();
   }
   // ---- top plane 2 nz (only the layer below contributes)
   if (kend == nz) {
-    __syncthreads();
-    for (int idx = tid; idx < 3 * nplane; idx += 64) {
+    for (int idx = tid; idx < 3 * nplane; idx += NT) {
       const int c = idx / nplane;
       const int r2 = idx - c * nplane;
       const int mx = 2 * i0 + r2 % nmx, my = 2 * j0 + r2 / nmx, mz = 2 * nz;
-      const long long go = c * nu1 + mx + sy * my + sz * mz;
+      const int go = c * nu1 + mx + sy * my + sz * mz;
       T v;
       if (ugrid_fixed(3, J.su, c, mx, my, mz)) {
-        v = J.mode == 0 ? J.X[go] : T(0);
+        v = J.mode == 0 ? J.X[go] : J.Bv[go];
       } else {
         const bool xo = mx & 1, yo = my & 1;
         const int cx0 = xo ? (mx - 1) / 2 : mx / 2 - 1, ax0 = xo ? 1 : 2;
@@ -228,43 +202,48 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
         for (int q = 0; q < 4; ++q) {
           const int qx = q & 1, qy = q >> 1;
           if (!((qy ? vy1 : vy0) && (qx ? vx1 : vx0))) continue;
-          const int t = (ty0 + qy) * kT3 + tx0 + qx;
-          const int a = qx ? 0 : ax0, b = qy ? 0 : ay0;
-          v += C[c * 9 + b * 3 + a][t];
+          const int cell = (ty0 + qy) * kT3 + tx0 + qx;
+          v += Cc[(c * 9 + (qy ? 0 : ay0) * 3 + (qx ? 0 : ax0)) * NC + cell];
         }
+        if (J.mode != 0) v = J.Bv[go] - v;
       }
-      J.Y[go] = J.mode == 0 ? v : J.Bv[go] - v;
+      J.Y[go] = v;
     }
   }
 }
 
 // operator apply: u-rows of time level blockIdx.y
 template <typename T, int NL, bool TR>
-__global__ __launch_bounds__(64) void apply3d_u_kernel(const InstDev* __restrict__ insts, const int4* __restrict__ work,
-                                                       TimeMat tm, const T* __restrict__ X, T* __restrict__ Y) {
+__global__ __launch_bounds__(64 * kW3) void apply3d_u_kernel(const InstDev* __restrict__ insts,
+                                                             const int4* __restrict__ work, TimeMat tm,
+                                                             const T* __restrict__ emat, const T* __restrict__ X,
+                                                             T* __restrict__ Y) {
   const int4 w = work[blockIdx.x];
   const InstDev& I = insts[w.x];
   const int lev = blockIdx.y;
   U3Job<T> J;
-  for (int e = 0; e < 3; ++e) { J.n[e] = I.n[e]; J.su[e] = I.su[e]; J.h[e] = T(I.h[e]); }
-  J.tau = T(I.tau); J.lam = T(I.lam); J.mu = T(I.mu);
+  for (int e = 0; e < 3; ++e) { J.n[e] = I.n[e]; J.su[e] = I.su[e]; }
+  J.A = emat + I.emat_off;
   J.X = X + I.x_off + lev * I.N + I.off_u[0];
   J.Y = Y + I.x_off + lev * I.N + I.off_u[0];
   J.Bv = nullptr;
   J.mode = 0;
   J.P = X + I.x_off + I.off_p;
   J.plstride = I.N;
-  J.npl = NL;
   J.sp[0] = I.sp[0]; J.sp[1] = I.sp[1];
   for (int l = 0; l < 4; ++l) J.pw[l] = T(0);
   if (!TR) {
-    for (int l = 0; l < NL; ++l) J.pw[l] = (l == lev) ? T(1) : T(0);
+    // forward: the coupling uses the pressure of the same level only
+    J.P += lev * I.N;
+    J.npl = 1;
+    J.pw[0] = T(1);
     J.cp = T(I.tau * I.b);
   } else {
+    J.npl = NL;
     for (int l = 0; l < NL; ++l) J.pw[l] = T(tm.T[l * 4 + lev]);
     J.cp = T(I.b);
   }
-  u3_run<T>(J, w.y * kO3, w.z * kO3, w.w * kZC);
+  u3_run<T, 23>(J, w.y * kO3, w.z * kO3, w.w * kZC, kZC);
 }
 
 // q-rows: tau (Mq q + B p), identity on essential rows
@@ -276,62 +255,103 @@ __global__ __launch_bounds__(256) void qrows_kernel(const InstDev* __restrict__ 
   const T* Xl = X + I.x_off + lev * I.N;
   T* Yl = Y + I.x_off + lev * I.N;
   const T* kc = kinv + I.cell_off;
-  for (long long t = I.off_q[0] + (long long)blockIdx.x * blockDim.x + threadIdx.x; t < I.off_p;
-       t += (long long)gridDim.x * blockDim.x) {
+  const int q0 = (int)I.off_q[0], q1 = (int)I.off_p;
+  for (int t = q0 + blockIdx.x * blockDim.x + threadIdx.x; t < q1; t += gridDim.x * blockDim.x) {
     int blk, comp, co[3];
     decode_dof(I, t, blk, comp, co);
     if (q_fixed(I, comp, co[comp])) { Yl[t] = Xl[t]; continue; }
-    T dg;
-    Yl[t] = mq_node<T>(I, kc, Xl, comp, co, dg) + T(I.tau) * bp_node<T>(I, Xl, comp, co);
+    T mq, dg, bp;
+    flux_row<T>(I, kc, Xl, comp, co, t - (int)I.off_q[comp], mq, dg, bp);
+    Yl[t] = mq + T(I.tau) * bp;
   }
 }
 
-// p-rows of every time level, one thread per cell
-template <typename T, int NL, bool TR, int DIM>
-__global__ __launch_bounds__(256) void prows_kernel(const InstDev* __restrict__ insts, TimeMat tm,
-                                                    const T* __restrict__ X, T* __restrict__ Y) {
+// p-rows in two passes (few live registers per thread):
+//  pass 1, one thread per (cell, level l):
+//    forward:    Y_l(p) = b div u_l + p_l / M           (zeta_l, staged in Y)
+//    transposed: Y_l(p) = -w tau (div q_l + b div u_l)
+//  pass 2, one thread per cell, all levels:
+//    forward:    Y_l(p) = -w (tau div q_l + sum_j T_lj zeta_j)
+//    transposed: Y_l(p) += -w sum_j T_jl p_j / M
+template <typename T, bool TR, int DIM>
+__global__ __launch_bounds__(256) void prows_local_kernel(const InstDev* __restrict__ insts, const T* __restrict__ X,
+                                                          T* __restrict__ Y) {
   constexpr int NG = 1 << DIM;
   const InstDev& I = insts[blockIdx.y];
-  for (long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x; cell < I.ncells;
-       cell += (long long)gridDim.x * blockDim.x) {
-    const int ce[3] = {(int)(cell % I.n[0]), (int)((cell / I.n[0]) % I.n[1]),
-                       DIM == 3 ? (int)(cell / ((long long)I.n[0] * I.n[1])) : 0};
-    long long po[NG];
-#pragma unroll
-    for (int g = 0; g < NG; ++g)
-      po[g] = p_index(I, 2 * ce[0] + (g & 1), 2 * ce[1] + ((g >> 1) & 1), DIM == 3 ? 2 * ce[2] + (g >> 2) : 0);
-    T w = 1;
-#pragma unroll
-    for (int e = 0; e < DIM; ++e) w *= T(0.5 * I.h[e]);
-    T acc[NL][NG];
-#pragma unroll
-    for (int l = 0; l < NL; ++l)
-#pragma unroll
-      for (int g = 0; g < NG; ++g) acc[l][g] = 0;
-#pragma unroll
-    for (int j = 0; j < NL; ++j) {
-      const T* Xj = X + I.x_off + j * I.N;
-      T du[NG], dq[NG];
-      cell_div<T, DIM>(I, Xj, ce, du, dq);
+  const int l = blockIdx.z;
+  const int nc = (int)I.ncells;
+  const unsigned n0 = I.n[0], n1 = I.n[1];
+  const T* Xl = X + I.x_off + l * I.N;
+  T* Yl = Y + I.x_off + l * I.N;
+  const T w = T(DIM == 3 ? 0.125 * I.h[0] * I.h[1] * I.h[2] : 0.25 * I.h[0] * I.h[1]);
+  for (int cell = blockIdx.x * blockDim.x + threadIdx.x; cell < nc; cell += gridDim.x * blockDim.x) {
+    const unsigned q = (unsigned)cell / n0;
+    const int ce[3] = {(int)((unsigned)cell - q * n0), (int)(q % n1), DIM == 3 ? (int)(q / n1) : 0};
+    const int pb = (int)I.off_p + 2 * ce[0] + I.sp[0] * (2 * ce[1] + I.sp[1] * (DIM == 3 ? 2 * ce[2] : 0));
+    T du[NG];
+    cell_divu<T, DIM>(I, Xl, ce, du);
+    if (!TR) {
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
-        const T pj = Xj[po[g]];
-        if (!TR) {
-          const T z = T(I.b) * du[g] + T(I.Minv) * pj;
+        const int o = pb + (g & 1) + I.sp[0] * (((g >> 1) & 1) + I.sp[1] * ((g >> 2) & 1));
+        Yl[o] = T(I.b) * du[g] + T(I.Minv) * Xl[o];
+      }
+    } else {
+      T dq[NG];
+      cell_divq<T, DIM>(I, Xl, ce, dq);
 #pragma unroll
-          for (int l = 0; l < NL; ++l) acc[l][g] += T(tm.T[l * 4 + j]) * z + ((l == j) ? T(I.tau) * dq[g] : T(0));
-        } else {
+      for (int g = 0; g < NG; ++g) {
+        const int o = pb + (g & 1) + I.sp[0] * (((g >> 1) & 1) + I.sp[1] * ((g >> 2) & 1));
+        Yl[o] = -w * T(I.tau) * (dq[g] + T(I.b) * du[g]);
+      }
+    }
+  }
+}
+
+template <typename T, int NL, bool TR, int DIM>
+__global__ __launch_bounds__(256) void prows_mix_kernel(const InstDev* __restrict__ insts, TimeMat tm,
+                                                        const T* __restrict__ X, T* __restrict__ Y) {
+  constexpr int NG = 1 << DIM;
+  const InstDev& I = insts[blockIdx.y];
+  const int nc = (int)I.ncells;
+  const unsigned n0 = I.n[0], n1 = I.n[1];
+  const T w = T(DIM == 3 ? 0.125 * I.h[0] * I.h[1] * I.h[2] : 0.25 * I.h[0] * I.h[1]);
+  for (int cell = blockIdx.x * blockDim.x + threadIdx.x; cell < nc; cell += gridDim.x * blockDim.x) {
+    const unsigned q = (unsigned)cell / n0;
+    const int ce[3] = {(int)((unsigned)cell - q * n0), (int)(q % n1), DIM == 3 ? (int)(q / n1) : 0};
+    const int pb = (int)I.off_p + 2 * ce[0] + I.sp[0] * (2 * ce[1] + I.sp[1] * (DIM == 3 ? 2 * ce[2] : 0));
+    int po[NG];
 #pragma unroll
-          for (int l = 0; l < NL; ++l)
-            acc[l][g] += T(tm.T[j * 4 + l]) * T(I.Minv) * pj +
-                         ((l == j) ? T(I.tau) * (dq[g] + T(I.b) * du[g]) : T(0));
+    for (int g = 0; g < NG; ++g) po[g] = pb + (g & 1) + I.sp[0] * (((g >> 1) & 1) + I.sp[1] * ((g >> 2) & 1));
+    T v[NL][NG];   // forward: zeta_j; transposed: p_j / M
+#pragma unroll
+    for (int j = 0; j < NL; ++j)
+#pragma unroll
+      for (int g = 0; g < NG; ++g)
+        v[j][g] = TR ? T(I.Minv) * X[I.x_off + j * I.N + po[g]] : Y[I.x_off + j * I.N + po[g]];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      T* Yl = Y + I.x_off + l * I.N;
+      if (!TR) {
+        T dq[NG];
+        cell_divq<T, DIM>(I, X + I.x_off + l * I.N, ce, dq);
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+          T s = T(I.tau) * dq[g];
+#pragma unroll
+          for (int j = 0; j < NL; ++j) s += T(tm.T[l * 4 + j]) * v[j][g];
+          Yl[po[g]] = -w * s;
+        }
+      } else {
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+          T s = 0;
+#pragma unroll
+          for (int j = 0; j < NL; ++j) s += T(tm.T[j * 4 + l]) * v[j][g];
+          Yl[po[g]] += -w * s;
         }
       }
     }
-#pragma unroll
-    for (int l = 0; l < NL; ++l)
-#pragma unroll
-      for (int g = 0; g < NG; ++g) Y[I.x_off + l * I.N + po[g]] = -w * acc[l][g];
   }
 }
 
@@ -344,18 +364,23 @@ template <typename T, int NL>
 static void apply3d_nl(const ApplyArgs& a, const void* x, void* y, int tr, long long maxN, long long maxc, int count) {
   const T* X = (const T*)x;
   T* Y = (T*)y;
+  const T* em = (const T*)a.emat;
   if (tr)
-    hipLaunchKernelGGL((apply3d_u_kernel<T, NL, true>), dim3(a.nwork, NL), dim3(64), 0, a.stream, a.inst, a.work, *a.tm,
-                       X, Y);
+    hipLaunchKernelGGL((apply3d_u_kernel<T, NL, true>), dim3(a.nwork, NL), dim3(64 * kW3), 0, a.stream, a.inst,
+                       a.work, *a.tm, em, X, Y);
   else
-    hipLaunchKernelGGL((apply3d_u_kernel<T, NL, false>), dim3(a.nwork, NL), dim3(64), 0, a.stream, a.inst, a.work,
-                       *a.tm, X, Y);
+    hipLaunchKernelGGL((apply3d_u_kernel<T, NL, false>), dim3(a.nwork, NL), dim3(64 * kW3), 0, a.stream, a.inst,
+                       a.work, *a.tm, em, X, Y);
   hipLaunchKernelGGL((qrows_kernel<T>), g3(maxN, count, NL), dim3(256), 0, a.stream, a.inst, (const T*)a.kinv, X, Y);
-  if (tr)
-    hipLaunchKernelGGL((prows_kernel<T, NL, true, 3>), g3(maxc, count, 1), dim3(256), 0, a.stream, a.inst, *a.tm, X, Y);
-  else
-    hipLaunchKernelGGL((prows_kernel<T, NL, false, 3>), g3(maxc, count, 1), dim3(256), 0, a.stream, a.inst, *a.tm, X,
-                       Y);
+  if (tr) {
+    hipLaunchKernelGGL((prows_local_kernel<T, true, 3>), g3(maxc, count, NL), dim3(256), 0, a.stream, a.inst, X, Y);
+    hipLaunchKernelGGL((prows_mix_kernel<T, NL, true, 3>), g3(maxc, count, 1), dim3(256), 0, a.stream, a.inst, *a.tm,
+                       X, Y);
+  } else {
+    hipLaunchKernelGGL((prows_local_kernel<T, false, 3>), g3(maxc, count, NL), dim3(256), 0, a.stream, a.inst, X, Y);
+    hipLaunchKernelGGL((prows_mix_kernel<T, NL, false, 3>), g3(maxc, count, 1), dim3(256), 0, a.stream, a.inst,
+                       *a.tm, X, Y);
+  }
 }
 
 template <typename T>
@@ -372,15 +397,17 @@ template void launch_apply3d<float>(const ApplyArgs&, const void*, void*, int);
 
 // elasticity multigrid level: y = tau A x (mode 0) or y = b - tau A x (mode 1)
 template <typename T>
-__global__ __launch_bounds__(64) void uapply3d_kernel(const UGridSeg* __restrict__ segs, const int4* __restrict__ work,
-                                                      int mode, const T* __restrict__ X, const T* __restrict__ Bv,
-                                                      T* __restrict__ Y) {
+__global__ __launch_bounds__(64 * kW3) void uapply3d_kernel(const UGridSeg* __restrict__ segs,
+                                                            const int4* __restrict__ work, int mode,
+                                                            const T* __restrict__ emat, const T* __restrict__ X,
+                                                            const T* __restrict__ Bv, T* __restrict__ Y) {
   const int4 w = work[blockIdx.x];
   const UGridSeg& G = segs[w.x];
   const long long vo = G.voff + blockIdx.y * G.vjstride;
   U3Job<T> J;
-  for (int e = 0; e < 3; ++e) { J.n[e] = G.n[e]; J.su[e] = G.su[e]; J.h[e] = T(G.h[e]); }
-  J.tau = T(G.tau); J.lam = T(G.lam); J.mu = T(G.mu); J.cp = T(0);
+  for (int e = 0; e < 3; ++e) { J.n[e] = G.n[e]; J.su[e] = G.su[e]; }
+  J.A = emat + G.emat_off;
+  J.cp = T(0);
   J.X = X + vo;
   J.Y = Y + vo;
   J.Bv = Bv ? Bv + vo : nullptr;
@@ -390,16 +417,16 @@ __global__ __launch_bounds__(64) void uapply3d_kernel(const UGridSeg* __restrict
   J.npl = 0;
   J.sp[0] = 1; J.sp[1] = 1;
   for (int l = 0; l < 4; ++l) J.pw[l] = T(0);
-  u3_run<T>(J, w.y * kO3, w.z * kO3, w.w * kZC);
+  u3_run<T, 21>(J, w.y * kO3, w.z * kO3, w.w * kZC, kZC);
 }
 template <typename T>
 void launch_uapply3d(const UGridSeg* segs, const int4* work, int nwork, int nj, int mode, const T* x, const T* b, T* y,
-                     hipStream_t s) {
-  hipLaunchKernelGGL((uapply3d_kernel<T>), dim3(nwork, nj), dim3(64), 0, s, segs, work, mode, x, b, y);
+                     const T* emat, hipStream_t s) {
+  hipLaunchKernelGGL((uapply3d_kernel<T>), dim3(nwork, nj), dim3(64 * kW3), 0, s, segs, work, mode, emat, x, b, y);
 }
 template void launch_uapply3d<double>(const UGridSeg*, const int4*, int, int, int, const double*, const double*,
-                                      double*, hipStream_t);
+                                      double*, const double*, hipStream_t);
 template void launch_uapply3d<float>(const UGridSeg*, const int4*, int, int, int, const float*, const float*, float*,
-                                     hipStream_t);
+                                     const float*, hipStream_t);
 
 }  // namespace bt

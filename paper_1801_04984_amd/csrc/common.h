@@ -75,7 +75,7 @@ struct InstDev {
   long long cell_off;    // offset into per-cell arrays
   long long state_off;   // offset into state (one level) vectors
   long long ncells;
-  long long emat_off;    // 2D: tau*A_e (18x18) then E_e (18x4) in the element-matrix array
+  long long emat_off;    // element matrices of the instance (2D: tau*A_e, E_e; 3D: matrix-core fragments)
 };
 
 // temporal matrices shared by a batch (same r)

@@ -66,4 +66,27 @@ std::vector<double> coupling_element(int d, const double* hh) {
   return E;
 }
 
+// 3D matrix-core layout of the element matrix [tau A_e | E_e] (81 x 81 or
+// 81 x 89 with the coupling columns).  Rows are padded per component to 32
+// (component c in padded rows 32c .. 32c+26), columns to a multiple of 4.
+// Six 16-row tiles, tile w = (component w/2, half w%2); for k-step s and
+// lane l the value is the entry at row 16 (w%2) + (l % 16) of that component
+// and column 4 s + l / 16 (the A-operand layout of a 16x16x4 MFMA).
+std::vector<double> elast_fragments3d(const std::vector<double>& A, const std::vector<double>* E) {
+  const int ks = E ? 23 : 21;
+  std::vector<double> out((size_t)6 * ks * 64, 0.0);
+  for (int w = 0; w < 6; ++w)
+    for (int s = 0; s < ks; ++s)
+      for (int l = 0; l < 64; ++l) {
+        const int pr = 16 * (w % 2) + (l % 16), col = 4 * s + l / 16;
+        if (pr >= 27) continue;
+        const int row = (w / 2) * 27 + pr;
+        double v = 0.0;
+        if (col < 81) v = A[(size_t)row * 81 + col];
+        else if (E && col < 89) v = (*E)[(size_t)row * 8 + (col - 81)];
+        out[((size_t)w * ks + s) * 64 + l] = v;
+      }
+  return out;
+}
+
 }  // namespace bt

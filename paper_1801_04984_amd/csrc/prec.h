@@ -96,7 +96,7 @@ struct UGridSeg {
   long long voff, vjstride;    // u block of time level j: voff + j*vjstride, components contiguous
   long long doff;              // Dinv (normalised), shared by all time levels
   long long nu;                // dim * prod(su)
-  long long emat_off;          // 2D: tau*A_e (18x18) in the element-matrix array
+  long long emat_off;          // tau*A_e of the level (2D 18x18; 3D matrix-core fragments)
 };
 // one separable restriction pass along `axis` (input dims din -> output dims dout)
 struct RPass {
@@ -118,7 +118,7 @@ void launch_uapply(int dim, const UGridSeg* segs, const int4* work, int nwork, i
 int uapply_tile(int dim);
 template <typename T>
 void launch_uapply3d(const UGridSeg* segs, const int4* work, int nwork, int nj, int mode, const T* x, const T* b,
-                     T* y, hipStream_t s);
+                     T* y, const T* emat, hipStream_t s);
 template <typename T>
 void launch_rpass(const RPass* segs, int nseg, int nj, long long maxout, const double* tab, const T* in, T* out,
                   hipStream_t s);

@@ -12,6 +12,7 @@
 // no constant mode), a Dirichlet-type term on the drained top face, and the
 // cell mass.  Further levels aggregate 2^d cells (sums of coefficients).
 #include "prec.h"
+#include "rows.h"
 
 namespace bt {
 
@@ -155,12 +156,10 @@ __global__ __launch_bounds__(256) void pdg_kernel(const InstDev* __restrict__ in
   const T* dqi = dqinv + sg.dqoff;
   const T cm = T(sg.cm[j]);
   const long long pstr[3] = {1, (long long)I.sp[0], (long long)I.sp[0] * I.sp[1]};
-  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < I.ncells;
-       c += (long long)gridDim.x * blockDim.x) {
+  const int ncl = (int)I.ncells;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncl; c += gridDim.x * blockDim.x) {
     int ce[3];
-    ce[0] = (int)(c % I.n[0]);
-    ce[1] = (int)((c / I.n[0]) % I.n[1]);
-    ce[2] = DIM == 3 ? (int)(c / ((long long)I.n[0] * I.n[1])) : 0;
+    unrank((unsigned)c, I.n, ce);
     long long base = 0;
 #pragma unroll
     for (int e = 0; e < DIM; ++e) base += (long long)(2 * ce[e]) * pstr[e];
@@ -252,11 +251,11 @@ void launch_pdg_diag(int dim, const InstDev* insts, const PDgSeg* segs, int nseg
 // ---- cell levels ------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void pcell_eval(const PCellSeg& sg, const T* __restrict__ coef, const T* __restrict__ x,
-                                           long long c, T cm, T& Sx, T& diag) {
+                                           int c, T cm, T& Sx, T& diag) {
   const long long nc = sg.ncells;
-  const int i = c % sg.n[0];
-  const int jy = (c / sg.n[0]) % sg.n[1];
-  const int k = sg.dim == 3 ? (int)(c / ((long long)sg.n[0] * sg.n[1])) : 0;
+  int ce3[3];
+  unrank((unsigned)c, sg.n, ce3);
+  const int i = ce3[0], jy = ce3[1], k = ce3[2];
   const T* C = coef + sg.coff;
   const T xc = x[c];
   T dg = cm * C[4 * nc + c] + C[3 * nc + c];
@@ -289,8 +288,8 @@ __global__ __launch_bounds__(256) void pcell_kernel(const PCellSeg* __restrict__
   const long long vo = sg.voff + j * sg.vjstride;
   const long long dof = sg.doff + j * sg.djstride;
   const T cm = T(sg.cm[j]);
-  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < sg.ncells;
-       c += (long long)gridDim.x * blockDim.x) {
+  const int ncl = (int)sg.ncells;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncl; c += gridDim.x * blockDim.x) {
     const T di = dinv[dof + c];
     if (mode == kResInitZero) {
       const T rr = T(cc.bsign) * b[vo + c];
@@ -446,10 +445,11 @@ __global__ __launch_bounds__(256) void p_restrict_dg_kernel(const InstDev* __res
   const T* R = r + fs.voff + j * fs.vjstride;
   T* Bc = b + cs.voff + j * cs.vjstride;
   const int d = I.dim;
-  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < cs.ncells;
-       c += (long long)gridDim.x * blockDim.x) {
-    const int i = c % I.n[0], jy = (c / I.n[0]) % I.n[1];
-    const int k = d == 3 ? (int)(c / ((long long)I.n[0] * I.n[1])) : 0;
+  const int ncl = (int)cs.ncells;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncl; c += gridDim.x * blockDim.x) {
+    int ce3[3];
+    unrank((unsigned)c, I.n, ce3);
+    const int i = ce3[0], jy = ce3[1], k = ce3[2];
     T s = 0;
     for (int g = 0; g < (d == 3 ? 8 : 4); ++g) {
       const long long o = (2 * i + (g & 1)) + (long long)I.sp[0] * ((2 * jy + ((g >> 1) & 1)) +
@@ -470,9 +470,11 @@ __global__ __launch_bounds__(256) void p_prolong_dg_kernel(const InstDev* __rest
   const long long np = (long long)I.sp[0] * I.sp[1] * I.sp[2];
   T* X = x + fs.voff + j * fs.vjstride;
   const T* Ec = e + cs.voff + j * cs.vjstride;
-  for (long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x; o < np; o += (long long)gridDim.x * blockDim.x) {
-    const int ox = o % I.sp[0], oy = (o / I.sp[0]) % I.sp[1];
-    const int oz = I.dim == 3 ? (int)(o / ((long long)I.sp[0] * I.sp[1])) : 0;
+  const int npi = (int)np;
+  for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < npi; o += gridDim.x * blockDim.x) {
+    int oc[3];
+    unrank((unsigned)o, I.sp, oc);
+    const int ox = oc[0], oy = oc[1], oz = oc[2];
     const long long c = (ox >> 1) + (long long)I.n[0] * ((oy >> 1) + (long long)I.n[1] * (oz >> 1));
     X[o] += T(w) * Ec[c];
   }
@@ -486,10 +488,10 @@ __global__ __launch_bounds__(256) void p_restrict_cell_kernel(const PCellSeg* __
   const T* R = r + fs.voff + j * fs.vjstride;
   T* Bc = b + cs.voff + j * cs.vjstride;
   const int d = cs.dim;
-  for (long long C = (long long)blockIdx.x * blockDim.x + threadIdx.x; C < cs.ncells;
-       C += (long long)gridDim.x * blockDim.x) {
-    const int Ce[3] = {(int)(C % cs.n[0]), (int)((C / cs.n[0]) % cs.n[1]),
-                       d == 3 ? (int)(C / ((long long)cs.n[0] * cs.n[1])) : 0};
+  const int ncc = (int)cs.ncells;
+  for (int C = blockIdx.x * blockDim.x + threadIdx.x; C < ncc; C += gridDim.x * blockDim.x) {
+    int Ce[3];
+    unrank((unsigned)C, cs.n, Ce);
     T s = 0;
     for (int dz = 0; dz < (d == 3 ? 2 : 1); ++dz)
       for (int dy = 0; dy < 2; ++dy)
@@ -509,10 +511,11 @@ __global__ __launch_bounds__(256) void p_prolong_cell_kernel(const PCellSeg* __r
   const int j = blockIdx.z;
   T* X = x + fs.voff + j * fs.vjstride;
   const T* Ec = e + cs.voff + j * cs.vjstride;
-  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < fs.ncells;
-       c += (long long)gridDim.x * blockDim.x) {
-    const int i = c % fs.n[0], jy = (c / fs.n[0]) % fs.n[1];
-    const int k = fs.dim == 3 ? (int)(c / ((long long)fs.n[0] * fs.n[1])) : 0;
+  const int ncf = (int)fs.ncells;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncf; c += gridDim.x * blockDim.x) {
+    int ce3[3];
+    unrank((unsigned)c, fs.n, ce3);
+    const int i = ce3[0], jy = ce3[1], k = ce3[2];
     X[c] += T(w) * Ec[(i >> 1) + (long long)cs.n[0] * ((jy >> 1) + (long long)cs.n[1] * (k >> 1))];
   }
 }

@@ -11,6 +11,7 @@
 // flux component's own axis (the open basis is orthogonal under 2-point
 // Gauss) with the cellwise eta/K.
 #include "prec.h"
+#include "rows.h"
 
 namespace bt {
 
@@ -19,107 +20,28 @@ static dim3 grid3(long long maxlen, int nseg, int nj) {
   return dim3((unsigned)(b < 1 ? 1 : (b > 65535 ? 65535 : b)), nseg, nj);
 }
 
-__device__ __forceinline__ void decode(const InstDev& I, long long t, int& blk, int& comp, int co[3]) {
-  // blk: 0 = u, 1 = q, 2 = p
-  const int d = I.dim;
-  if (t >= I.off_p) {
-    blk = 2; comp = 0;
-    long long rem = t - I.off_p;
-    for (int f = 0; f < 3; ++f) { co[f] = rem % I.sp[f]; rem /= I.sp[f]; }
-    return;
-  }
-  if (t >= I.off_q[0]) {
-    blk = 1; comp = 0;
-    for (int c = 1; c < d; ++c)
-      if (t >= I.off_q[c]) comp = c;
-    long long rem = t - I.off_q[comp];
-    for (int f = 0; f < 3; ++f) { co[f] = rem % I.sq[comp][f]; rem /= I.sq[comp][f]; }
-    return;
-  }
-  blk = 0;
-  comp = 0;
-  for (int c = 1; c < d; ++c)
-    if (t >= I.off_u[c]) comp = c;
-  long long rem = t - I.off_u[comp];
-  for (int f = 0; f < 3; ++f) { co[f] = rem % I.su[f]; rem /= I.su[f]; }
-}
-
-__device__ __forceinline__ long long pidx(const InstDev& I, int ox, int oy, int oz) {
-  return I.off_p + ox + (long long)I.sp[0] * (oy + (long long)I.sp[1] * oz);
-}
-
-template <typename T>
-__device__ T bp_at(const InstDev& I, const T* P, int e, const int co[3]) {
-  // (B p) at flux node of component e with coordinates co (closed along e)
-  const int d = I.dim;
-  double hp = 1.0;
-  for (int f = 0; f < d; ++f)
-    if (f != e) hp *= 0.5 * I.h[f];
-  const int m = co[e];
-  double s = 0.0;
-  for (int side = 0; side < 2; ++side) {
-    int ce, a;
-    if (m & 1) { if (side) break; ce = (m - 1) / 2; a = 1; }
-    else { ce = m / 2 - 1 + side; a = side ? 0 : 2; if (ce < 0 || ce >= I.n[e]) continue; }
-    int o[3] = {co[0], co[1], co[2]};
-    o[e] = 2 * ce;
-    const double p0 = (double)P[pidx(I, o[0], o[1], o[2])];
-    o[e] = 2 * ce + 1;
-    const double p1 = (double)P[pidx(I, o[0], o[1], o[2])];
-    s += GB(a, 0) * p0 + GB(a, 1) * p1;
-  }
-  return (T)(-hp * s);
-}
-
-template <typename T>
-__device__ T ep_at(const InstDev& I, const T* P, int c, const int co[3]) {
-  // (E p) at the u_c node co: sum over cells sharing the node, Gauss-2 collocation
-  const int d = I.dim;
-  int cl[3][2], al[3][2], nl[3];
-  for (int f = 0; f < 3; ++f) {
-    nl[f] = 0;
-    if (f >= d) { cl[f][0] = 0; al[f][0] = 0; nl[f] = 1; continue; }
-    const int m = co[f];
-    if (m & 1) { cl[f][0] = (m - 1) / 2; al[f][0] = 1; nl[f] = 1; }
-    else {
-      if (m / 2 - 1 >= 0) { cl[f][nl[f]] = m / 2 - 1; al[f][nl[f]] = 2; ++nl[f]; }
-      if (m / 2 < I.n[f]) { cl[f][nl[f]] = m / 2; al[f][nl[f]] = 0; ++nl[f]; }
-    }
-  }
-  double s = 0.0;
-  for (int iz = 0; iz < nl[2]; ++iz)
-    for (int iy = 0; iy < nl[1]; ++iy)
-      for (int ix = 0; ix < nl[0]; ++ix) {
-        const int cc[3] = {cl[0][ix], cl[1][iy], cl[2][iz]};
-        const int aa[3] = {al[0][ix], al[1][iy], al[2][iz]};
-        for (int g = 0; g < (d == 3 ? 8 : 4); ++g) {
-          const int gg[3] = {g & 1, (g >> 1) & 1, (g >> 2) & 1};
-          double w = 1.0;
-          for (int f = 0; f < d; ++f) w *= (f == c) ? GB(aa[f], gg[f]) : 0.5 * I.h[f] * VG(gg[f], aa[f]);
-          s += w * (double)P[pidx(I, 2 * cc[0] + gg[0], 2 * cc[1] + gg[1], d == 3 ? 2 * cc[2] + gg[2] : 0)];
-        }
-      }
-  return (T)s;
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void coupling_kernel(const InstDev* __restrict__ insts, const T* __restrict__ rt, const T* __restrict__ zp,
-                                T* __restrict__ fu, T* __restrict__ fq) {
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void coupling_kernel(const InstDev* __restrict__ insts, const T* __restrict__ rt,
+                                                       const T* __restrict__ zp, T* __restrict__ fu,
+                                                       T* __restrict__ fq) {
   const InstDev& I = insts[blockIdx.y];
   const int j = blockIdx.z;
   const long long lo = I.x_off + j * I.N;
-  const T* P = zp + lo;
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < I.off_p;
-       t += (long long)gridDim.x * blockDim.x) {
+  const T* P = zp + lo + I.off_p;
+  const int nuq = (int)I.off_p;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nuq; t += gridDim.x * blockDim.x) {
     int blk, comp, co[3];
-    decode(I, t, blk, comp, co);
+    decode_dof(I, t, blk, comp, co);
+    T v = 0;
     if (blk == 0) {
-      T v = 0;
-      if (!u_fixed(I, comp, co[0], co[1], co[2])) v = rt[lo + t] + T(I.b * I.tau) * ep_at<T>(I, P, comp, co);
+      if (!u_fixed(I, comp, co[0], co[1], co[2])) v = rt[lo + t] + T(I.b * I.tau) * ep_node<T, DIM>(I, P, comp, co);
       fu[lo + t] = v;
     } else {
-      T v = 0;
-      if (!q_fixed(I, comp, co[comp])) v = rt[lo + t] - T(I.tau) * bp_at<T>(I, P, comp, co);
+      if (!q_fixed(I, comp, co[comp])) {
+        T mq, dg, bp;
+        flux_row<T, false>(I, nullptr, zp + lo, comp, co, t - (int)I.off_q[comp], mq, dg, bp);
+        v = rt[lo + t] - T(I.tau) * bp;
+      }
       fq[lo + t] = v;
     }
   }
@@ -127,8 +49,10 @@ __global__ __launch_bounds__(256) void coupling_kernel(const InstDev* __restrict
 template <typename T>
 void launch_coupling(int dim, const InstDev* insts, int count, int nj, long long maxN, const T* rt, const T* zp, T* fu,
                      T* fq, hipStream_t s) {
-  (void)dim;
-  hipLaunchKernelGGL((coupling_kernel<T>), grid3(maxN, count, nj), dim3(256), 0, s, insts, rt, zp, fu, fq);
+  if (dim == 2)
+    hipLaunchKernelGGL((coupling_kernel<T, 2>), grid3(maxN, count, nj), dim3(256), 0, s, insts, rt, zp, fu, fq);
+  else
+    hipLaunchKernelGGL((coupling_kernel<T, 3>), grid3(maxN, count, nj), dim3(256), 0, s, insts, rt, zp, fu, fq);
 }
 template void launch_coupling<double>(int, const InstDev*, int, int, long long, const double*, const double*,
                                       double*, double*, hipStream_t);
@@ -137,79 +61,41 @@ template void launch_coupling<float>(int, const InstDev*, int, int, long long, c
 
 // ---- tau Mq and its Chebyshev solve ---------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ T mq_at(const InstDev& I, const T* kc, const T* X, int e, const int co[3], T& dg) {
-  const int d = I.dim;
-  T hp = 1;
-  for (int f = 0; f < d; ++f)
-    if (f != e) hp *= T(0.5 * I.h[f]);
-  const int m = co[e];
-  const long long qstr_e = e == 0 ? 1 : (e == 1 ? (long long)I.sq[e][0] : (long long)I.sq[e][0] * I.sq[e][1]);
-  long long base = I.off_q[e];
-  {
-    long long s = 1;
-    for (int f = 0; f < d; ++f) {
-      if (f != e) base += (long long)co[f] * s;
-      s *= I.sq[e][f];
-    }
-  }
-  T acc = 0;
-  dg = 0;
-  for (int side = 0; side < 2; ++side) {
-    int ce, a;
-    if (m & 1) { if (side) break; ce = (m - 1) / 2; a = 1; }
-    else { ce = m / 2 - 1 + side; a = side ? 0 : 2; if (ce < 0 || ce >= I.n[e]) continue; }
-    int cc[3] = {co[0] >> 1, co[1] >> 1, co[2] >> 1};
-    cc[e] = ce;
-    const long long cell = cc[0] + (long long)I.n[0] * (cc[1] + (long long)I.n[1] * (d == 3 ? cc[2] : 0));
-    const T f = kc[cell] * T(I.tau * I.h[e]) * hp;
-    T s = 0;
-    for (int a2 = 0; a2 < 3; ++a2) {
-      const int m2 = 2 * ce + a2;
-      if (q_fixed(I, e, m2)) continue;
-      s += T(MC(a, a2)) * X[base + m2 * qstr_e];
-    }
-    acc += f * s;
-    dg += f * T(MC(a, a));
-  }
-  return acc;
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void mq_kernel(const InstDev* __restrict__ insts, int mode, ChebCoef cc, const T* __restrict__ kinv,
-                          const T* __restrict__ b, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ din,
-                          T* __restrict__ dout) {
+__global__ __launch_bounds__(256) void mq_kernel(const InstDev* __restrict__ insts, int mode, ChebCoef cc,
+                                                 const T* __restrict__ kinv, const T* __restrict__ b,
+                                                 T* __restrict__ x, T* __restrict__ r, const T* __restrict__ din,
+                                                 T* __restrict__ dout) {
   const InstDev& I = insts[blockIdx.y];
   const int j = blockIdx.z;
   const long long lo = I.x_off + j * I.N;
   const T* kc = kinv + I.cell_off;
-  for (long long t = I.off_q[0] + (long long)blockIdx.x * blockDim.x + threadIdx.x; t < I.off_p;
-       t += (long long)gridDim.x * blockDim.x) {
+  const int q0 = (int)I.off_q[0], q1 = (int)I.off_p;
+  for (int t = q0 + blockIdx.x * blockDim.x + threadIdx.x; t < q1; t += gridDim.x * blockDim.x) {
     int blk, comp, co[3];
-    decode(I, t, blk, comp, co);
+    decode_dof(I, t, blk, comp, co);
     if (q_fixed(I, comp, co[comp])) {
       if (mode == kResInitZero) { x[lo + t] = 0; r[lo + t] = 0; }
       dout[lo + t] = 0;
       continue;
     }
+    const int loc = t - (int)I.off_q[comp];
+    T Sd, dg, bp;
     if (mode == kResInitZero) {
-      T dg;
-      mq_at<T>(I, kc, b + lo, comp, co, dg);   // diagonal only
+      flux_row<T>(I, kc, b + lo, comp, co, loc, Sd, dg, bp);   // diagonal only
       const T rr = b[lo + t];
       x[lo + t] = 0;
       r[lo + t] = rr;
       dout[lo + t] = T(cc.s0) * rr / dg;
     } else if (mode == kStep) {
-      T dg;
-      const T Sd = mq_at<T>(I, kc, din + lo, comp, co, dg);
+      flux_row<T>(I, kc, din + lo, comp, co, loc, Sd, dg, bp);
       const T dd = din[lo + t];
       x[lo + t] += dd;
       const T rr = r[lo + t] - Sd;
       r[lo + t] = rr;
       dout[lo + t] = T(cc.rho) * dd + T(cc.sig) * rr / dg;
     } else {
-      T dg;
-      const T Sx = mq_at<T>(I, kc, din + lo, comp, co, dg);
-      dout[lo + t] = Sx / dg;
+      flux_row<T>(I, kc, din + lo, comp, co, loc, Sd, dg, bp);
+      dout[lo + t] = Sd / dg;
     }
   }
 }
@@ -231,9 +117,10 @@ template <typename T, int NL>
 __global__ __launch_bounds__(256) void finalize_kernel(const InstDev* __restrict__ insts, Mat4 Q, const T* __restrict__ zt,
                                 const T* __restrict__ r, T* __restrict__ z) {
   const InstDev& I = insts[blockIdx.y];
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < I.N; t += (long long)gridDim.x * blockDim.x) {
+  const int n = (int)I.N;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
     int blk, comp, co[3];
-    decode(I, t, blk, comp, co);
+    decode_dof(I, t, blk, comp, co);
     bool fixed = false;
     if (blk == 0) fixed = u_fixed(I, comp, co[0], co[1], co[2]);
     else if (blk == 1) fixed = q_fixed(I, comp, co[comp]);

@@ -10,6 +10,7 @@
 // vectors are kept zero there.
 #include "cell2d.h"
 #include "prec.h"
+#include "rows.h"
 
 namespace bt {
 
@@ -99,7 +100,7 @@ void launch_uapply(int dim, const UGridSeg* segs, const int4* work, int nwork, i
   if (dim == 2) {
     hipLaunchKernelGGL((uapply2d_kernel<T>), dim3(nwork, nj), dim3(kUT, kUT), 0, s, segs, work, mode, x, b, y, emat);
   } else {
-    launch_uapply3d<T>(segs, work, nwork, nj, mode, x, b, y, s);
+    launch_uapply3d<T>(segs, work, nwork, nj, mode, x, b, y, emat, s);
   }
 }
 template void launch_uapply<double>(int, const UGridSeg*, const int4*, int, int, int, const double*, const double*,
@@ -118,14 +119,11 @@ __global__ __launch_bounds__(256) void rpass_kernel(const RPass* __restrict__ se
   const T* I = in + P.ioff + j * P.ijstride;
   T* O = out + P.ooff + j * P.ojstride;
   const long long istr[3] = {1, (long long)P.din[0], (long long)P.din[0] * P.din[1]};
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < no * P.dim;
-       t += (long long)gridDim.x * blockDim.x) {
-    const int c = (int)(t / no);
-    long long rem = t - c * no;
+  const int nout = (int)(no * P.dim), no32 = (int)no;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nout; t += gridDim.x * blockDim.x) {
+    const int c = t >= no32 ? (t >= 2 * no32 ? 2 : 1) : 0;
     int co[3];
-    co[0] = rem % P.dout[0]; rem /= P.dout[0];
-    co[1] = rem % P.dout[1]; rem /= P.dout[1];
-    co[2] = (int)rem;
+    unrank((unsigned)(t - c * no32), P.dout, co);
     if (P.last && ugrid_fixed(P.dim, P.dout, c, co[0], co[1], co[2])) { O[t] = T(0); continue; }
     long long base = c * ni;
     for (int f = 0; f < 3; ++f)
@@ -162,14 +160,11 @@ __global__ __launch_bounds__(256) void uprolong_kernel(const UProl* __restrict__
   const long long nc = (long long)P.sc[0] * P.sc[1] * P.sc[2];
   const T* Ec = e + P.coff + j * P.cjstride;
   T* Xf = x + P.foff + j * P.fjstride;
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < nf * P.dim;
-       t += (long long)gridDim.x * blockDim.x) {
-    const int c = (int)(t / nf);
-    long long rem = t - c * nf;
+  const int nft = (int)(nf * P.dim), nf32 = (int)nf;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nft; t += gridDim.x * blockDim.x) {
+    const int c = t >= nf32 ? (t >= 2 * nf32 ? 2 : 1) : 0;
     int m[3];
-    m[0] = rem % P.sf[0]; rem /= P.sf[0];
-    m[1] = rem % P.sf[1]; rem /= P.sf[1];
-    m[2] = (int)rem;
+    unrank((unsigned)(t - c * nf32), P.sf, m);
     if (ugrid_fixed(P.dim, P.sf, c, m[0], m[1], m[2])) continue;
     const double* tx = tab + P.tab[0] + 4LL * m[0];
     const double* ty = tab + P.tab[1] + 4LL * m[1];

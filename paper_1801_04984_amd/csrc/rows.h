@@ -1,147 +1,207 @@
 // Node- and cell-local pieces of the slab operator shared by several kernels
-// (any dimension): flux-row gathers tau Mq q and B p, DoF decoding, and the
-// Gauss-2 point divergences used by the pressure rows.
+// (any dimension): DoF decoding, the flux-row gathers tau Mq q and B p, the
+// E p gather at a displacement node and the Gauss-2 point divergences used by
+// the pressure rows.  Indices within one instance's level are 32-bit (the
+// host rejects instances whose slab holds 2^31 unknowns or more).
 #pragma once
 #include "common.h"
 
 namespace bt {
 
+// coordinates of flat index t in a nodal array of sizes s (x fastest)
+__device__ __forceinline__ void unrank(unsigned t, const int* s, int co[3]) {
+  const unsigned s0 = (unsigned)s[0], s1 = (unsigned)s[1];
+  const unsigned q = t / s0;
+  const unsigned z = q / s1;
+  co[0] = (int)(t - q * s0);
+  co[1] = (int)(q - z * s1);
+  co[2] = (int)z;
+}
+
 // blk: 0 = u, 1 = q, 2 = p; comp; coordinates in the block's nodal array
-__device__ __forceinline__ void decode_dof(const InstDev& I, long long t, int& blk, int& comp, int co[3]) {
-  const int d = I.dim;
-  if (t >= I.off_p) {
+__device__ __forceinline__ void decode_dof(const InstDev& I, int t, int& blk, int& comp, int co[3]) {
+  if (t >= (int)I.off_p) {
     blk = 2; comp = 0;
-    long long rem = t - I.off_p;
-    for (int f = 0; f < 3; ++f) { co[f] = rem % I.sp[f]; rem /= I.sp[f]; }
+    unrank((unsigned)(t - (int)I.off_p), I.sp, co);
     return;
   }
-  if (t >= I.off_q[0]) {
-    blk = 1; comp = 0;
-    for (int c = 1; c < d; ++c)
-      if (t >= I.off_q[c]) comp = c;
-    long long rem = t - I.off_q[comp];
-    for (int f = 0; f < 3; ++f) { co[f] = rem % I.sq[comp][f]; rem /= I.sq[comp][f]; }
+  if (t >= (int)I.off_q[0]) {
+    blk = 1;
+    comp = (t >= (int)I.off_q[1] ? 1 : 0) + ((I.dim == 3 && t >= (int)I.off_q[2]) ? 1 : 0);
+    unrank((unsigned)(t - (int)I.off_q[comp]), I.sq[comp], co);
     return;
   }
   blk = 0;
-  comp = 0;
-  for (int c = 1; c < d; ++c)
-    if (t >= I.off_u[c]) comp = c;
-  long long rem = t - I.off_u[comp];
-  for (int f = 0; f < 3; ++f) { co[f] = rem % I.su[f]; rem /= I.su[f]; }
+  comp = (t >= (int)I.off_u[1] ? 1 : 0) + ((I.dim == 3 && t >= (int)I.off_u[2]) ? 1 : 0);
+  unrank((unsigned)(t - (int)I.off_u[comp]), I.su, co);
 }
 
-__device__ __forceinline__ long long p_index(const InstDev& I, int ox, int oy, int oz) {
-  return I.off_p + ox + (long long)I.sp[0] * (oy + (long long)I.sp[1] * oz);
+__device__ __forceinline__ int sel3(int e, const int v[3]) { return e == 0 ? v[0] : (e == 1 ? v[1] : v[2]); }
+
+// cells of the 1D node m (closed coordinate) on an axis with n cells:
+// side 0 = low cell (local node a = 2, or a = 1 for a midpoint), side 1 = high cell (a = 0)
+__device__ __forceinline__ bool node_cell(int m, int n, int side, int& c, int& a) {
+  if (m & 1) { c = m >> 1; a = 1; return side == 0; }
+  if (side == 0) { c = (m >> 1) - 1; a = 2; return c >= 0; }
+  c = m >> 1; a = 0;
+  return c < n;
 }
 
-// (B p) at the flux node of component e with coordinates co (closed along e):
-//   -hp_e sum_{cells of the node along e} sum_g GB(a, g) p(2c + g)
-template <typename T>
-__device__ T bp_node(const InstDev& I, const T* P, int e, const int co[3]) {
+// 1D tables at a runtime local node a (second index compile-time after unrolling)
+__device__ __forceinline__ double gb_sel(int a, int g) { return a == 0 ? GB(0, g) : (a == 1 ? GB(1, g) : GB(2, g)); }
+__device__ __forceinline__ double vg_sel(int g, int a) { return a == 0 ? VG(g, 0) : (a == 1 ? VG(g, 1) : VG(g, 2)); }
+__device__ __forceinline__ double mc_sel(int a, int b) { return a == 0 ? MC(0, b) : (a == 1 ? MC(1, b) : MC(2, b)); }
+__device__ __forceinline__ double mc_diag(int a) { return a == 0 ? MC(0, 0) : (a == 1 ? MC(1, 1) : MC(2, 2)); }
+
+// Flux row pieces at node co of q_e (local index `loc` within the q_e array)
+// of one level Xl:  mq = tau (Mq q)(node) with essential q masked, dg = its
+// diagonal entry (both only if MASS), bp = (B p)(node) =
+// -hp_e sum_{cells of the node} sum_g GB(a, g) p(g).
+template <typename T, bool MASS = true>
+__device__ __forceinline__ void flux_row(const InstDev& I, const T* __restrict__ kc, const T* __restrict__ Xl, int e,
+                                         const int co[3], int loc, T& mq, T& dg, T& bp) {
   const int d = I.dim;
+  const int m = sel3(e, co);
+  const int ne = sel3(e, I.n);
+  const double he = e == 0 ? I.h[0] : (e == 1 ? I.h[1] : I.h[2]);
   double hp = 1.0;
   for (int f = 0; f < d; ++f)
     if (f != e) hp *= 0.5 * I.h[f];
-  const int m = co[e];
-  double s = 0.0;
+  const int qstr = e == 0 ? 1 : (e == 1 ? I.sq[1][0] : I.sq[2][0] * I.sq[2][1]);
+  const int cstr = e == 0 ? 1 : (e == 1 ? I.n[0] : I.n[0] * I.n[1]);
+  const int pstr = e == 0 ? 1 : (e == 1 ? I.sp[0] : I.sp[0] * I.sp[1]);
+  const T* Q = Xl + I.off_q[e] + (loc - m * qstr);           // line of q_e through the node
+  const int cell0 = (co[0] >> 1) + I.n[0] * ((co[1] >> 1) + I.n[1] * (co[2] >> 1)) - (m >> 1) * cstr;
+  const T* P = Xl + I.off_p + ((co[0] + I.sp[0] * (co[1] + I.sp[1] * co[2])) - m * pstr);
+  const T fq = T(I.tau * he * hp);
+  T acc = 0, dacc = 0;
+  double sb = 0.0;
+#pragma unroll
   for (int side = 0; side < 2; ++side) {
     int ce, a;
-    if (m & 1) { if (side) break; ce = (m - 1) / 2; a = 1; }
-    else { ce = m / 2 - 1 + side; a = side ? 0 : 2; if (ce < 0 || ce >= I.n[e]) continue; }
-    int o[3] = {co[0], co[1], co[2]};
-    o[e] = 2 * ce;
-    const double p0 = (double)P[p_index(I, o[0], o[1], o[2])];
-    o[e] = 2 * ce + 1;
-    const double p1 = (double)P[p_index(I, o[0], o[1], o[2])];
-    s += GB(a, 0) * p0 + GB(a, 1) * p1;
+    if (!node_cell(m, ne, side, ce, a)) continue;
+    if (MASS) {
+      const T f = kc[cell0 + ce * cstr] * fq;
+      T s = 0;
+#pragma unroll
+      for (int a2 = 0; a2 < 3; ++a2) {
+        const int m2 = 2 * ce + a2;
+        if (!q_fixed(I, e, m2)) s += T(mc_sel(a, a2)) * Q[m2 * qstr];
+      }
+      acc += f * s;
+      dacc += f * T(mc_diag(a));
+    }
+    sb += gb_sel(a, 0) * (double)P[(2 * ce) * pstr] + gb_sel(a, 1) * (double)P[(2 * ce + 1) * pstr];
   }
-  return (T)(-hp * s);
+  mq = acc;
+  dg = dacc;
+  bp = T(-hp * sb);
 }
 
-// tau Mq q at the flux node (e, co); dg receives the diagonal entry
-template <typename T>
-__device__ __forceinline__ T mq_node(const InstDev& I, const T* kc, const T* X, int e, const int co[3], T& dg) {
-  const int d = I.dim;
-  T hp = 1;
-  for (int f = 0; f < d; ++f)
-    if (f != e) hp *= T(0.5 * I.h[f]);
-  const int m = co[e];
-  const long long qstr_e = e == 0 ? 1 : (e == 1 ? (long long)I.sq[e][0] : (long long)I.sq[e][0] * I.sq[e][1]);
-  long long base = I.off_q[e];
-  {
-    long long s = 1;
-    for (int f = 0; f < d; ++f) {
-      if (f != e) base += (long long)co[f] * s;
-      s *= I.sq[e][f];
-    }
-  }
-  T acc = 0;
-  dg = 0;
-  for (int side = 0; side < 2; ++side) {
-    int ce, a;
-    if (m & 1) { if (side) break; ce = (m - 1) / 2; a = 1; }
-    else { ce = m / 2 - 1 + side; a = side ? 0 : 2; if (ce < 0 || ce >= I.n[e]) continue; }
-    int cc[3] = {co[0] >> 1, co[1] >> 1, co[2] >> 1};
-    cc[e] = ce;
-    const long long cell = cc[0] + (long long)I.n[0] * (cc[1] + (long long)I.n[1] * (d == 3 ? cc[2] : 0));
-    const T f = kc[cell] * T(I.tau * I.h[e]) * hp;
-    T s = 0;
-    for (int a2 = 0; a2 < 3; ++a2) {
-      const int m2 = 2 * ce + a2;
-      if (q_fixed(I, e, m2)) continue;
-      s += T(MC(a, a2)) * X[base + m2 * qstr_e];
-    }
-    acc += f * s;
-    dg += f * T(MC(a, a));
-  }
-  return acc;
-}
-
-// div u and div q of one level at the 2^d Gauss points of cell ce (x fastest), masked inputs
+// (E p) at the u_c node co of one level's pressure block P:
+//   sum_{cells of the node} sum_g GB(a_c, g_c) prod_{f != c} (h_f / 2) VG(g_f, a_f) p(g)
 template <typename T, int DIM>
-__device__ void cell_div(const InstDev& I, const T* Xl, const int ce[3], T du[1 << DIM], T dq[1 << DIM]) {
+__device__ __forceinline__ T ep_node(const InstDev& I, const T* __restrict__ P, int c, const int co[3]) {
+  double s = 0.0;
+  const double hh[3] = {0.5 * I.h[0], 0.5 * I.h[1], DIM == 3 ? 0.5 * I.h[2] : 1.0};
+#pragma unroll
+  for (int sz = 0; sz < (DIM == 3 ? 2 : 1); ++sz) {
+    int cz = 0, az = 0;
+    if (DIM == 3 && !node_cell(co[2], I.n[2], sz, cz, az)) continue;
+#pragma unroll
+    for (int sy = 0; sy < 2; ++sy) {
+      int cy, ay;
+      if (!node_cell(co[1], I.n[1], sy, cy, ay)) continue;
+#pragma unroll
+      for (int sx = 0; sx < 2; ++sx) {
+        int cx, ax;
+        if (!node_cell(co[0], I.n[0], sx, cx, ax)) continue;
+        const T* pc = P + (2 * cx) + I.sp[0] * ((2 * cy) + I.sp[1] * (2 * cz));
+#pragma unroll
+        for (int g = 0; g < (1 << DIM); ++g) {
+          const int gx = g & 1, gy = (g >> 1) & 1, gz = (g >> 2) & 1;
+          const double wx = c == 0 ? gb_sel(ax, gx) : hh[0] * vg_sel(gx, ax);
+          const double wy = c == 1 ? gb_sel(ay, gy) : hh[1] * vg_sel(gy, ay);
+          double w = wx * wy;
+          if (DIM == 3) w *= c == 2 ? gb_sel(az, gz) : hh[2] * vg_sel(gz, az);
+          s += w * (double)pc[gx + I.sp[0] * (gy + I.sp[1] * gz)];
+        }
+      }
+    }
+  }
+  return (T)s;
+}
+
+// div u of one level at the 2^DIM Gauss points of cell ce (x fastest),
+// essential values masked.  All node loops are compile-time.
+template <typename T, int DIM>
+__device__ __forceinline__ void cell_divu(const InstDev& I, const T* __restrict__ Xl, const int ce[3],
+                                          T du[1 << DIM]) {
   constexpr int NG = 1 << DIM;
 #pragma unroll
-  for (int g = 0; g < NG; ++g) { du[g] = 0; dq[g] = 0; }
-  const long long us[3] = {1, (long long)I.su[0], (long long)I.su[0] * I.su[1]};
+  for (int g = 0; g < NG; ++g) du[g] = 0;
+  const int su0 = I.su[0], su1 = I.su[1];
+  const bool bx0 = ce[0] == 0, bx1 = ce[0] == I.n[0] - 1;
+  const bool by0 = ce[1] == 0, by1 = ce[1] == I.n[1] - 1;
+  const bool bz0 = DIM == 3 ? ce[2] == 0 : false;
+  const int nb = 2 * ce[0] + su0 * (2 * ce[1] + su1 * (DIM == 3 ? 2 * ce[2] : 0));
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
     const T ih = T(1.0 / I.h[c]);
-    // u_c: closed in every axis
-    for (int nidx = 0; nidx < (DIM == 3 ? 27 : 9); ++nidx) {
-      const int a[3] = {nidx % 3, (nidx / 3) % 3, DIM == 3 ? nidx / 9 : 0};
-      const int m[3] = {2 * ce[0] + a[0], 2 * ce[1] + a[1], DIM == 3 ? 2 * ce[2] + a[2] : 0};
-      if (u_fixed(I, c, m[0], m[1], m[2])) continue;
-      const T v = Xl[I.off_u[c] + m[0] + us[1] * m[1] + us[2] * m[2]];
+    const T* U = Xl + I.off_u[c] + nb;
+    T s[NG];
 #pragma unroll
-      for (int g = 0; g < NG; ++g) {
-        T f = ih;
+    for (int g = 0; g < NG; ++g) s[g] = 0;
 #pragma unroll
-        for (int e = 0; e < DIM; ++e) {
-          const int ge = (g >> e) & 1;
-          f *= T(e == c ? DG(ge, a[e]) : VG(ge, a[e]));
+    for (int az = 0; az < (DIM == 3 ? 3 : 1); ++az)
+#pragma unroll
+      for (int ay = 0; ay < 3; ++ay)
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          // essential u_c: bottom face (all components), lateral faces (normal component)
+          bool fx = DIM == 3 ? (az == 0 && bz0) : (ay == 0 && by0);
+          if (c == 0) fx = fx || (ax == 0 && bx0) || (ax == 2 && bx1);
+          if (DIM == 3 && c == 1) fx = fx || (ay == 0 && by0) || (ay == 2 && by1);
+          const T v = fx ? T(0) : U[ax + su0 * (ay + su1 * az)];
+#pragma unroll
+          for (int g = 0; g < NG; ++g) {
+            const int gx = g & 1, gy = (g >> 1) & 1, gz = (g >> 2) & 1;
+            double f = (c == 0 ? DG(gx, ax) : VG(gx, ax)) * (c == 1 ? DG(gy, ay) : VG(gy, ay));
+            if (DIM == 3) f *= c == 2 ? DG(gz, az) : VG(gz, az);
+            s[g] += T(f) * v;
+          }
         }
-        du[g] += f * v;
-      }
-    }
-    // q_c: closed along c, nodal (open) across
-    long long qs[3], s = 1;
-    for (int f = 0; f < 3; ++f) { qs[f] = s; s *= I.sq[c][f]; }
+#pragma unroll
+    for (int g = 0; g < NG; ++g) du[g] += ih * s[g];
+  }
+}
+
+// div q of one level at the 2^DIM Gauss points of cell ce; q_c is closed
+// along c (3 nodes) and nodal (open) across, essential values masked.
+template <typename T, int DIM>
+__device__ __forceinline__ void cell_divq(const InstDev& I, const T* __restrict__ Xl, const int ce[3],
+                                          T dq[1 << DIM]) {
+  constexpr int NG = 1 << DIM;
+#pragma unroll
+  for (int g = 0; g < NG; ++g) dq[g] = 0;
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    const T ih = T(1.0 / I.h[c]);
+    const int qs0 = I.sq[c][0], qs1 = I.sq[c][1];
+    const int mc0 = 2 * ce[c];
+    const bool lo_fixed = q_fixed(I, c, mc0), hi_fixed = q_fixed(I, c, mc0 + 2);
+    const int cstr = c == 0 ? 1 : (c == 1 ? qs0 : qs0 * qs1);
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
-      long long base = I.off_q[c];
-#pragma unroll
-      for (int f = 0; f < DIM; ++f)
-        if (f != c) base += (long long)(2 * ce[f] + ((g >> f) & 1)) * qs[f];
+      int o[3] = {2 * ce[0] + (g & 1), 2 * ce[1] + ((g >> 1) & 1), DIM == 3 ? 2 * ce[2] + ((g >> 2) & 1) : 0};
       const int gc = (g >> c) & 1;
-      T acc = 0;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const int mc = 2 * ce[c] + a;
-        if (q_fixed(I, c, mc)) continue;
-        acc += T(DG(gc, a)) * Xl[base + mc * qs[c]];
-      }
+      if (c == 0) o[0] = mc0;
+      if (c == 1) o[1] = mc0;
+      if (c == 2) o[2] = mc0;
+      const T* Q = Xl + I.off_q[c] + (o[0] + qs0 * (o[1] + qs1 * o[2]));
+      T acc = T(DG(gc, 1)) * Q[cstr];
+      if (!lo_fixed) acc += T(DG(gc, 0)) * Q[0];
+      if (!hi_fixed) acc += T(DG(gc, 2)) * Q[2 * cstr];
       dq[g] += ih * acc;
     }
   }

@@ -39,6 +39,18 @@ static void validate_desc(const biot_problem_desc& d, int idx) {
     if (!fin(d.length[e]) || d.length[e] <= 0) arg_fail(os.str() + "box lengths must be > 0");
   }
   if (d.r < 0 || d.r > 3) arg_fail(os.str() + "dG order r must be in 0..3");
+  {
+    // kernels index within one instance's slab with 32-bit integers
+    double nu = 1, np = 1, nq = 0;
+    for (int e = 0; e < d.dim; ++e) { nu *= 2.0 * d.n[e] + 1; np *= 2.0 * d.n[e]; }
+    for (int c = 0; c < d.dim; ++c) {
+      double t = 1;
+      for (int e = 0; e < d.dim; ++e) t *= (e == c) ? 2.0 * d.n[e] + 1 : 2.0 * d.n[e];
+      nq += t;
+    }
+    if ((d.r + 1) * (d.dim * nu + nq + np) >= 2147483647.0)
+      arg_fail(os.str() + "one instance's slab must hold fewer than 2^31 unknowns");
+  }
   if (!fin(d.tau) || d.tau <= 0) arg_fail(os.str() + "tau must be > 0");
   if (!fin(d.mu) || d.mu <= 0) arg_fail(os.str() + "mu must be > 0");
   if (!fin(d.lambda) || d.lambda + 2.0 * d.mu / d.dim <= 0) arg_fail(os.str() + "lambda + 2 mu / dim must be > 0");
@@ -51,6 +63,9 @@ static void validate_desc(const biot_problem_desc& d, int idx) {
   if (d.load_kind == BIOT_LOAD_RAMP && (!fin(d.load_t_ramp) || d.load_t_ramp <= 0))
     arg_fail(os.str() + "load_t_ramp must be > 0 for a ramp load");
 }
+
+// 2D: tau A_e (18 x 18) followed by E_e (18 x 4); 3D: matrix-core fragments of [tau A_e | E_e]
+static long long emat_per_instance(int d) { return d == 2 ? 18 * 18 + 18 * 4 : 6 * 23 * 64; }
 
 static InstDev make_inst(const biot_problem_desc& d) {
   InstDev I;
@@ -107,11 +122,11 @@ static void build_host_state(biot_problem_s* h, const biot_problem_desc* descs, 
   for (int k = 0; k < count; ++k) {
     InstDev I = make_inst(descs[k]);
     I.x_off = xo; I.state_off = so; I.cell_off = co;
-    I.emat_off = descs[0].dim == 2 ? (long long)k * (18 * 18 + 18 * 4) : 0;
+    I.emat_off = (long long)k * emat_per_instance(descs[0].dim);
     xo += I.N * h->nl; so += I.N; co += I.ncells;
     h->inst.push_back(I);
   }
-  h->emat_len = descs[0].dim == 2 ? (long long)count * (18 * 18 + 18 * 4) : 0;
+  h->emat_len = (long long)count * emat_per_instance(descs[0].dim);
   h->slab_len = xo; h->state_len = so; h->ncells = co;
   // apply work list
   int nw = 0;
@@ -289,10 +304,15 @@ biot_status create_slab_problem(const biot_problem_desc* descs, int32_t count, c
       for (int k = 0; k < h->count; ++k) {
         const auto& D = h->descs[k];
         const double hh[3] = {h->inst[k].h[0], h->inst[k].h[1], h->inst[k].h[2]};
-        auto A = elast_element(2, hh, D.lambda, D.mu, D.tau);
-        auto E = coupling_element(2, hh);
-        std::copy(A.begin(), A.end(), em.begin() + h->inst[k].emat_off);
-        std::copy(E.begin(), E.end(), em.begin() + h->inst[k].emat_off + 18 * 18);
+        auto A = elast_element(h->dim, hh, D.lambda, D.mu, D.tau);
+        auto E = coupling_element(h->dim, hh);
+        if (h->dim == 3) {
+          auto F = elast_fragments3d(A, &E);
+          std::copy(F.begin(), F.end(), em.begin() + h->inst[k].emat_off);
+        } else {
+          std::copy(A.begin(), A.end(), em.begin() + h->inst[k].emat_off);
+          std::copy(E.begin(), E.end(), em.begin() + h->inst[k].emat_off + (long long)A.size());
+        }
       }
       for (long long q = 0; q < h->emat_len; ++q) em32[q] = (float)em[q];
       hip_check(hipMemcpyAsync(h->d_emat64, em.data(), 8 * em.size(), hipMemcpyHostToDevice, s), "emat");

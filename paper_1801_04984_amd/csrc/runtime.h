@@ -54,7 +54,7 @@ struct biot_problem_s {
   double* d_kinv64 = nullptr;
   float* d_kinv32 = nullptr;
   double* d_theta = nullptr;
-  double* d_emat64 = nullptr;          // 2D element matrices per instance (tau*A_e, E_e)
+  double* d_emat64 = nullptr;          // element matrices per instance (tau*A_e, E_e)
   float* d_emat32 = nullptr;
   long long emat_len = 0;
   bt::PrecData* prec = nullptr;        // owned (host struct with device pointers)

@@ -234,8 +234,8 @@ static void build_hierarchy(biot_problem_s* h, PrecData* P) {
       }
       g.tau = D.tau; g.lam = D.lambda; g.mu = D.mu;
       g.nu = (long long)d * g.su[0] * g.su[1] * g.su[2];
-      g.emat_off = d == 2 ? uemat_off : 0;
-      if (d == 2) uemat_off += 18 * 18;
+      g.emat_off = uemat_off;
+      uemat_off += d == 2 ? 18 * 18 : 6 * 21 * 64;
       g.doff = dinv_off + lvtot;
       if (level == 0) { g.voff = h->inst[k].x_off + h->inst[k].off_u[0]; g.vjstride = h->inst[k].N; }
       else { g.voff = voff; g.vjstride = g.nu; voff += nl * g.nu; }
@@ -749,12 +749,13 @@ static void setup_elasticity(biot_problem_s* h, hipStream_t s) {
   PrecData* P = h->prec;
   auto& B = P->b64;
   const int cnt = h->count, d = h->dim;
-  if (d == 2) {
+  {
     std::vector<double> em(P->uemat_len);
     for (int l = 0; l < P->nul; ++l)
       for (int k = 0; k < cnt; ++k) {
         const UGridSeg& g = P->ug[l][k];
-        auto A = elast_element(2, g.h, g.lam, g.mu, g.tau);
+        auto A = elast_element(d, g.h, g.lam, g.mu, g.tau);
+        if (d == 3) A = elast_fragments3d(A, nullptr);
         std::copy(A.begin(), A.end(), em.begin() + g.emat_off);
       }
     upload(em, P->d_uemat64, s);
