@@ -96,7 +96,10 @@ typedef struct {
   int32_t precision;    /* biot_precision                                [FP64]   */
   double inner_rtol;    /* mixed: inner FP32 solve tolerance              [1e-2]   */
   int32_t max_refine;   /* mixed: outer refinement sweeps                   [30]   */
-  int32_t cheb_degree;  /* Chebyshev degree of the flux-mass block          [8]    */
+  int32_t cheb_degree;  /* flux-mass block: 0 = exact line solves, k = 1..64 [-1]
+                           Chebyshev-Jacobi of degree k, -1 = line solves
+                           when instances x levels x flux lines >= 16384,
+                           else degree 8                                  */
   int32_t graph;        /* 1: replay the preconditioner as a captured      [1]
                            hipGraph (captured on first use); 0: eager     */
 } biot_solve_opts;
@@ -140,6 +143,28 @@ biot_status biot_totals(biot_problem h, int64_t* slab_len, int64_t* state_len);
  * dtype 1: float x, y.  x and y must not alias.  Asynchronous on stream. */
 biot_status apply_operator(biot_problem h, const void* x, void* y, int32_t transpose,
                            int32_t dtype, void* stream);
+
+/* Tile shapes of the operator apply.  Every variant computes bitwise the same
+ * y; they differ only in the work decomposition (2D: 0 = 16x16-thread tiles,
+ * 1 = 8x8; 3D: z-chunk of 0 = 8, 1 = 4, 2 = 16 cell layers per block).
+ * apply_variant[0] is used for FP64 applies, [1] for FP32. */
+typedef struct {
+  int32_t apply_variant[2];
+  int32_t n_variants;        /* out: variants available for the handle's dimension */
+  double apply_us[2][4];     /* out of biot_autotune: average apply time per variant,
+                                microseconds (0 for variants beyond n_variants)    */
+} biot_tuning;
+
+/* In-project autotuner: times `reps` (1..1000) operator applies per variant
+ * and precision on `stream` (HIP events; workspace buffers as operands),
+ * selects the fastest for each precision and reports the timings in `out`
+ * (nullable).  Synchronises `stream`. */
+biot_status biot_autotune(biot_problem h, int32_t reps, biot_tuning* out, void* stream);
+/* Current selection (n_variants filled, apply_us zero). */
+biot_status biot_get_tuning(biot_problem h, biot_tuning* out);
+/* Select variants (e.g. from a cache of earlier biot_autotune results);
+ * BIOT_ERR_ARG for an index outside 0..n_variants-1. */
+biot_status biot_set_tuning(biot_problem h, const biot_tuning* t);
 
 /* Slab right-hand side (device): rhs = tau F(t_start + tau s_i) + g_i M_t state,
  * essential rows zero.  state: device, one spatial level per instance. */

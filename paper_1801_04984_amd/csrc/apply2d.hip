@@ -16,8 +16,9 @@
 // (18x4), identical for every cell of an instance: 396 FMA per cell and level,
 // fewer than the sum-factorised evaluation in 2D and far lighter on registers.
 //
-// Work decomposition: one block = one tile of 15x15 owned cells plus a
-// one-cell halo on the low sides (16x16 threads, one cell each).  Every
+// Work decomposition: one block = one tile of (TS-1)x(TS-1) owned cells plus a
+// one-cell halo on the low sides (TS x TS threads, one cell each; TS = 16 or
+// 8, chosen per handle by the tile autotuner: both give identical results).  Every
 // output DoF is written by exactly one block: u-rows are summed from the
 // per-cell element vectors staged in LDS in a fixed order (deterministic,
 // no atomics); q-rows are evaluated node by node from X; p-rows are
@@ -27,14 +28,12 @@
 
 namespace bt {
 
-constexpr int kT2 = 16;
-constexpr int kO2 = kT2 - 1;
-
-template <typename T, int NL, bool TR>
-__global__ __launch_bounds__(256) void apply2d_kernel(const InstDev* __restrict__ insts,
+template <typename T, int NL, bool TR, int kT2>
+__global__ __launch_bounds__(kT2 * kT2) void apply2d_kernel(const InstDev* __restrict__ insts,
                                                       const int4* __restrict__ work, TimeMat tm,
                                                       const T* __restrict__ kinv_all, const T* __restrict__ emat,
                                                       const T* __restrict__ X, T* __restrict__ Y) {
+  constexpr int kO2 = kT2 - 1;
   __shared__ T E[18][kT2 * kT2];
   const int4 w = work[blockIdx.x];
   const InstDev& I = insts[w.x];
@@ -271,15 +270,21 @@ __global__ __launch_bounds__(256) void apply2d_kernel(const InstDev* __restrict_
   }
 }
 
+template <typename T, int NL, int TS>
+static void launch_ts(const ApplyArgs& a, const void* x, void* y, int transpose) {
+  dim3 blk(TS, TS);
+  if (transpose)
+    hipLaunchKernelGGL((apply2d_kernel<T, NL, true, TS>), dim3(a.nwork), blk, 0, a.stream, a.inst, a.work, *a.tm,
+                       (const T*)a.kinv, (const T*)a.emat, (const T*)x, (T*)y);
+  else
+    hipLaunchKernelGGL((apply2d_kernel<T, NL, false, TS>), dim3(a.nwork), blk, 0, a.stream, a.inst, a.work, *a.tm,
+                       (const T*)a.kinv, (const T*)a.emat, (const T*)x, (T*)y);
+}
+
 template <typename T, int NL>
 static void launch_nl(const ApplyArgs& a, const void* x, void* y, int transpose) {
-  dim3 blk(kT2, kT2);
-  if (transpose)
-    hipLaunchKernelGGL((apply2d_kernel<T, NL, true>), dim3(a.nwork), blk, 0, a.stream, a.inst, a.work,
-                       *a.tm, (const T*)a.kinv, (const T*)a.emat, (const T*)x, (T*)y);
-  else
-    hipLaunchKernelGGL((apply2d_kernel<T, NL, false>), dim3(a.nwork), blk, 0, a.stream, a.inst, a.work,
-                       *a.tm, (const T*)a.kinv, (const T*)a.emat, (const T*)x, (T*)y);
+  if (a.variant == 1) launch_ts<T, NL, 8>(a, x, y, transpose);
+  else launch_ts<T, NL, 16>(a, x, y, transpose);
 }
 
 template <typename T>
@@ -295,6 +300,8 @@ void launch_apply2d(const ApplyArgs& a, const void* x, void* y, int transpose) {
 template void launch_apply2d<double>(const ApplyArgs&, const void*, void*, int);
 template void launch_apply2d<float>(const ApplyArgs&, const void*, void*, int);
 
-int apply2d_tile_cells() { return kO2; }
+// tile variants: 0 = 16x16 threads (15x15 owned cells), 1 = 8x8 (7x7)
+int apply2d_variants() { return 2; }
+int apply2d_tile_cells(int variant) { return variant == 1 ? 7 : 15; }
 
 }  // namespace bt

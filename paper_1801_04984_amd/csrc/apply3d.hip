@@ -31,7 +31,9 @@ constexpr int kW3 = 6;        // waves per block: one 16-row tile of the 96 padd
 constexpr int kLD3 = 80;      // LDS row stride (elements): 16-lane groups of one half-wave hit disjoint banks
 
 int apply3d_tile_cells_xy() { return kO3; }
-int apply3d_tile_cells_z() { return kZC; }
+// z-chunk variants of the operator apply (tile autotuner; identical results): 8, 4, 16 layers
+int apply3d_variants() { return 3; }
+int apply3d_tile_cells_z(int variant) { return variant == 1 ? 4 : (variant == 2 ? 16 : kZC); }
 
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
 typedef float mf_f4 __attribute__((ext_vector_type(4)));
@@ -215,7 +217,7 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
 // operator apply: u-rows of time level blockIdx.y
 template <typename T, int NL, bool TR>
 __global__ __launch_bounds__(64 * kW3) void apply3d_u_kernel(const InstDev* __restrict__ insts,
-                                                             const int4* __restrict__ work, TimeMat tm,
+                                                             const int4* __restrict__ work, int zc, TimeMat tm,
                                                              const T* __restrict__ emat, const T* __restrict__ X,
                                                              T* __restrict__ Y) {
   const int4 w = work[blockIdx.x];
@@ -243,7 +245,7 @@ __global__ __launch_bounds__(64 * kW3) void apply3d_u_kernel(const InstDev* __re
     for (int l = 0; l < NL; ++l) J.pw[l] = T(tm.T[l * 4 + lev]);
     J.cp = T(I.b);
   }
-  u3_run<T, 23>(J, w.y * kO3, w.z * kO3, w.w * kZC, kZC);
+  u3_run<T, 23>(J, w.y * kO3, w.z * kO3, w.w * zc, zc);
 }
 
 // q-rows: tau (Mq q + B p), identity on essential rows
@@ -367,10 +369,10 @@ static void apply3d_nl(const ApplyArgs& a, const void* x, void* y, int tr, long 
   const T* em = (const T*)a.emat;
   if (tr)
     hipLaunchKernelGGL((apply3d_u_kernel<T, NL, true>), dim3(a.nwork, NL), dim3(64 * kW3), 0, a.stream, a.inst,
-                       a.work, *a.tm, em, X, Y);
+                       a.work, apply3d_tile_cells_z(a.variant), *a.tm, em, X, Y);
   else
     hipLaunchKernelGGL((apply3d_u_kernel<T, NL, false>), dim3(a.nwork, NL), dim3(64 * kW3), 0, a.stream, a.inst,
-                       a.work, *a.tm, em, X, Y);
+                       a.work, apply3d_tile_cells_z(a.variant), *a.tm, em, X, Y);
   hipLaunchKernelGGL((qrows_kernel<T>), g3(maxN, count, NL), dim3(256), 0, a.stream, a.inst, (const T*)a.kinv, X, Y);
   if (tr) {
     hipLaunchKernelGGL((prows_local_kernel<T, true, 3>), g3(maxc, count, NL), dim3(256), 0, a.stream, a.inst, X, Y);

@@ -112,6 +112,107 @@ template void launch_mq<double>(int, const InstDev*, int, int, long long, int, C
 template void launch_mq<float>(int, const InstDev*, int, int, long long, int, ChebCoef, const float*, const float*,
                                const float*, float*, float*, const float*, float*, hipStream_t);
 
+// ---- exact flux-mass solve: tau Mq x = b, line by line -------------------------------------
+// Mq couples the nodes of q_e only along axis e (the open basis is orthogonal
+// under 2-point Gauss across), so tau Mq is block diagonal with one banded
+// SPD block per line of q_e nodes.  Within a cell the three nodes couple
+// through f_c MC (f_c = eta/K_c tau h_e hp_e).  Condensing the cell-interior
+// node leaves a tridiagonal system on the cell-end nodes:
+//   diag_i = S00 (f_{i-1} + f_i),  off-diagonal (i, i+1) = S02 f_i,
+//   rhs_i  = b_2i - (MC01 / MC11) (b_{2i-1} + b_{2i+1}),
+// with S00 = MC00 - MC01^2 / MC11 and S02 = MC02 - MC01 MC12 / MC11; it is
+// solved by a Thomas sweep and the interior node recovered from its row.
+// Essential nodes stay zero (identity rows with zero right-hand side).
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void mq_line_kernel(const InstDev* __restrict__ insts, const T* __restrict__ kinv,
+                                                      const T* __restrict__ b, T* __restrict__ x,
+                                                      T* __restrict__ w) {
+  constexpr double kS00 = MC(0, 0) - MC(0, 1) * MC(1, 0) / MC(1, 1);
+  constexpr double kS02 = MC(0, 2) - MC(0, 1) * MC(1, 2) / MC(1, 1);
+  constexpr double kR = MC(0, 1) / MC(1, 1);
+  const InstDev& I = insts[blockIdx.y];
+  const long long lo = I.x_off + blockIdx.z * I.N;
+  const T* kc = kinv + I.cell_off;
+  int nlines[3] = {0, 0, 0};
+#pragma unroll
+  for (int e = 0; e < DIM; ++e) {
+    int c = 1;
+#pragma unroll
+    for (int f = 0; f < DIM; ++f)
+      if (f != e) c *= I.sp[f];
+    nlines[e] = c;
+  }
+  const int total = nlines[0] + nlines[1] + nlines[2];
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+    const int e = t < nlines[0] ? 0 : (t < nlines[0] + nlines[1] ? 1 : 2);
+    const int ln = t - (e == 0 ? 0 : (e == 1 ? nlines[0] : nlines[0] + nlines[1]));
+    // open coordinates across the line (the two axes other than e, lower first)
+    const int fa = e == 0 ? 1 : 0, fb = e == 2 ? 1 : 2;
+    const int sa = I.sp[fa];
+    const int oa = ln % sa, ob = DIM == 3 ? ln / sa : 0;
+    // strides of q_e along e and across
+    const int qs0 = I.sq[e][0], qs1 = I.sq[e][1];
+    const int qstr[3] = {1, qs0, qs0 * qs1};
+    const int cstr[3] = {1, I.n[0], I.n[0] * I.n[1]};
+    const int base = oa * qstr[fa] + (DIM == 3 ? ob * qstr[fb] : 0);
+    const int cbase = (oa >> 1) * cstr[fa] + (DIM == 3 ? (ob >> 1) * cstr[fb] : 0);
+    const int qs = qstr[e], cs = cstr[e];
+    const int n = I.n[e];
+    double hp = 1.0;
+#pragma unroll
+    for (int f = 0; f < DIM; ++f)
+      if (f != e) hp *= 0.5 * I.h[f];
+    const T fsc = T(I.tau * I.h[e] * hp);
+    const T* B = b + lo + I.off_q[e] + base;
+    T* X = x + lo + I.off_q[e] + base;
+    T* W = w + lo + I.off_q[e] + base;
+    const bool top_free = e == DIM - 1;      // the top face carries no flux condition
+    // forward sweep over the cell-end nodes i = 0..n (node 2i)
+    T cprev = 0, dprev = 0, fprev = 0;
+    for (int i = 0; i <= n; ++i) {
+      const T fi = i < n ? kc[cbase + i * cs] * fsc : T(0);
+      const bool fixed = i == 0 || (i == n && !top_free);
+      T cp, dp;
+      if (fixed) {
+        cp = 0; dp = 0;
+      } else {
+        const T diag = T(kS00) * (fprev + fi);
+        const T low = T(kS02) * fprev, up = T(kS02) * fi;
+        T rhs = B[(2 * i) * qs];
+        if (i > 0) rhs -= T(kR) * B[(2 * i - 1) * qs];
+        if (i < n) rhs -= T(kR) * B[(2 * i + 1) * qs];
+        const T den = diag - low * cprev;
+        cp = up / den;
+        dp = (rhs - low * dprev) / den;
+      }
+      W[(2 * i) * qs] = cp;
+      X[(2 * i) * qs] = dp;
+      cprev = cp; dprev = dp; fprev = fi;
+    }
+    // back substitution, interior nodes from their rows
+    T xn = X[(2 * n) * qs];
+    for (int i = n - 1; i >= 0; --i) {
+      const T xi = X[(2 * i) * qs] - W[(2 * i) * qs] * xn;
+      X[(2 * i) * qs] = xi;
+      const T fi = kc[cbase + i * cs] * fsc;
+      X[(2 * i + 1) * qs] = (B[(2 * i + 1) * qs] / fi - T(MC(1, 0)) * xi - T(MC(1, 2)) * xn) / T(MC(1, 1));
+      xn = xi;
+    }
+  }
+}
+template <typename T>
+void launch_mq_lines(int dim, const InstDev* insts, int count, int nj, long long maxlines, const T* kinv, const T* b,
+                     T* x, T* w, hipStream_t s) {
+  if (dim == 2)
+    hipLaunchKernelGGL((mq_line_kernel<T, 2>), grid3(maxlines, count, nj), dim3(256), 0, s, insts, kinv, b, x, w);
+  else
+    hipLaunchKernelGGL((mq_line_kernel<T, 3>), grid3(maxlines, count, nj), dim3(256), 0, s, insts, kinv, b, x, w);
+}
+template void launch_mq_lines<double>(int, const InstDev*, int, int, long long, const double*, const double*, double*,
+                                      double*, hipStream_t);
+template void launch_mq_lines<float>(int, const InstDev*, int, int, long long, const float*, const float*, float*,
+                                     float*, hipStream_t);
+
 // ---- finalize -----------------------------------------------------------------------------------
 template <typename T, int NL>
 __global__ __launch_bounds__(256) void finalize_kernel(const InstDev* __restrict__ insts, Mat4 Q, const T* __restrict__ zt,

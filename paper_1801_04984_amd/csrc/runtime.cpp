@@ -95,17 +95,37 @@ static InstDev make_inst(const biot_problem_desc& d) {
   return I;
 }
 
+static std::vector<int4> make_work(const biot_problem_s* h, int variant) {
+  std::vector<int4> w;
+  for (int k = 0; k < h->count; ++k) {
+    const InstDev& I = h->inst[k];
+    if (h->dim == 2) {
+      int t = apply2d_tile_cells(variant);
+      for (int ty = 0; ty < (I.n[1] + t - 1) / t; ++ty)
+        for (int tx = 0; tx < (I.n[0] + t - 1) / t; ++tx) w.push_back(make_int4(k, tx, ty, 0));
+    } else {
+      int t = apply3d_tile_cells_xy(), tz = apply3d_tile_cells_z(variant);
+      for (int z = 0; z < (I.n[2] + tz - 1) / tz; ++z)
+        for (int ty = 0; ty < (I.n[1] + t - 1) / t; ++ty)
+          for (int tx = 0; tx < (I.n[0] + t - 1) / t; ++tx) w.push_back(make_int4(k, tx, ty, z));
+    }
+  }
+  return w;
+}
+
 // layout of everything the handle keeps on the device
 static void plan_layout(biot_problem_s* h, Layout& L, bool carve) {
   auto* d_inst = L.take<InstDev>(h->count);
-  auto* d_work = L.take<int4>(h->nwork_apply);
+  int4* d_work[biot_problem_s::kMaxVariants] = {nullptr, nullptr, nullptr};
+  for (int v = 0; v < h->nvariants; ++v) d_work[v] = L.take<int4>(h->nwork_apply[v]);
   auto* kinv64 = L.take<double>(h->ncells);
   auto* kinv32 = L.take<float>(h->ncells);
   auto* theta = L.take<double>(h->ncells);
   auto* em64 = L.take<double>(std::max(1LL, h->emat_len));
   auto* em32 = L.take<float>(std::max(1LL, h->emat_len));
   if (carve) {
-    h->d_inst = d_inst; h->d_work_apply = d_work; h->d_kinv64 = kinv64; h->d_kinv32 = kinv32;
+    h->d_inst = d_inst; h->d_kinv64 = kinv64; h->d_kinv32 = kinv32;
+    for (int v = 0; v < h->nvariants; ++v) h->d_work_apply[v] = d_work[v];
     h->d_theta = theta; h->d_emat64 = em64; h->d_emat32 = em32;
   }
   plan_solver_layout(h, L, carve);
@@ -128,18 +148,9 @@ static void build_host_state(biot_problem_s* h, const biot_problem_desc* descs, 
   }
   h->emat_len = (long long)count * emat_per_instance(descs[0].dim);
   h->slab_len = xo; h->state_len = so; h->ncells = co;
-  // apply work list
-  int nw = 0;
-  for (auto& I : h->inst) {
-    if (h->dim == 2) {
-      int t = apply2d_tile_cells();
-      nw += ((I.n[0] + t - 1) / t) * ((I.n[1] + t - 1) / t);
-    } else {
-      int t = apply3d_tile_cells_xy(), tz = apply3d_tile_cells_z();
-      nw += ((I.n[0] + t - 1) / t) * ((I.n[1] + t - 1) / t) * ((I.n[2] + tz - 1) / tz);
-    }
-  }
-  h->nwork_apply = nw;
+  // apply work lists (one per tile variant)
+  h->nvariants = h->dim == 2 ? apply2d_variants() : apply3d_variants();
+  for (int v = 0; v < h->nvariants; ++v) h->nwork_apply[v] = (int)make_work(h, v).size();
   h->tc = make_temporal(h->r);
   std::memset(&h->tm, 0, sizeof(h->tm));
   for (int k = 0; k < 16; ++k) { h->tm.T[k] = h->tc.T[k]; h->tm.Q[k] = h->tc.Q[k]; h->tm.Qi[k] = h->tc.Qi[k]; }
@@ -177,29 +188,12 @@ static void upload_log_k(biot_problem_s* h, const double* const* log_k, hipStrea
   hip_check(hipStreamSynchronize(s), "upload sync");
 }
 
-static std::vector<int4> make_work(const biot_problem_s* h) {
-  std::vector<int4> w;
-  for (int k = 0; k < h->count; ++k) {
-    const InstDev& I = h->inst[k];
-    if (h->dim == 2) {
-      int t = apply2d_tile_cells();
-      for (int ty = 0; ty < (I.n[1] + t - 1) / t; ++ty)
-        for (int tx = 0; tx < (I.n[0] + t - 1) / t; ++tx) w.push_back(make_int4(k, tx, ty, 0));
-    } else {
-      int t = apply3d_tile_cells_xy(), tz = apply3d_tile_cells_z();
-      for (int z = 0; z < (I.n[2] + tz - 1) / tz; ++z)
-        for (int ty = 0; ty < (I.n[1] + t - 1) / t; ++ty)
-          for (int tx = 0; tx < (I.n[0] + t - 1) / t; ++tx) w.push_back(make_int4(k, tx, ty, z));
-    }
-  }
-  return w;
-}
-
 ApplyArgs apply_args(const biot_problem_s* h, int dtype, hipStream_t s) {
   ApplyArgs a;
   a.inst = h->d_inst;
-  a.work = h->d_work_apply;
-  a.nwork = h->nwork_apply;
+  a.variant = h->variant[dtype ? 1 : 0];
+  a.work = h->d_work_apply[a.variant];
+  a.nwork = h->nwork_apply[a.variant];
   a.nl = h->nl;
   a.tm = &h->tm;
   a.kinv = dtype ? (const void*)h->d_kinv32 : (const void*)h->d_kinv64;
@@ -294,9 +288,13 @@ biot_status create_slab_problem(const biot_problem_desc* descs, int32_t count, c
     hip_check(hipMemsetAsync((void*)base, 0, C.off, s), "workspace clear");
     hip_check(hipMemcpyAsync(h->d_inst, h->inst.data(), sizeof(InstDev) * h->count, hipMemcpyHostToDevice, s),
               "upload instances");
-    auto w = make_work(h);
-    hip_check(hipMemcpyAsync(h->d_work_apply, w.data(), sizeof(int4) * w.size(), hipMemcpyHostToDevice, s),
-              "upload work list");
+    std::vector<std::vector<int4>> works;
+    for (int v = 0; v < h->nvariants; ++v) {
+      works.push_back(make_work(h, v));
+      hip_check(hipMemcpyAsync(h->d_work_apply[v], works.back().data(), sizeof(int4) * works.back().size(),
+                               hipMemcpyHostToDevice, s),
+                "upload work list");
+    }
     upload_log_k(h, log_k, s);
     if (h->emat_len > 0) {
       std::vector<double> em(h->emat_len);

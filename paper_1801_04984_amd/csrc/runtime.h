@@ -49,8 +49,12 @@ struct biot_problem_s {
   long long slab_len = 0, state_len = 0, ncells = 0;
   // device arrays (carved from ws)
   bt::InstDev* d_inst = nullptr;
-  int4* d_work_apply = nullptr;
-  int nwork_apply = 0;
+  // operator-apply work lists, one per tile variant; variant[dtype] is the one in use
+  static constexpr int kMaxVariants = 3;
+  int nvariants = 1;
+  int4* d_work_apply[kMaxVariants] = {nullptr, nullptr, nullptr};
+  int nwork_apply[kMaxVariants] = {0, 0, 0};
+  int variant[2] = {0, 0};
   double* d_kinv64 = nullptr;
   float* d_kinv32 = nullptr;
   double* d_theta = nullptr;

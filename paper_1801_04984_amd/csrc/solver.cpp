@@ -34,6 +34,8 @@ constexpr double kPLo = 1.0 / 8.0, kPHi = 1.1;
 constexpr int kUDeg = 2;                 // elasticity levels
 constexpr double kULo = 1.0 / 15.0, kUHi = 1.1;
 constexpr double kQLo = 0.25, kQHi = 1.75;  // Gershgorin interval of Dq^-1 Mq
+constexpr long long kLineSolveMinLines = 16384;   // automatic flux-block choice
+constexpr int kQDegDefault = 8;                     // Chebyshev degree when line solves are not used
 constexpr long long kPCoarseCells = 64;
 constexpr long long kUCoarseDofs = 1100;
 
@@ -108,7 +110,7 @@ struct PrecData {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int gdeg[2] = {0, 0};
-  long long maxN = 0, maxcells = 0;
+  long long maxN = 0, maxcells = 0, maxlines = 0;
 };
 
 template <typename T>
@@ -156,8 +158,19 @@ static void interp_table(int nf, int nc, std::vector<double>& prol, std::vector<
 static void build_hierarchy(biot_problem_s* h, PrecData* P) {
   const int d = h->dim, nl = h->nl, cnt = h->count;
   P->nl = nl; P->dim = d; P->count = cnt;
-  P->maxN = 0; P->maxcells = 0;
-  for (auto& I : h->inst) { P->maxN = std::max(P->maxN, I.N); P->maxcells = std::max(P->maxcells, I.ncells); }
+  P->maxN = 0; P->maxcells = 0; P->maxlines = 0;
+  for (auto& I : h->inst) {
+    P->maxN = std::max(P->maxN, I.N);
+    P->maxcells = std::max(P->maxcells, I.ncells);
+    long long lines = 0;   // lines of flux nodes: per component, the product of the open sizes across
+    for (int e = 0; e < d; ++e) {
+      long long c = 1;
+      for (int f = 0; f < d; ++f)
+        if (f != e) c *= I.sp[f];
+      lines += c;
+    }
+    P->maxlines = std::max(P->maxlines, lines);
+  }
   // ---- pressure: DG level segments
   P->pdg.clear();
   long long off = 0;
@@ -277,7 +290,7 @@ static void build_hierarchy(biot_problem_s* h, PrecData* P) {
         for (int ty = 0; ty < (g.n[1] + t - 1) / t; ++ty)
           for (int tx = 0; tx < (g.n[0] + t - 1) / t; ++tx) P->uwork[l].push_back(make_int4(k, tx, ty, 0));
       } else {
-        const int txy = apply3d_tile_cells_xy(), tz = apply3d_tile_cells_z();
+        const int txy = apply3d_tile_cells_xy(), tz = apply3d_tile_cells_z(0);
         for (int z = 0; z < (g.n[2] + tz - 1) / tz; ++z)
           for (int ty = 0; ty < (g.n[1] + txy - 1) / txy; ++ty)
             for (int tx = 0; tx < (g.n[0] + txy - 1) / txy; ++tx) P->uwork[l].push_back(make_int4(k, tx, ty, z));
@@ -963,8 +976,10 @@ static void apply_prec(biot_problem_s* h, const T* rin, T* z, int qdeg, hipStrea
   p_solve<T>(h, B.Wr, B.Wz, s);
   // 2) coupling right-hand sides
   launch_coupling<T>(d, h->d_inst, cnt, nl, P->maxN, B.Wr, B.Wz, B.Wf, B.Wf, s);
-  // 3) flux: tau Mq q = f_q  (Chebyshev-Jacobi on the Gershgorin interval)
-  {
+  // 3) flux: tau Mq q = f_q  (exact line solves, or Chebyshev-Jacobi of degree qdeg on the Gershgorin interval)
+  if (qdeg == 0) {
+    launch_mq_lines<T>(d, h->d_inst, cnt, nl, P->maxlines, B.kinv, B.Wf, B.Wz, B.T1, s);
+  } else {
     const ChebSeq cs = cheb_seq(kQLo, kQHi, qdeg);
     launch_mq<T>(d, h->d_inst, cnt, nl, P->maxN, kResInitZero, ChebCoef{cs.s0, 0, 0, 1}, B.kinv, nullptr, B.Wf, B.Wz,
                  B.T1, nullptr, B.T2, s);
@@ -1177,13 +1192,19 @@ static void solve_impl(biot_problem_s* h, const double* b, double* x, int transp
                        biot_solve_info* info, hipStream_t s) {
   biot_solve_opts opts;
   opts.rtol = 1e-12; opts.maxit = 1000; opts.restart = 40; opts.precision = BIOT_FP64;
-  opts.inner_rtol = 1e-2; opts.max_refine = 30; opts.cheb_degree = 8; opts.graph = 1;
+  opts.inner_rtol = 1e-2; opts.max_refine = 30; opts.cheb_degree = -1; opts.graph = 1;
   if (o) opts = *o;
   if (!(opts.rtol > 0) || !std::isfinite(opts.rtol)) throw BiotError{BIOT_ERR_ARG, "rtol must be > 0"};
   if (opts.maxit < 1) throw BiotError{BIOT_ERR_ARG, "maxit must be >= 1"};
   if (opts.restart < 1 || opts.restart > kMaxRestart) throw BiotError{BIOT_ERR_ARG, "restart must be in 1..64"};
   if (opts.precision != BIOT_FP64 && opts.precision != BIOT_MIXED) throw BiotError{BIOT_ERR_ARG, "unknown precision"};
-  if (opts.cheb_degree < 1 || opts.cheb_degree > 64) throw BiotError{BIOT_ERR_ARG, "cheb_degree must be in 1..64"};
+  if (opts.cheb_degree < -1 || opts.cheb_degree > 64) throw BiotError{BIOT_ERR_ARG, "cheb_degree must be in -1..64"};
+  if (opts.cheb_degree == -1) {
+    // exact line solves need one thread per flux line: use them when the lines of
+    // all instances and time levels fill the device, Chebyshev-Jacobi otherwise
+    const long long lines = (long long)h->count * h->nl * h->prec->maxlines;
+    opts.cheb_degree = lines >= kLineSolveMinLines ? 0 : kQDegDefault;
+  }
   const int cnt = h->count;
   std::vector<int> its, rst, st;
   std::vector<double> rr;
@@ -1306,6 +1327,68 @@ static biot_status worst(const biot_solve_info* info, int n) {
 }
 
 extern "C" {
+
+biot_status biot_get_tuning(biot_problem h, biot_tuning* out) {
+  BIOT_TRY
+  need(h && out, "handle and out must be non-null");
+  std::memset(out, 0, sizeof(*out));
+  out->apply_variant[0] = h->variant[0];
+  out->apply_variant[1] = h->variant[1];
+  out->n_variants = h->nvariants;
+  BIOT_CATCH
+}
+
+biot_status biot_set_tuning(biot_problem h, const biot_tuning* t) {
+  BIOT_TRY
+  need(h && t, "handle and tuning must be non-null");
+  for (int q = 0; q < 2; ++q)
+    need(t->apply_variant[q] >= 0 && t->apply_variant[q] < h->nvariants, "apply_variant out of range");
+  h->variant[0] = t->apply_variant[0];
+  h->variant[1] = t->apply_variant[1];
+  BIOT_CATCH
+}
+
+biot_status biot_autotune(biot_problem h, int32_t reps, biot_tuning* out, void* stream) {
+  BIOT_TRY
+  need(h, "handle is null");
+  need(reps >= 1 && reps <= 1000, "reps must be in 1..1000");
+  hipStream_t s = (hipStream_t)stream;
+  PrecData* P = h->prec;
+  biot_tuning res;
+  std::memset(&res, 0, sizeof(res));
+  res.n_variants = h->nvariants;
+  hipEvent_t e0, e1;
+  hip_check(hipEventCreate(&e0), "event");
+  hip_check(hipEventCreate(&e1), "event");
+  const int saved[2] = {h->variant[0], h->variant[1]};
+  for (int dt = 0; dt < 2; ++dt) {
+    const void* x = dt ? (const void*)P->b32.T1 : (const void*)P->b64.T1;
+    void* y = dt ? (void*)P->b32.T2 : (void*)P->b64.T2;
+    if (dt) vfill<float>(P->b32.T1, 0.5f, h->slab_len, s);
+    else vfill<double>(P->b64.T1, 0.5, h->slab_len, s);
+    int best = saved[dt];
+    double best_us = 0.0;
+    for (int v = 0; v < h->nvariants; ++v) {
+      h->variant[dt] = v;
+      launch_apply(h, x, y, 0, dt, s);     // warm-up
+      hip_check(hipEventRecord(e0, s), "event record");
+      for (int q = 0; q < reps; ++q) launch_apply(h, x, y, 0, dt, s);
+      hip_check(hipEventRecord(e1, s), "event record");
+      hip_check(hipEventSynchronize(e1), "event sync");
+      float ms = 0.0f;
+      hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
+      const double us = 1e3 * ms / reps;
+      res.apply_us[dt][v] = us;
+      if (v == 0 || us < best_us) { best_us = us; best = v; }
+    }
+    h->variant[dt] = best;
+    res.apply_variant[dt] = best;
+  }
+  hip_check(hipEventDestroy(e0), "event");
+  hip_check(hipEventDestroy(e1), "event");
+  if (out) *out = res;
+  BIOT_CATCH
+}
 
 biot_status slab_rhs(biot_problem h, const double* state, double t_start, double* rhs, void* stream) {
   BIOT_TRY

@@ -24,7 +24,8 @@ STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_WORKSPACE", 3: "ERR_DEVICE", 4: "
 EXPORTS = [
     "biot_workspace_bytes", "create_slab_problem", "destroy_slab_problem", "biot_set_log_k",
     "biot_sizes", "biot_totals", "apply_operator", "slab_rhs", "solve_slab",
-    "solve_slab_transposed", "step", "adjoint_sweep", "biot_misfit", "biot_last_error",
+    "solve_slab_transposed", "step", "adjoint_sweep", "biot_misfit", "biot_autotune",
+    "biot_get_tuning", "biot_set_tuning", "biot_last_error",
 ]
 
 
@@ -55,6 +56,17 @@ class SolveInfo(ctypes.Structure):
     def as_dict(self):
         return dict(iterations=self.iterations, restarts=self.restarts, ir_sweeps=self.ir_sweeps,
                     status=self.status, rel_residual=self.rel_residual)
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [
+        ("apply_variant", ctypes.c_int32 * 2), ("n_variants", ctypes.c_int32),
+        ("apply_us", (ctypes.c_double * 4) * 2),
+    ]
+
+    def as_dict(self):
+        return dict(apply_variant=list(self.apply_variant), n_variants=self.n_variants,
+                    apply_us=[list(r) for r in self.apply_us])
 
 
 class BiotError(RuntimeError):
@@ -92,6 +104,9 @@ def load_library(path: str = LIB_PATH):
     lib.adjoint_sweep.argtypes = [P, i32, dbl, P, ctypes.POINTER(dbl), i32, P, ctypes.POINTER(SolveOpts),
                                   ctypes.POINTER(dbl), P, P]
     lib.biot_misfit.argtypes = [P, i32, P, ctypes.POINTER(dbl), i32, P, ctypes.POINTER(dbl), P]
+    lib.biot_autotune.argtypes = [P, i32, ctypes.POINTER(Tuning), P]
+    lib.biot_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    lib.biot_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
     for name in EXPORTS:
         if name != "biot_last_error":
             getattr(lib, name).restype = ctypes.c_int32
@@ -123,7 +138,7 @@ def make_desc(wl) -> Desc:
 
 
 def make_opts(rtol=1e-12, maxit=2000, restart=40, precision=0, inner_rtol=1e-2, max_refine=30,
-              cheb_degree=8, graph=1) -> SolveOpts:
+              cheb_degree=-1, graph=1) -> SolveOpts:
     o = SolveOpts()
     o.rtol, o.maxit, o.restart, o.precision = rtol, maxit, restart, precision
     o.inner_rtol, o.max_refine, o.cheb_degree, o.graph = inner_rtol, max_refine, cheb_degree, graph
@@ -253,6 +268,22 @@ class BiotSlab:
                                     sens.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), sens.shape[0],
                                     _ptr(p_obs), J, self._stream()))
         return list(J)
+
+    # -- tile autotuner ----------------------------------------------------------
+    def autotune(self, reps=20):
+        t = Tuning()
+        _check(self.lib.biot_autotune(self.h, int(reps), ctypes.byref(t), self._stream()))
+        return t.as_dict()
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(self.lib.biot_get_tuning(self.h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, apply_variant):
+        t = Tuning()
+        t.apply_variant[0], t.apply_variant[1] = int(apply_variant[0]), int(apply_variant[1])
+        _check(self.lib.biot_set_tuning(self.h, ctypes.byref(t)))
 
     # -- layout helpers (host) ---------------------------------------------------
     def instance_slab(self, vec, k):

@@ -97,3 +97,25 @@ def test_create_rejects_small_workspace_and_nonfinite_logk():
     assert not h.value
     assert L.apply_operator(None, None, None, 0, 0, None) == 1
     assert L.destroy_slab_problem(None) == 1
+
+
+def test_instance_size_limit():
+    """One instance's slab must stay below 2^31 unknowns (32-bit kernel indexing)."""
+    from paper_1801_04984_amd import native
+    d = native.make_desc(W.c4_adjoint3d())
+    for e in range(3):
+        d.n[e] = 1024
+    st, _, err = _ws([d])
+    assert st == 1 and "2^31" in err
+    d = native.make_desc(W.c4_adjoint3d())
+    st, nb, _ = _ws([d])
+    assert st == 0 and nb > 0
+
+
+def test_tuning_calls_reject_null():
+    from paper_1801_04984_amd import native
+    L = lib()
+    t = native.Tuning()
+    assert L.biot_get_tuning(None, ctypes.byref(t)) == 1
+    assert L.biot_set_tuning(None, ctypes.byref(t)) == 1
+    assert L.biot_autotune(None, 5, ctypes.byref(t), None) == 1

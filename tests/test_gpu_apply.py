@@ -104,3 +104,43 @@ def test_slab_rhs_3d(r):
         ref = prob.rhs(t0, state)
         assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
     h.close()
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_tile_variants_identical_and_autotune(d, tmp_path):
+    """Every tile variant of the apply gives bitwise the same y (FP64, FP32,
+    transposed), the autotuner selects a valid variant per precision, and a
+    cached selection is restored by the tuning module."""
+    torch = torch_cuda()
+    from paper_1801_04984_amd import BiotSlab, native, tuning
+    if d == 2:
+        wls = [small_workload(2, (37, 21), 1, seed=5), small_workload(2, (9, 30), 1, seed=6)]
+    else:
+        wls = [small_workload(3, (9, 8, 19), 1, seed=7), small_workload(3, (4, 6, 5), 1, seed=8)]
+    h = BiotSlab(wls, [w.log_k() for w in wls])
+    nv = h.get_tuning()["n_variants"]
+    assert nv == (2 if d == 2 else 3)
+    rng = np.random.default_rng(3)
+    x64 = torch.tensor(rng.standard_normal(h.slab_len), device="cuda")
+    for dtype in (torch.float64, torch.float32):
+        x = x64.to(dtype)
+        for tr in (False, True):
+            outs = []
+            for v in range(nv):
+                h.set_tuning([v, v])
+                outs.append(h.apply(x, transpose=tr).clone())
+            torch.cuda.synchronize()
+            for v in range(1, nv):
+                assert torch.equal(outs[0], outs[v]), (dtype, tr, v)
+    res = h.autotune(reps=3)
+    assert all(0 <= v < nv for v in res["apply_variant"])
+    assert all(res["apply_us"][q][v] > 0 for q in range(2) for v in range(nv))
+    with pytest.raises(native.BiotError):
+        h.set_tuning([nv, 0])
+    path = str(tmp_path / "tiles.json")
+    first = tuning.tune(h, path=path, reps=2)
+    assert first["source"] == "timed"
+    h.set_tuning([0, 0])
+    again = tuning.tune(h, path=path)
+    assert again["source"] == "cache" and h.get_tuning()["apply_variant"] == first["apply_variant"]
+    h.close()

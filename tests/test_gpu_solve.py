@@ -207,6 +207,27 @@ def test_solve3d_fp64_and_mixed(n, r):
     h.close()
 
 
+@pytest.mark.parametrize("d,n", [(2, (20, 13)), (3, (5, 4, 6))])
+def test_flux_block_variants(d, n):
+    """The flux-mass block of the preconditioner solved exactly line by line
+    (default) or by Chebyshev-Jacobi: both preconditioned solves reach the
+    oracle's solution; the exact block needs no more iterations."""
+    torch = torch_cuda()
+    wl = small_workload(d, n, 1, seed=90 + d)
+    h, (prob,) = make_pair([wl])
+    b = _rhs(prob, seed=4)
+    ref = prob.solve(b)
+    its = {}
+    for deg in (0, 8):
+        x, info, st = h.solve(torch.tensor(b, device="cuda"), rtol=RT, cheb_degree=deg)
+        assert st == 0, (deg, info)
+        err = field_rel(prob, x.cpu().numpy(), ref)
+        assert max(err.values()) < TOL, (deg, err)
+        its[deg] = info[0]["iterations"]
+    assert its[0] <= its[8] + 2, its
+    h.close()
+
+
 def test_step3d_and_adjoint():
     torch = torch_cuda()
     from oracle import adjoint, fe
