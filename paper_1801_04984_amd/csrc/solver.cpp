@@ -101,6 +101,10 @@ struct PrecData {
   double *partial = nullptr, *dot1 = nullptr, *dot2 = nullptr, *dot3 = nullptr, *coef = nullptr, *scal = nullptr;
   // adjoint helpers
   double *lam = nullptr, *lam_next = nullptr, *xfwd = nullptr, *arhs = nullptr, *sres = nullptr, *sobs = nullptr;
+  // march predictor: xfwd holds the slab solved last by step(), ending at prev_tend
+  bool have_prev = false;
+  double prev_tend = 0.0;
+  Mat4 pred;
   SensorW* sw = nullptr;
   int max_sens = 256;
   PrecBufs<double> b64;
@@ -843,6 +847,20 @@ void setup_solver(biot_problem_s* h, hipStream_t s) {
   upload(P->pd, P->d_pd, s);
   upload(P->gseg, P->d_gseg, s);
   for (int j = 0; j < 16; ++j) { P->Q.m[j] = h->tc.Q[j]; P->Qi.m[j] = h->tc.Qi[j]; }
+  // initial guess of the next slab: the previous slab's solution extrapolated
+  // linearly in time through its last two Radau levels (r >= 1), or its end
+  // value (r = 0), evaluated at the next slab's levels 1 + s_i (units of tau)
+  std::memset(&P->pred, 0, sizeof(P->pred));
+  {
+    const int r = h->r;
+    for (int i = 0; i <= r; ++i) {
+      if (r == 0) { P->pred.m[0] = 1.0; break; }
+      const double s1 = h->tc.s[r], s0 = h->tc.s[r - 1];
+      const double f = (1.0 + h->tc.s[i] - s1) / (s1 - s0);
+      P->pred.m[i * 4 + r] = 1.0 + f;
+      P->pred.m[i * 4 + r - 1] = -f;
+    }
+  }
   P->b64.kinv = h->d_kinv64;
   P->b32.kinv = h->d_kinv32;
   setup_elasticity(h, s);
@@ -851,6 +869,7 @@ void setup_solver(biot_problem_s* h, hipStream_t s) {
 }
 
 void refresh_solver(biot_problem_s* h, hipStream_t s) {
+  h->prec->have_prev = false;
   setup_pressure(h, s);
   hip_check(hipStreamSynchronize(s), "solver refresh");
 }
@@ -1442,13 +1461,23 @@ biot_status step(biot_problem h, int32_t nslabs, double t_start, double* state, 
     double* rhs = P->arhs;
     double* x = P->xfwd;
     biot_status worst_st = BIOT_OK;
+    const double tau = h->descs[0].tau;
+    // continue from the slab solved last (still in x) when this call picks up where it ended
+    bool prev = P->have_prev && std::fabs(t_start - P->prev_tend) <= 1e-9 * tau;
+    P->have_prev = false;
     for (int n = 0; n < nslabs; ++n) {
       if (checkpoints)
         hip_check(hipMemcpyAsync(checkpoints + (long long)n * h->state_len, state, 8 * h->state_len,
                                  hipMemcpyDeviceToDevice, s), "checkpoint");
-      const double tn = t_start + n * h->descs[0].tau;
+      const double tn = t_start + n * tau;
       launch_slab_rhs(h, state, tn, rhs, s);
-      launch_bcast(h->d_inst, h->count, P->maxN, h->nl, state, x, s);
+      if (prev) {
+        time_transform<double>(h->d_inst, h->count, P->maxN, h->nl, P->pred, x, P->b64.T1, s);
+        hip_check(hipMemcpyAsync(x, P->b64.T1, 8 * h->slab_len, hipMemcpyDeviceToDevice, s), "predictor");
+      } else {
+        launch_bcast(h->d_inst, h->count, P->maxN, h->nl, state, x, s);
+      }
+      prev = true;
       solve_impl(h, rhs, x, 0, opts, infos + (long long)n * h->count, s);
       biot_status st = worst(infos + (long long)n * h->count, h->count);
       if (st != BIOT_OK) worst_st = st;
@@ -1458,6 +1487,8 @@ biot_status step(biot_problem h, int32_t nslabs, double t_start, double* state, 
       launch_extract(h->d_inst, h->count, P->maxN, h->nl - 1, x, state, s);
     }
     hip_check(hipStreamSynchronize(s), "step sync");
+    P->have_prev = nslabs > 0;
+    P->prev_tend = t_start + nslabs * tau;
     if (worst_st != BIOT_OK) set_error("a slab solve did not reach the tolerance");
     return worst_st;
   } catch (const BiotError& e) {
@@ -1477,6 +1508,7 @@ biot_status biot_misfit(biot_problem h, int32_t nslabs, const double* states, co
     need(states && p_obs, "states and p_obs must be device pointers");
     need(sensors_xyz && J, "sensors_xyz and J must be host pointers");
     PrecData* P = h->prec;
+    P->have_prev = false;   // the forward slab buffer is reused below
     need(nsens >= 1 && nsens <= P->max_sens, "nsens must be in 1..256");
     hipStream_t s = (hipStream_t)stream;
     const int cnt = h->count;
@@ -1515,6 +1547,7 @@ biot_status adjoint_sweep(biot_problem h, int32_t nslabs, double t_start, const 
     need(checkpoints && p_obs && grad_log_k, "checkpoints, p_obs and grad_log_k must be device pointers");
     need(sensors_xyz && J, "sensors_xyz and J must be host pointers");
     PrecData* P = h->prec;
+    P->have_prev = false;   // the forward slab buffer is reused below
     need(nsens >= 1 && nsens <= P->max_sens, "nsens must be in 1..256");
     hipStream_t s = (hipStream_t)stream;
     const int cnt = h->count, d = h->dim, nl = h->nl;
