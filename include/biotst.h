@@ -92,7 +92,7 @@ typedef struct {
 typedef struct {
   double rtol;          /* stop when ||b - A x|| <= rtol ||b||          [1e-12]   */
   int32_t maxit;        /* total GMRES iterations                         [1000]   */
-  int32_t restart;      /* GMRES(m) restart length, <= 64                   [40]   */
+  int32_t restart;      /* GMRES(m) restart length, <= 64                   [30]   */
   int32_t precision;    /* biot_precision                                [FP64]   */
   double inner_rtol;    /* mixed: inner FP32 solve tolerance              [1e-2]   */
   int32_t max_refine;   /* mixed: outer refinement sweeps                   [30]   */

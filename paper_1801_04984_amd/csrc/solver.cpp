@@ -1210,7 +1210,7 @@ static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const Solv
 static void solve_impl(biot_problem_s* h, const double* b, double* x, int transpose, const biot_solve_opts* o,
                        biot_solve_info* info, hipStream_t s) {
   biot_solve_opts opts;
-  opts.rtol = 1e-12; opts.maxit = 1000; opts.restart = 40; opts.precision = BIOT_FP64;
+  opts.rtol = 1e-12; opts.maxit = 1000; opts.restart = 30; opts.precision = BIOT_FP64;
   opts.inner_rtol = 1e-2; opts.max_refine = 30; opts.cheb_degree = -1; opts.graph = 1;
   if (o) opts = *o;
   if (!(opts.rtol > 0) || !std::isfinite(opts.rtol)) throw BiotError{BIOT_ERR_ARG, "rtol must be > 0"};

@@ -137,7 +137,7 @@ def make_desc(wl) -> Desc:
     return d
 
 
-def make_opts(rtol=1e-12, maxit=2000, restart=40, precision=0, inner_rtol=1e-2, max_refine=30,
+def make_opts(rtol=1e-12, maxit=2000, restart=30, precision=0, inner_rtol=1e-2, max_refine=30,
               cheb_degree=-1, graph=1) -> SolveOpts:
     o = SolveOpts()
     o.rtol, o.maxit, o.restart, o.precision = rtol, maxit, restart, precision
