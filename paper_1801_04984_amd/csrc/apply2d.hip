@@ -30,27 +30,36 @@ namespace bt {
 
 template <typename T, int NL, bool TR, int kT2>
 __global__ __launch_bounds__(kT2 * kT2) void apply2d_kernel(const InstDev* __restrict__ insts,
-                                                      const int4* __restrict__ work, TimeMat tm,
-                                                      const T* __restrict__ kinv_all, const T* __restrict__ emat,
-                                                      const T* __restrict__ X, T* __restrict__ Y) {
+                                                            const int4* __restrict__ work, TimeMat tm,
+                                                            const T* __restrict__ kinv_all, const T* __restrict__ emat,
+                                                            const T* __restrict__ X, T* __restrict__ Y) {
   constexpr int kO2 = kT2 - 1;
   __shared__ T E[18][kT2 * kT2];
   const int4 w = work[blockIdx.x];
   const InstDev& I = insts[w.x];
   const int lx = threadIdx.x, ly = threadIdx.y, tid = ly * kT2 + lx;
   const int nx = I.n[0], ny = I.n[1];
-  const int i0 = w.y * kO2, j0 = w.z * kO2;
-  const int i = i0 - 1 + lx, j = j0 - 1 + ly;
+  const int i = w.y * kO2 - 1 + lx, j = w.z * kO2 - 1 + ly;
   const bool valid = (i >= 0) && (i < nx) && (j >= 0) && (j < ny);
   const bool owned = valid && lx >= 1 && ly >= 1;
+  const bool lastx = i == nx - 1, lasty = j == ny - 1;
   const int sux = I.su[0], spx = I.sp[0];
-  const long long N = I.N;
+  const int N = (int)I.N;
   const T* Xb = X + I.x_off;
   T* Yb = Y + I.x_off;
   const T hx = T(I.h[0]), hy = T(I.h[1]);
-  const T tau = T(I.tau), lam = T(I.lam), mu = T(I.mu), bb = T(I.b), Minv = T(I.Minv);
+  const T ihx = T(1.0 / I.h[0]), ihy = T(1.0 / I.h[1]);
+  const T tau = T(I.tau), bb = T(I.b), Minv = T(I.Minv);
   const T w2 = hx * hy * T(0.25);
-  const T* kinv = kinv_all + I.cell_off;
+  const T kc = valid ? kinv_all[I.cell_off + i + nx * j] : T(0);
+  // offsets of the cell's lowest node in each nodal array (x fastest)
+  const int ub = 2 * i + sux * (2 * j);      // u_c (su0 x su1) and q_x (su0 x sp1) arrays
+  const int qyb = 2 * i + spx * (2 * j);     // q_y (sp0 x su1) and p (sp0 x sp1) arrays
+  const int ou0 = (int)I.off_u[0], ou1 = (int)I.off_u[1];
+  const int oq0 = (int)I.off_q[0], oq1 = (int)I.off_q[1], op = (int)I.off_p;
+  // flux-row scales: tau h_e (h_f / 2) eta/K for the mass part, tau (h_f / 2) for B p
+  const T cqx = tau * hx * hy * T(0.5) * kc, cbx = tau * hy * T(0.5);
+  const T cqy = tau * hx * hy * T(0.5) * kc, cby = tau * hx * T(0.5);
 
   // pressure of every level (p is never constrained)
   T pl[NL][2][2];
@@ -59,8 +68,7 @@ __global__ __launch_bounds__(kT2 * kT2) void apply2d_kernel(const InstDev* __res
 #pragma unroll
     for (int gy = 0; gy < 2; ++gy)
 #pragma unroll
-      for (int gx = 0; gx < 2; ++gx)
-        pl[l][gy][gx] = valid ? Xb[l * N + I.off_p + (2 * i + gx) + (long long)spx * (2 * j + gy)] : T(0);
+      for (int gx = 0; gx < 2; ++gx) pl[l][gy][gx] = valid ? Xb[l * N + op + qyb + gx + spx * gy] : T(0);
 
   // forward p-rows accumulate over levels: yp_i = tau dq_i + sum_j T_ij zeta_j
   // (register arrays are only indexed with compile-time indices)
@@ -70,62 +78,47 @@ __global__ __launch_bounds__(kT2 * kT2) void apply2d_kernel(const InstDev* __res
 #pragma unroll
     for (int g = 0; g < 4; ++g) yp[l][g >> 1][g & 1] = T(0);
 
-  // owned node ranges (the last tile along an axis also owns the top face)
-  const int mxe = (i0 + kO2 >= nx) ? 2 * nx + 1 : 2 * i0 + 2 * kO2;
-  const int mye = (j0 + kO2 >= ny) ? 2 * ny + 1 : 2 * j0 + 2 * kO2;
-  const int oxe = min(2 * i0 + 2 * kO2, 2 * nx);
-  const int oye = min(2 * j0 + 2 * kO2, 2 * ny);
-  const int nmx = mxe - 2 * i0, nmy = mye - 2 * j0, nox = oxe - 2 * i0, noy = oye - 2 * j0;
-
 #pragma unroll 1
   for (int lev = 0; lev < NL; ++lev) {
     const T* Xl = Xb + lev * N;
     T* Yl = Yb + lev * N;
+    // ---- cell data of this level, essential values masked
     T ux[3][3], uy[3][3], qx[2][3], qy[3][2];
 #pragma unroll
     for (int b = 0; b < 3; ++b)
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const int mx = 2 * i + a, my = 2 * j + b;
-        const long long o = mx + (long long)sux * my;
-        ux[b][a] = valid ? ld(Xl + I.off_u[0] + o, u_fixed(I, 0, mx, my, 0)) : T(0);
-        uy[b][a] = valid ? ld(Xl + I.off_u[1] + o, u_fixed(I, 1, mx, my, 0)) : T(0);
+        const bool bot = b == 0 && j == 0;
+        const bool fx = bot || (a == 0 && i == 0) || (a == 2 && lastx);
+        const int o = ub + a + sux * b;
+        ux[b][a] = (valid && !fx) ? Xl[ou0 + o] : T(0);
+        uy[b][a] = (valid && !bot) ? Xl[ou1 + o] : T(0);
       }
 #pragma unroll
     for (int g = 0; g < 2; ++g)
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const int mx = 2 * i + a, oy = 2 * j + g;
-        qx[g][a] = valid ? ld(Xl + I.off_q[0] + mx + (long long)sux * oy, q_fixed(I, 0, mx)) : T(0);
-        const int ox = 2 * i + g, my = 2 * j + a;
-        qy[a][g] = valid ? ld(Xl + I.off_q[1] + ox + (long long)spx * my, q_fixed(I, 1, my)) : T(0);
+        const bool fqx = (a == 0 && i == 0) || (a == 2 && lastx);   // no-flow on the x faces
+        const bool fqy = a == 0 && j == 0;                           // no-flow at the bottom
+        qx[g][a] = (valid && !fqx) ? Xl[oq0 + ub + a + sux * g] : T(0);
+        qy[a][g] = (valid && !fqy) ? Xl[oq1 + qyb + g + spx * a] : T(0);
       }
-    T pc[2][2];
-    T cp;
-    if (!TR) {
+    T pcur[2][2], pc[2][2];
 #pragma unroll
-      for (int gy = 0; gy < 2; ++gy)
+    for (int gy = 0; gy < 2; ++gy)
 #pragma unroll
-        for (int gx = 0; gx < 2; ++gx) {
-          T s = 0;
+      for (int gx = 0; gx < 2; ++gx) {
+        T s = 0, st = 0;
 #pragma unroll
-          for (int l = 0; l < NL; ++l) s += (l == lev) ? pl[l][gy][gx] : T(0);
-          pc[gy][gx] = s;
+        for (int l = 0; l < NL; ++l) {
+          s += (l == lev) ? pl[l][gy][gx] : T(0);
+          st += T(tm.T[l * 4 + lev]) * pl[l][gy][gx];
         }
-      cp = tau * bb;
-    } else {
-#pragma unroll
-      for (int gy = 0; gy < 2; ++gy)
-#pragma unroll
-        for (int gx = 0; gx < 2; ++gx) {
-          T s = 0;
-#pragma unroll
-          for (int l = 0; l < NL; ++l) s += T(tm.T[l * 4 + lev]) * pl[l][gy][gx];
-          pc[gy][gx] = s;
-        }
-      cp = bb;
-    }
-    // element u-rows: tau A_e u - cp E_e p  (A_e, E_e identical for every cell of the instance)
+        pcur[gy][gx] = s;
+        pc[gy][gx] = TR ? st : s;
+      }
+    const T cp = TR ? bb : tau * bb;
+    // ---- element u-rows: tau A_e u - cp E_e p  (A_e, E_e identical for every cell of the instance)
     {
       const T* AE = emat + I.emat_off;
       const T* EE = AE + 18 * 18;
@@ -144,15 +137,49 @@ __global__ __launch_bounds__(kT2 * kT2) void apply2d_kernel(const InstDev* __res
         E[rr][tid] = acc - cp * ep;
       }
     }
+    // ---- element flux rows (kept in registers until the u-rows are gathered):
+    //   q_x node (a, g): cqx sum_a2 MC(a, a2) qx[g][a2] - cbx (GB(a,0) p(g,0) + GB(a,1) p(g,1))
+    //   q_y node (a, g): cqy sum_a2 MC(a, a2) qy[a2][g] - cby (GB(a,0) p(0,g) + GB(a,1) p(1,g))
+    T fqx[2][3], fqy[3][2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        T mx_ = 0, my_ = 0;
+#pragma unroll
+        for (int a2 = 0; a2 < 3; ++a2) {
+          mx_ += T(MC(a, a2)) * qx[g][a2];
+          my_ += T(MC(a, a2)) * qy[a2][g];
+        }
+        fqx[g][a] = cqx * mx_ - cbx * (T(GB(a, 0)) * pcur[g][0] + T(GB(a, 1)) * pcur[g][1]);
+        fqy[a][g] = cqy * my_ - cby * (T(GB(a, 0)) * pcur[0][g] + T(GB(a, 1)) * pcur[1][g]);
+      }
+    // ---- p-rows (cell-local)
     T du[2][2], dq[2][2];
-    divu2d<T>(ux, uy, hx, hy, du);
-    divq2d<T>(qx, qy, hx, hy, dq);
+#pragma unroll
+    for (int gy = 0; gy < 2; ++gy)
+#pragma unroll
+      for (int gx = 0; gx < 2; ++gx) {
+        T sx = 0, sy = 0, tx = 0, ty = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            sx += T(VG(gy, b) * DG(gx, a)) * ux[b][a];
+            sy += T(DG(gy, b) * VG(gx, a)) * uy[b][a];
+          }
+          tx += T(DG(gx, a)) * qx[gy][a];
+          ty += T(DG(gy, a)) * qy[a][gx];
+        }
+        du[gy][gx] = sx * ihx + sy * ihy;
+        dq[gy][gx] = tx * ihx + ty * ihy;
+      }
     if (!TR) {
 #pragma unroll
       for (int gy = 0; gy < 2; ++gy)
 #pragma unroll
         for (int gx = 0; gx < 2; ++gx) {
-          const T z = bb * du[gy][gx] + Minv * pc[gy][gx];
+          const T z = bb * du[gy][gx] + Minv * pcur[gy][gx];
 #pragma unroll
           for (int l = 0; l < NL; ++l)
             yp[l][gy][gx] += T(tm.T[l * 4 + lev]) * z + ((l == lev) ? tau * dq[gy][gx] : T(0));
@@ -165,96 +192,83 @@ __global__ __launch_bounds__(kT2 * kT2) void apply2d_kernel(const InstDev* __res
           T s = 0;
 #pragma unroll
           for (int l = 0; l < NL; ++l) s += T(tm.T[l * 4 + lev]) * pl[l][gy][gx];
-          Yl[I.off_p + (2 * i + gx) + (long long)spx * (2 * j + gy)] =
-              -w2 * (tau * dq[gy][gx] + tau * bb * du[gy][gx] + Minv * s);
+          Yl[op + qyb + gx + spx * gy] = -w2 * (tau * dq[gy][gx] + tau * bb * du[gy][gx] + Minv * s);
         }
     }
     __syncthreads();
 
-    // ---- u-rows: sum element contributions of the (up to 4) cells of each node
-    const int nu = nmx * nmy;
-    for (int idx = tid; idx < 2 * nu; idx += kT2 * kT2) {
-      const int c = idx >= nu;
-      const int r = idx - c * nu;
-      const int mx = 2 * i0 + r % nmx, my = 2 * j0 + r / nmx;
-      const long long go = (c ? I.off_u[1] : I.off_u[0]) + mx + (long long)sux * my;
-      T v;
-      if (u_fixed(I, c, mx, my, 0)) {
-        v = Xl[go];
-      } else {
-        // the (up to) two cells along each axis that share the node, low first
-        const bool xo = mx & 1, yo = my & 1;
-        const int cx0 = xo ? (mx - 1) / 2 : mx / 2 - 1, ax0 = xo ? 1 : 2;
-        const int cy0 = yo ? (my - 1) / 2 : my / 2 - 1, ay0 = yo ? 1 : 2;
-        const bool vx0 = cx0 >= 0, vx1 = !xo && (mx / 2 < nx);
-        const bool vy0 = cy0 >= 0, vy1 = !yo && (my / 2 < ny);
-        const int tx0 = cx0 - i0 + 1, ty0 = cy0 - j0 + 1;
-        v = 0;
-        if (vy0 && vx0) v += E[c * 9 + ay0 * 3 + ax0][ty0 * kT2 + tx0];
-        if (vy0 && vx1) v += E[c * 9 + ay0 * 3 + 0][ty0 * kT2 + tx0 + 1];
-        if (vy1 && vx0) v += E[c * 9 + 0 * 3 + ax0][(ty0 + 1) * kT2 + tx0];
-        if (vy1 && vx1) v += E[c * 9 + 0][(ty0 + 1) * kT2 + tx0 + 1];
-      }
-      Yl[go] = v;
-    }
-    // ---- q-rows: tau (Mq q + B p), node by node along the flux axis
-    const T cqx = tau * hx * hy * T(0.5), cbx = tau * hy * T(0.5);
-    const int nqx = nmx * noy;
-    for (int idx = tid; idx < nqx; idx += kT2 * kT2) {
-      const int mx = 2 * i0 + idx % nmx, oy = 2 * j0 + idx / nmx;
-      const long long go = I.off_q[0] + mx + (long long)sux * oy;
-      T v;
-      if (q_fixed(I, 0, mx)) {
-        v = Xl[go];
-      } else {
-        v = 0;
-        const int jj = oy >> 1;
+    // ---- u-rows: each owned cell sums its lower-left 2x2 nodes (and the top/right
+    // boundary nodes of the last cells) from the element rows of the cells sharing them
+    if (owned) {
+#pragma unroll 1
+      for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          int ii, a;
-          if (mx & 1) { if (s) break; ii = (mx - 1) / 2; a = 1; }
-          else { ii = mx / 2 - 1 + s; a = s ? 0 : 2; if (ii < 0 || ii >= nx) continue; }
-          T m = 0;
+        for (int b = 0; b < 3; ++b)
 #pragma unroll
-          for (int a2 = 0; a2 < 3; ++a2) {
-            const int m2 = 2 * ii + a2;
-            m += T(MC(a, a2)) * ld(Xl + I.off_q[0] + m2 + (long long)sux * oy, q_fixed(I, 0, m2));
+          for (int a = 0; a < 3; ++a) {
+            if ((a == 2 && !lastx) || (b == 2 && !lasty)) continue;
+            const int mx = 2 * i + a, my = 2 * j + b;
+            const int go = (c ? ou1 : ou0) + ub + a + sux * b;
+            const bool fixed = my == 0 || (c == 0 && (mx == 0 || mx == 2 * nx));
+            T v;
+            if (fixed) {
+              v = Xl[go];
+            } else {
+              v = 0;
+#pragma unroll
+              for (int sy = 0; sy < 2; ++sy) {
+                // cells along y sharing row b: b == 0 -> (j-1: local 2), (j: local 0); else (j: local b)
+                if (b != 0 && sy == 0) continue;
+                const int lb = b != 0 ? b : (sy == 0 ? 2 : 0);
+                const int dy = (b == 0 && sy == 0) ? -kT2 : 0;
+#pragma unroll
+                for (int sx = 0; sx < 2; ++sx) {
+                  if (a != 0 && sx == 0) continue;
+                  const int la = a != 0 ? a : (sx == 0 ? 2 : 0);
+                  const int dx = (a == 0 && sx == 0) ? -1 : 0;
+                  v += E[c * 9 + lb * 3 + la][tid + dy + dx];
+                }
+              }
+            }
+            Yl[go] = v;
           }
-          const T* pp = Xl + I.off_p + 2 * ii + (long long)spx * oy;
-          const T bp = T(GB(a, 0)) * pp[0] + T(GB(a, 1)) * pp[1];
-          v += cqx * kinv[ii + (long long)nx * jj] * m - cbx * bp;
-        }
-      }
-      Yl[go] = v;
     }
-    const T cqy = tau * hx * hy * T(0.5), cby = tau * hx * T(0.5);
-    const int nqy = nox * nmy;
-    for (int idx = tid; idx < nqy; idx += kT2 * kT2) {
-      const int ox = 2 * i0 + idx % nox, my = 2 * j0 + idx / nox;
-      const long long go = I.off_q[1] + ox + (long long)spx * my;
-      T v;
-      if (q_fixed(I, 1, my)) {
-        v = Xl[go];
-      } else {
-        v = 0;
-        const int ii = ox >> 1;
+    __syncthreads();
+    // ---- flux rows: stage the element rows, then each owned cell sums its nodes
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          int jj, a;
-          if (my & 1) { if (s) break; jj = (my - 1) / 2; a = 1; }
-          else { jj = my / 2 - 1 + s; a = s ? 0 : 2; if (jj < 0 || jj >= ny) continue; }
-          T m = 0;
+    for (int g = 0; g < 2; ++g)
 #pragma unroll
-          for (int a2 = 0; a2 < 3; ++a2) {
-            const int m2 = 2 * jj + a2;
-            m += T(MC(a, a2)) * ld(Xl + I.off_q[1] + ox + (long long)spx * m2, q_fixed(I, 1, m2));
-          }
-          const T* pp = Xl + I.off_p + ox + (long long)spx * (2 * jj);
-          const T bp = T(GB(a, 0)) * pp[0] + T(GB(a, 1)) * pp[spx];
-          v += cqy * kinv[ii + (long long)nx * jj] * m - cby * bp;
-        }
+      for (int a = 0; a < 3; ++a) {
+        E[g * 3 + a][tid] = fqx[g][a];
+        E[6 + a * 2 + g][tid] = fqy[a][g];
       }
-      Yl[go] = v;
+    __syncthreads();
+    if (owned) {
+#pragma unroll 1
+      for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          // q_x node (2i + a, 2j + g)
+          if (!(a == 2 && !lastx)) {
+            const int go = oq0 + ub + a + sux * g;
+            const bool fixed = (a == 0 && i == 0) || (a == 2 && lastx);
+            T v;
+            if (fixed) v = Xl[go];
+            else if (a == 0) v = E[g * 3 + 2][tid - 1] + E[g * 3 + 0][tid];
+            else v = E[g * 3 + a][tid];
+            Yl[go] = v;
+          }
+          // q_y node (2i + g, 2j + a)
+          if (!(a == 2 && !lasty)) {
+            const int go = oq1 + qyb + g + spx * a;
+            const bool fixed = a == 0 && j == 0;
+            T v;
+            if (fixed) v = Xl[go];
+            else if (a == 0) v = E[6 + 2 * 2 + g][tid - kT2] + E[6 + 0 * 2 + g][tid];
+            else v = E[6 + a * 2 + g][tid];
+            Yl[go] = v;
+          }
+        }
     }
     __syncthreads();
   }
@@ -265,8 +279,7 @@ __global__ __launch_bounds__(kT2 * kT2) void apply2d_kernel(const InstDev* __res
 #pragma unroll
       for (int gy = 0; gy < 2; ++gy)
 #pragma unroll
-        for (int gx = 0; gx < 2; ++gx)
-          Yb[lev * N + I.off_p + (2 * i + gx) + (long long)spx * (2 * j + gy)] = -w2 * yp[lev][gy][gx];
+        for (int gx = 0; gx < 2; ++gx) Yb[lev * N + op + qyb + gx + spx * gy] = -w2 * yp[lev][gy][gx];
   }
 }
 

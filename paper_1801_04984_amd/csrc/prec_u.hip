@@ -19,7 +19,10 @@ constexpr int kUO = kUT - 1;
 
 int uapply_tile(int dim) { return dim == 2 ? kUO : -1; }
 
-// y = tau A x (mode 0) or y = b - tau A x (mode 1); identity on essential rows
+// y = tau A x (mode 0) or y = b - tau A x (mode 1); essential rows: y = 0 (mode 0), y = b (mode 1).
+// One block = 16x16 cells (15x15 owned + low-side halo); each owned cell sums
+// its lower-left 2x2 nodes (and the top/right boundary nodes of the last
+// cells) from the element rows of the cells sharing them, staged in LDS.
 template <typename T>
 __global__ __launch_bounds__(256) void uapply2d_kernel(const UGridSeg* __restrict__ segs, const int4* __restrict__ work,
                                                        int mode, const T* __restrict__ X, const T* __restrict__ Bv,
@@ -34,28 +37,26 @@ __global__ __launch_bounds__(256) void uapply2d_kernel(const UGridSeg* __restric
   T* Yl = Y + vo;
   const int lx = threadIdx.x, ly = threadIdx.y, tid = ly * kUT + lx;
   const int nx = G.n[0], ny = G.n[1];
-  const int i0 = w.y * kUO, j0 = w.z * kUO;
-  const int i = i0 - 1 + lx, jc = j0 - 1 + ly;
+  const int i = w.y * kUO - 1 + lx, jc = w.z * kUO - 1 + ly;
   const bool valid = (i >= 0) && (i < nx) && (jc >= 0) && (jc < ny);
+  const bool owned = valid && lx >= 1 && ly >= 1;
+  const bool lastx = i == nx - 1, lasty = jc == ny - 1;
   const int sux = G.su[0];
-  const long long nu1 = (long long)G.su[0] * G.su[1];
-  T ux[3][3], uy[3][3];
+  const int nu1 = G.su[0] * G.su[1];
+  const int ub = 2 * i + sux * (2 * jc);
+  T uu[18];
 #pragma unroll
   for (int b = 0; b < 3; ++b)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const int mx = 2 * i + a, my = 2 * jc + b;
-      const long long o = mx + (long long)sux * my;
-      ux[b][a] = (valid && !ugrid_fixed(2, G.su, 0, mx, my, 0)) ? Xl[o] : T(0);
-      uy[b][a] = (valid && !ugrid_fixed(2, G.su, 1, mx, my, 0)) ? Xl[nu1 + o] : T(0);
+      const bool bot = b == 0 && jc == 0;
+      const bool fx = bot || (a == 0 && i == 0) || (a == 2 && lastx);
+      const int o = ub + a + sux * b;
+      uu[b * 3 + a] = (valid && !fx) ? Xl[o] : T(0);
+      uu[9 + b * 3 + a] = (valid && !bot) ? Xl[nu1 + o] : T(0);
     }
   {
     const T* AE = emat + G.emat_off;   // tau A_e of this level (18x18)
-    T uu[18];
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) { uu[b * 3 + a] = ux[b][a]; uu[9 + b * 3 + a] = uy[b][a]; }
 #pragma unroll
     for (int rr = 0; rr < 18; ++rr) {
       T acc = 0;
@@ -65,33 +66,35 @@ __global__ __launch_bounds__(256) void uapply2d_kernel(const UGridSeg* __restric
     }
   }
   __syncthreads();
-  const int mxe = (i0 + kUO >= nx) ? 2 * nx + 1 : 2 * i0 + 2 * kUO;
-  const int mye = (j0 + kUO >= ny) ? 2 * ny + 1 : 2 * j0 + 2 * kUO;
-  const int nmx = mxe - 2 * i0, nmy = mye - 2 * j0;
-  const int nuo = nmx * nmy;
-  for (int idx = tid; idx < 2 * nuo; idx += kUT * kUT) {
-    const int c = idx >= nuo;
-    const int rr = idx - c * nuo;
-    const int mx = 2 * i0 + rr % nmx, my = 2 * j0 + rr / nmx;
-    const long long go = c * nu1 + mx + (long long)sux * my;
-    T v;
-    if (ugrid_fixed(2, G.su, c, mx, my, 0)) {
-      v = T(0);
-    } else {
-      const bool xo = mx & 1, yo = my & 1;
-      const int cx0 = xo ? (mx - 1) / 2 : mx / 2 - 1, ax0 = xo ? 1 : 2;
-      const int cy0 = yo ? (my - 1) / 2 : my / 2 - 1, ay0 = yo ? 1 : 2;
-      const bool vx0 = cx0 >= 0, vx1 = !xo && (mx / 2 < nx);
-      const bool vy0 = cy0 >= 0, vy1 = !yo && (my / 2 < ny);
-      const int tx0 = cx0 - i0 + 1, ty0 = cy0 - j0 + 1;
-      v = 0;
-      if (vy0 && vx0) v += E[c * 9 + ay0 * 3 + ax0][ty0 * kUT + tx0];
-      if (vy0 && vx1) v += E[c * 9 + ay0 * 3 + 0][ty0 * kUT + tx0 + 1];
-      if (vy1 && vx0) v += E[c * 9 + ax0][(ty0 + 1) * kUT + tx0];
-      if (vy1 && vx1) v += E[c * 9 + 0][(ty0 + 1) * kUT + tx0 + 1];
-    }
-    Yl[go] = mode == 0 ? v : Bl[go] - v;
-  }
+  if (!owned) return;
+#pragma unroll 1
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if ((a == 2 && !lastx) || (b == 2 && !lasty)) continue;
+        const int mx = 2 * i + a, my = 2 * jc + b;
+        const int go = c * nu1 + ub + a + sux * b;
+        const bool fixed = my == 0 || (c == 0 && (mx == 0 || mx == 2 * nx));
+        T v = 0;
+        if (!fixed) {
+#pragma unroll
+          for (int sy = 0; sy < 2; ++sy) {
+            if (b != 0 && sy == 0) continue;
+            const int lb = b != 0 ? b : (sy == 0 ? 2 : 0);
+            const int dy = (b == 0 && sy == 0) ? -kUT : 0;
+#pragma unroll
+            for (int sx = 0; sx < 2; ++sx) {
+              if (a != 0 && sx == 0) continue;
+              const int la = a != 0 ? a : (sx == 0 ? 2 : 0);
+              const int dx = (a == 0 && sx == 0) ? -1 : 0;
+              v += E[c * 9 + lb * 3 + la][tid + dy + dx];
+            }
+          }
+        }
+        Yl[go] = mode == 0 ? v : Bl[go] - v;
+      }
 }
 
 template <typename T>
