@@ -358,7 +358,7 @@ __global__ __launch_bounds__(256) void prows_mix_kernel(const InstDev* __restric
 }
 
 static dim3 g3(long long maxlen, int count, int nj) {
-  long long b = (maxlen + 255) / 256;
+  long long b = (maxlen + kBlk - 1) / kBlk;
   return dim3((unsigned)(b < 1 ? 1 : (b > 65535 ? 65535 : b)), count, nj);
 }
 
@@ -373,14 +373,14 @@ static void apply3d_nl(const ApplyArgs& a, const void* x, void* y, int tr, long 
   else
     hipLaunchKernelGGL((apply3d_u_kernel<T, NL, false>), dim3(a.nwork, NL), dim3(64 * kW3), 0, a.stream, a.inst,
                        a.work, apply3d_tile_cells_z(a.variant), *a.tm, em, X, Y);
-  hipLaunchKernelGGL((qrows_kernel<T>), g3(maxN, count, NL), dim3(256), 0, a.stream, a.inst, (const T*)a.kinv, X, Y);
+  hipLaunchKernelGGL((qrows_kernel<T>), g3(maxN, count, NL), dim3(kBlk), 0, a.stream, a.inst, (const T*)a.kinv, X, Y);
   if (tr) {
-    hipLaunchKernelGGL((prows_local_kernel<T, true, 3>), g3(maxc, count, NL), dim3(256), 0, a.stream, a.inst, X, Y);
-    hipLaunchKernelGGL((prows_mix_kernel<T, NL, true, 3>), g3(maxc, count, 1), dim3(256), 0, a.stream, a.inst, *a.tm,
+    hipLaunchKernelGGL((prows_local_kernel<T, true, 3>), g3(maxc, count, NL), dim3(kBlk), 0, a.stream, a.inst, X, Y);
+    hipLaunchKernelGGL((prows_mix_kernel<T, NL, true, 3>), g3(maxc, count, 1), dim3(kBlk), 0, a.stream, a.inst, *a.tm,
                        X, Y);
   } else {
-    hipLaunchKernelGGL((prows_local_kernel<T, false, 3>), g3(maxc, count, NL), dim3(256), 0, a.stream, a.inst, X, Y);
-    hipLaunchKernelGGL((prows_mix_kernel<T, NL, false, 3>), g3(maxc, count, 1), dim3(256), 0, a.stream, a.inst,
+    hipLaunchKernelGGL((prows_local_kernel<T, false, 3>), g3(maxc, count, NL), dim3(kBlk), 0, a.stream, a.inst, X, Y);
+    hipLaunchKernelGGL((prows_mix_kernel<T, NL, false, 3>), g3(maxc, count, 1), dim3(kBlk), 0, a.stream, a.inst,
                        *a.tm, X, Y);
   }
 }

@@ -14,6 +14,12 @@
 
 namespace bt {
 
+// threads per block of the element-wise and gather kernels over segments
+#ifndef BT_BLK
+#define BT_BLK 256
+#endif
+constexpr int kBlk = BT_BLK;
+
 // ---------------------------------------------------------------------------
 // 1D bases on [0, 1]
 //   closed:  phi_0 = (2s-1)(s-1), phi_1 = 4s(1-s), phi_2 = s(2s-1)

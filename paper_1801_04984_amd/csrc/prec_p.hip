@@ -17,7 +17,7 @@
 namespace bt {
 
 static dim3 grid3(long long maxlen, int nseg, int nj) {
-  long long b = (maxlen + 255) / 256;
+  long long b = (maxlen + kBlk - 1) / kBlk;
   return dim3((unsigned)(b < 1 ? 1 : (b > 65535 ? 65535 : b)), nseg, nj);
 }
 
@@ -229,10 +229,10 @@ void launch_pdg(int dim, const InstDev* insts, const PDgSeg* segs, int nseg, int
                 hipStream_t s) {
   const long long maxc = maxnp >> dim;      // one thread per cell
   if (dim == 2)
-    hipLaunchKernelGGL((pdg_kernel<T, 2>), grid3(maxc, nseg, nj), dim3(256), 0, s, insts, segs, mode, cc, dqinv, dinv,
+    hipLaunchKernelGGL((pdg_kernel<T, 2>), grid3(maxc, nseg, nj), dim3(kBlk), 0, s, insts, segs, mode, cc, dqinv, dinv,
                        b, x, r, din, dout);
   else
-    hipLaunchKernelGGL((pdg_kernel<T, 3>), grid3(maxc, nseg, nj), dim3(256), 0, s, insts, segs, mode, cc, dqinv, dinv,
+    hipLaunchKernelGGL((pdg_kernel<T, 3>), grid3(maxc, nseg, nj), dim3(kBlk), 0, s, insts, segs, mode, cc, dqinv, dinv,
                        b, x, r, din, dout);
 }
 template void launch_pdg<double>(int, const InstDev*, const PDgSeg*, int, int, long long, int, ChebCoef,
@@ -243,9 +243,9 @@ template void launch_pdg<float>(int, const InstDev*, const PDgSeg*, int, int, lo
 void launch_pdg_diag(int dim, const InstDev* insts, const PDgSeg* segs, int nseg, int nj, long long maxnp,
                      const double* dqinv, double* dinv, hipStream_t s) {
   if (dim == 2)
-    hipLaunchKernelGGL(pdg_diag_kernel<2>, grid3(maxnp, nseg, nj), dim3(256), 0, s, insts, segs, dqinv, dinv);
+    hipLaunchKernelGGL(pdg_diag_kernel<2>, grid3(maxnp, nseg, nj), dim3(kBlk), 0, s, insts, segs, dqinv, dinv);
   else
-    hipLaunchKernelGGL(pdg_diag_kernel<3>, grid3(maxnp, nseg, nj), dim3(256), 0, s, insts, segs, dqinv, dinv);
+    hipLaunchKernelGGL(pdg_diag_kernel<3>, grid3(maxnp, nseg, nj), dim3(kBlk), 0, s, insts, segs, dqinv, dinv);
 }
 
 // ---- cell levels ------------------------------------------------------------------------
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(256) void pcell_diag_kernel(const PCellSeg* __restr
 template <typename T>
 void launch_pcell(const PCellSeg* segs, int nseg, int nj, long long maxc, int mode, ChebCoef cc, const T* coef,
                   const T* dinv, const T* b, T* x, T* r, const T* din, T* dout, hipStream_t s) {
-  hipLaunchKernelGGL((pcell_kernel<T>), grid3(maxc, nseg, nj), dim3(256), 0, s, segs, mode, cc, coef, dinv, b, x, r,
+  hipLaunchKernelGGL((pcell_kernel<T>), grid3(maxc, nseg, nj), dim3(kBlk), 0, s, segs, mode, cc, coef, dinv, b, x, r,
                      din, dout);
 }
 template void launch_pcell<double>(const PCellSeg*, int, int, long long, int, ChebCoef, const double*, const double*,
@@ -340,7 +340,7 @@ template void launch_pcell<float>(const PCellSeg*, int, int, long long, int, Che
                                   const float*, float*, float*, const float*, float*, hipStream_t);
 void launch_pcell_diag(const PCellSeg* segs, int nseg, int nj, long long maxc, const double* coef, double* dinv,
                        hipStream_t s) {
-  hipLaunchKernelGGL(pcell_diag_kernel, grid3(maxc, nseg, nj), dim3(256), 0, s, segs, coef, dinv);
+  hipLaunchKernelGGL(pcell_diag_kernel, grid3(maxc, nseg, nj), dim3(kBlk), 0, s, segs, coef, dinv);
 }
 
 // ---- Galerkin coefficients ----------------------------------------------------------------
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(256) void pcoef_first_kernel(const InstDev* __restr
 }
 void launch_pcoef_first(const InstDev* insts, const PDgSeg* fine, const PCellSeg* lev1, int nseg, long long maxc,
                         const double* dqinv, double* coef, hipStream_t s) {
-  hipLaunchKernelGGL(pcoef_first_kernel, grid3(maxc, nseg, 1), dim3(256), 0, s, insts, fine, lev1, dqinv, coef);
+  hipLaunchKernelGGL(pcoef_first_kernel, grid3(maxc, nseg, 1), dim3(kBlk), 0, s, insts, fine, lev1, dqinv, coef);
 }
 
 __global__ __launch_bounds__(256) void pcoef_coarsen_kernel(const PCellSeg* __restrict__ fine, const PCellSeg* __restrict__ coarse,
@@ -430,7 +430,7 @@ __global__ __launch_bounds__(256) void pcoef_coarsen_kernel(const PCellSeg* __re
 }
 void launch_pcoef_coarsen(const PCellSeg* fine, const PCellSeg* coarse, int nseg, long long maxc, const double* coef_f,
                           double* coef_c, hipStream_t s) {
-  hipLaunchKernelGGL(pcoef_coarsen_kernel, grid3(maxc, nseg, 1), dim3(256), 0, s, fine, coarse, coef_f, coef_c);
+  hipLaunchKernelGGL(pcoef_coarsen_kernel, grid3(maxc, nseg, 1), dim3(kBlk), 0, s, fine, coarse, coef_f, coef_c);
 }
 
 // ---- transfers ------------------------------------------------------------------------------
@@ -522,22 +522,22 @@ __global__ __launch_bounds__(256) void p_prolong_cell_kernel(const PCellSeg* __r
 template <typename T>
 void launch_p_restrict_dg(const InstDev* insts, const PDgSeg* fine, const PCellSeg* coarse, int nseg, int nj,
                           long long maxc, const T* r, T* b, hipStream_t s) {
-  hipLaunchKernelGGL((p_restrict_dg_kernel<T>), grid3(maxc, nseg, nj), dim3(256), 0, s, insts, fine, coarse, r, b);
+  hipLaunchKernelGGL((p_restrict_dg_kernel<T>), grid3(maxc, nseg, nj), dim3(kBlk), 0, s, insts, fine, coarse, r, b);
 }
 template <typename T>
 void launch_p_prolong_dg(const InstDev* insts, const PDgSeg* fine, const PCellSeg* coarse, int nseg, int nj,
                          long long maxnp, double w, const T* e, T* x, hipStream_t s) {
-  hipLaunchKernelGGL((p_prolong_dg_kernel<T>), grid3(maxnp, nseg, nj), dim3(256), 0, s, insts, fine, coarse, w, e, x);
+  hipLaunchKernelGGL((p_prolong_dg_kernel<T>), grid3(maxnp, nseg, nj), dim3(kBlk), 0, s, insts, fine, coarse, w, e, x);
 }
 template <typename T>
 void launch_p_restrict_cell(const PCellSeg* fine, const PCellSeg* coarse, int nseg, int nj, long long maxc,
                             const T* r, T* b, hipStream_t s) {
-  hipLaunchKernelGGL((p_restrict_cell_kernel<T>), grid3(maxc, nseg, nj), dim3(256), 0, s, fine, coarse, r, b);
+  hipLaunchKernelGGL((p_restrict_cell_kernel<T>), grid3(maxc, nseg, nj), dim3(kBlk), 0, s, fine, coarse, r, b);
 }
 template <typename T>
 void launch_p_prolong_cell(const PCellSeg* fine, const PCellSeg* coarse, int nseg, int nj, long long maxc, double w,
                            const T* e, T* x, hipStream_t s) {
-  hipLaunchKernelGGL((p_prolong_cell_kernel<T>), grid3(maxc, nseg, nj), dim3(256), 0, s, fine, coarse, w, e, x);
+  hipLaunchKernelGGL((p_prolong_cell_kernel<T>), grid3(maxc, nseg, nj), dim3(kBlk), 0, s, fine, coarse, w, e, x);
 }
 #define BT_INST_P(T)                                                                                                 \
   template void launch_p_restrict_dg<T>(const InstDev*, const PDgSeg*, const PCellSeg*, int, int, long long, const T*, \
@@ -587,7 +587,7 @@ __global__ __launch_bounds__(256) void dq_kernel(const InstDev* __restrict__ ins
   }
 }
 void launch_dq(const InstDev* insts, int count, long long maxN, const double* kinv, double* dqinv, hipStream_t s) {
-  hipLaunchKernelGGL(dq_kernel, grid3(maxN, count, 1), dim3(256), 0, s, insts, kinv, dqinv);
+  hipLaunchKernelGGL(dq_kernel, grid3(maxN, count, 1), dim3(kBlk), 0, s, insts, kinv, dqinv);
 }
 
 }  // namespace bt

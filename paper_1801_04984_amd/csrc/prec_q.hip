@@ -16,7 +16,7 @@
 namespace bt {
 
 static dim3 grid3(long long maxlen, int nseg, int nj) {
-  long long b = (maxlen + 255) / 256;
+  long long b = (maxlen + kBlk - 1) / kBlk;
   return dim3((unsigned)(b < 1 ? 1 : (b > 65535 ? 65535 : b)), nseg, nj);
 }
 
@@ -50,9 +50,9 @@ template <typename T>
 void launch_coupling(int dim, const InstDev* insts, int count, int nj, long long maxN, const T* rt, const T* zp, T* fu,
                      T* fq, hipStream_t s) {
   if (dim == 2)
-    hipLaunchKernelGGL((coupling_kernel<T, 2>), grid3(maxN, count, nj), dim3(256), 0, s, insts, rt, zp, fu, fq);
+    hipLaunchKernelGGL((coupling_kernel<T, 2>), grid3(maxN, count, nj), dim3(kBlk), 0, s, insts, rt, zp, fu, fq);
   else
-    hipLaunchKernelGGL((coupling_kernel<T, 3>), grid3(maxN, count, nj), dim3(256), 0, s, insts, rt, zp, fu, fq);
+    hipLaunchKernelGGL((coupling_kernel<T, 3>), grid3(maxN, count, nj), dim3(kBlk), 0, s, insts, rt, zp, fu, fq);
 }
 template void launch_coupling<double>(int, const InstDev*, int, int, long long, const double*, const double*,
                                       double*, double*, hipStream_t);
@@ -104,7 +104,7 @@ void launch_mq(int dim, const InstDev* insts, int count, int nj, long long maxN,
                const T* dinvq, const T* b, T* x, T* r, const T* din, T* dout, hipStream_t s) {
   (void)dim;
   (void)dinvq;
-  hipLaunchKernelGGL((mq_kernel<T>), grid3(maxN, count, nj), dim3(256), 0, s, insts, mode, cc, kinv, b, x, r, din,
+  hipLaunchKernelGGL((mq_kernel<T>), grid3(maxN, count, nj), dim3(kBlk), 0, s, insts, mode, cc, kinv, b, x, r, din,
                      dout);
 }
 template void launch_mq<double>(int, const InstDev*, int, int, long long, int, ChebCoef, const double*, const double*,
@@ -204,9 +204,9 @@ template <typename T>
 void launch_mq_lines(int dim, const InstDev* insts, int count, int nj, long long maxlines, const T* kinv, const T* b,
                      T* x, T* w, hipStream_t s) {
   if (dim == 2)
-    hipLaunchKernelGGL((mq_line_kernel<T, 2>), grid3(maxlines, count, nj), dim3(256), 0, s, insts, kinv, b, x, w);
+    hipLaunchKernelGGL((mq_line_kernel<T, 2>), grid3(maxlines, count, nj), dim3(kBlk), 0, s, insts, kinv, b, x, w);
   else
-    hipLaunchKernelGGL((mq_line_kernel<T, 3>), grid3(maxlines, count, nj), dim3(256), 0, s, insts, kinv, b, x, w);
+    hipLaunchKernelGGL((mq_line_kernel<T, 3>), grid3(maxlines, count, nj), dim3(kBlk), 0, s, insts, kinv, b, x, w);
 }
 template void launch_mq_lines<double>(int, const InstDev*, int, int, long long, const double*, const double*, double*,
                                       double*, hipStream_t);
@@ -242,10 +242,10 @@ void launch_prec_finalize(const InstDev* insts, int count, long long maxN, int n
                           const T* r, T* z, hipStream_t s) {
   dim3 g = grid3(maxN, count, 1);
   switch (nl) {
-    case 1: hipLaunchKernelGGL((finalize_kernel<T, 1>), g, dim3(256), 0, s, insts, Q, zt, r, z); break;
-    case 2: hipLaunchKernelGGL((finalize_kernel<T, 2>), g, dim3(256), 0, s, insts, Q, zt, r, z); break;
-    case 3: hipLaunchKernelGGL((finalize_kernel<T, 3>), g, dim3(256), 0, s, insts, Q, zt, r, z); break;
-    default: hipLaunchKernelGGL((finalize_kernel<T, 4>), g, dim3(256), 0, s, insts, Q, zt, r, z); break;
+    case 1: hipLaunchKernelGGL((finalize_kernel<T, 1>), g, dim3(kBlk), 0, s, insts, Q, zt, r, z); break;
+    case 2: hipLaunchKernelGGL((finalize_kernel<T, 2>), g, dim3(kBlk), 0, s, insts, Q, zt, r, z); break;
+    case 3: hipLaunchKernelGGL((finalize_kernel<T, 3>), g, dim3(kBlk), 0, s, insts, Q, zt, r, z); break;
+    default: hipLaunchKernelGGL((finalize_kernel<T, 4>), g, dim3(kBlk), 0, s, insts, Q, zt, r, z); break;
   }
 }
 template void launch_prec_finalize<double>(const InstDev*, int, long long, int, const Mat4&, const double*,

@@ -144,8 +144,8 @@ __global__ __launch_bounds__(256) void rpass_kernel(const RPass* __restrict__ se
 template <typename T>
 void launch_rpass(const RPass* segs, int nseg, int nj, long long maxout, const double* tab, const T* in, T* out,
                   hipStream_t s) {
-  long long b = (maxout + 255) / 256;
-  hipLaunchKernelGGL((rpass_kernel<T>), dim3((unsigned)(b > 65535 ? 65535 : (b < 1 ? 1 : b)), nseg, nj), dim3(256), 0,
+  long long b = (maxout + kBlk - 1) / kBlk;
+  hipLaunchKernelGGL((rpass_kernel<T>), dim3((unsigned)(b > 65535 ? 65535 : (b < 1 ? 1 : b)), nseg, nj), dim3(kBlk), 0,
                      s, segs, tab, in, out);
 }
 template void launch_rpass<double>(const RPass*, int, int, long long, const double*, const double*, double*,
@@ -192,8 +192,8 @@ __global__ __launch_bounds__(256) void uprolong_kernel(const UProl* __restrict__
 template <typename T>
 void launch_uprolong(const UProl* segs, int nseg, int nj, long long maxfine, const double* tab, const T* e, T* x,
                      hipStream_t s) {
-  long long b = (maxfine + 255) / 256;
-  hipLaunchKernelGGL((uprolong_kernel<T>), dim3((unsigned)(b > 65535 ? 65535 : (b < 1 ? 1 : b)), nseg, nj), dim3(256),
+  long long b = (maxfine + kBlk - 1) / kBlk;
+  hipLaunchKernelGGL((uprolong_kernel<T>), dim3((unsigned)(b > 65535 ? 65535 : (b < 1 ? 1 : b)), nseg, nj), dim3(kBlk),
                      0, s, segs, tab, e, x);
 }
 template void launch_uprolong<double>(const UProl*, int, int, long long, const double*, const double*, double*,
@@ -214,8 +214,8 @@ __global__ __launch_bounds__(256) void muldinv_kernel(const LSeg* __restrict__ s
 template <typename T>
 void launch_mul_dinv(const LSeg* segs, int nseg, int nj, long long maxlen, const T* dinv, const T* x, T* y,
                      hipStream_t s) {
-  long long b = (maxlen + 255) / 256;
-  hipLaunchKernelGGL((muldinv_kernel<T>), dim3((unsigned)(b > 65535 ? 65535 : (b < 1 ? 1 : b)), nseg, nj), dim3(256), 0,
+  long long b = (maxlen + kBlk - 1) / kBlk;
+  hipLaunchKernelGGL((muldinv_kernel<T>), dim3((unsigned)(b > 65535 ? 65535 : (b < 1 ? 1 : b)), nseg, nj), dim3(kBlk), 0,
                      s, segs, dinv, x, y);
 }
 template void launch_mul_dinv<double>(const LSeg*, int, int, long long, const double*, const double*, double*,

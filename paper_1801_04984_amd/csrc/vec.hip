@@ -250,18 +250,18 @@ __global__ __launch_bounds__(256) void addseg_kernel(const LSeg* __restrict__ se
     x[off + i] += T(a) * d[off + i];
 }
 static dim3 lgrid(long long maxlen, int nseg, int nj) {
-  long long b = (maxlen + 255) / 256;
-  return dim3((unsigned)(b > 2048 ? 2048 : (b < 1 ? 1 : b)), nseg, nj);
+  long long b = (maxlen + kBlk - 1) / kBlk;
+  return dim3((unsigned)(b > 8192 ? 8192 : (b < 1 ? 1 : b)), nseg, nj);
 }
 template <typename T>
 void cheb_update(const LSeg* segs, int nseg, int nj, long long maxlen, int mode, double rho, double sig, T* x, T* r,
                  T* d, const T* y, const T* dinv, const T* b, hipStream_t s) {
-  hipLaunchKernelGGL((cheb_kernel<T>), lgrid(maxlen, nseg, nj), dim3(256), 0, s, segs, mode, rho, sig, x, r, d, y,
+  hipLaunchKernelGGL((cheb_kernel<T>), lgrid(maxlen, nseg, nj), dim3(kBlk), 0, s, segs, mode, rho, sig, x, r, d, y,
                      dinv, b);
 }
 template <typename T>
 void seg_add(const LSeg* segs, int nseg, int nj, long long maxlen, const T* d, T* x, double a, hipStream_t s) {
-  hipLaunchKernelGGL((addseg_kernel<T>), lgrid(maxlen, nseg, nj), dim3(256), 0, s, segs, d, x, a);
+  hipLaunchKernelGGL((addseg_kernel<T>), lgrid(maxlen, nseg, nj), dim3(kBlk), 0, s, segs, d, x, a);
 }
 template void cheb_update<double>(const LSeg*, int, int, long long, int, double, double, double*, double*, double*,
                                   const double*, const double*, const double*, hipStream_t);
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256) void zseg_kernel(const LSeg* __restrict__ segs
 }
 template <typename T>
 void seg_zero(const LSeg* segs, int nseg, int nj, long long maxlen, T* x, hipStream_t s) {
-  hipLaunchKernelGGL((zseg_kernel<T>), lgrid(maxlen, nseg, nj), dim3(256), 0, s, segs, x);
+  hipLaunchKernelGGL((zseg_kernel<T>), lgrid(maxlen, nseg, nj), dim3(kBlk), 0, s, segs, x);
 }
 template void seg_zero<double>(const LSeg*, int, int, long long, double*, hipStream_t);
 template void seg_zero<float>(const LSeg*, int, int, long long, float*, hipStream_t);
