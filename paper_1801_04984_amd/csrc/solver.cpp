@@ -36,7 +36,7 @@ constexpr double kULo = 1.0 / 15.0, kUHi = 1.1;
 constexpr double kQLo = 0.25, kQHi = 1.75;  // Gershgorin interval of Dq^-1 Mq
 constexpr long long kLineSolveMinLines = 16384;   // automatic flux-block choice
 constexpr int kQDegDefault = 8;                     // Chebyshev degree when line solves are not used
-constexpr long long kPCoarseCells = 64;
+constexpr long long kPCoarseCells = 256;
 constexpr long long kUCoarseDofs = 1100;
 
 template <typename T>
