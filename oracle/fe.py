@@ -272,12 +272,13 @@ def constrained_mask(mesh: Mesh):
     return mask
 
 
-def assemble_spatial(mesh: Mesh, mat: Material, theta):
-    """Global K_s and M_t (unconstrained), CSR, for cellwise theta = log K."""
+def cell_matrices(mesh: Mesh, mat: Material):
+    """Per-cell blocks over the local DoFs (order of local_dofs):
+    K_s of a cell = Ks_static + (1/K_cell) Mq_loc, and M_t of a cell = Mt_loc
+    (section "Monolithic Approach" block structure, mass equation negated)."""
     em = element_matrices(mesh.d, mesh.h, mat)
-    G = global_map(mesh)
     iu, iq, ip = em["iu"], em["iq"], em["ip"]
-    nl = G.shape[1]
+    nl = len(iu) + len(iq) + len(ip)
     Ks_static = np.zeros((nl, nl))
     Ks_static[np.ix_(iu, iu)] = em["A"]
     Ks_static[np.ix_(iu, ip)] = -mat.b * em["E"]
@@ -288,6 +289,14 @@ def assemble_spatial(mesh: Mesh, mat: Material, theta):
     Mt_loc = np.zeros((nl, nl))
     Mt_loc[np.ix_(ip, iu)] = -mat.b * em["E"].T
     Mt_loc[np.ix_(ip, ip)] = -(1.0 / mat.M) * em["Mp"]
+    return Ks_static, Mq_loc, Mt_loc
+
+
+def assemble_spatial(mesh: Mesh, mat: Material, theta):
+    """Global K_s and M_t (unconstrained), CSR, for cellwise theta = log K."""
+    G = global_map(mesh)
+    nl = G.shape[1]
+    Ks_static, Mq_loc, Mt_loc = cell_matrices(mesh, mat)
     kinv = np.exp(-np.asarray(theta, float))
     rows = np.repeat(G, nl, axis=1).reshape(-1)
     cols = np.tile(G, (1, nl)).reshape(-1)
