@@ -96,24 +96,48 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
   for (int idx = tid; idx < 27 * NC; idx += NT) Cc[idx] = T(0);
 
   for (int k = kbeg; k < kend; ++k) {
-    // ---- gather element vectors (essential u masked) and the scaled coupling pressure
-    for (int idx = tid; idx < KR * NC; idx += NT) {
-      const int kr = idx >> 6, cell = idx & 63;
+    // ---- gather element vectors: the three node planes 2k..2k+2 of the tile
+    // (17 x 17 nodes per plane and component) are read once, coalesced along x,
+    // and every node is written to the element-vector slot of each cell that
+    // shares it (essential u masked).  Cells outside the mesh get partial
+    // vectors; their rows are never summed into an owned node.
+    constexpr int NX = 2 * kT3 + 1, NP = NX * NX;
+    for (int idx = tid; idx < 9 * NP; idx += NT) {
+      const int cz = idx / NP;                 // comp * 3 + plane
+      const int r = idx - cz * NP;
+      const int c2 = cz / 3, z = cz - 3 * c2;
+      const int ny_ = r / NX, nx_ = r - NX * ny_;
+      const int mx = 2 * (i0 - 1) + nx_, my = 2 * (j0 - 1) + ny_, mz = 2 * k + z;
+      T v = 0;
+      if (mx >= 0 && mx < J.su[0] && my >= 0 && my < J.su[1] && !ugrid_fixed(3, J.su, c2, mx, my, mz))
+        v = J.X[c2 * nu1 + mx + sy * my + sz * mz];
+      // cells of the tile sharing the node along x and y (local node a, b)
+#pragma unroll
+      for (int sj = 0; sj < 2; ++sj) {
+        int ly, b;
+        if (ny_ & 1) { if (sj) break; ly = ny_ >> 1; b = 1; }
+        else { ly = (ny_ >> 1) - sj; b = sj ? 2 : 0; if (ly < 0 || ly >= kT3) continue; }
+#pragma unroll
+        for (int si = 0; si < 2; ++si) {
+          int lx, a;
+          if (nx_ & 1) { if (si) break; lx = nx_ >> 1; a = 1; }
+          else { lx = (nx_ >> 1) - si; a = si ? 2 : 0; if (lx < 0 || lx >= kT3) continue; }
+          Ul[(c2 * 27 + z * 9 + b * 3 + a) * kLD3 + ly * kT3 + lx] = v;
+        }
+      }
+    }
+    // coupling columns (scaled mixed pressure at the cell's Gauss points) and padding
+    for (int idx = tid; idx < (KR - 81) * NC; idx += NT) {
+      const int kr = 81 + (idx >> 6), cell = idx & 63;
       const int i = i0 - 1 + (cell & 7), j = j0 - 1 + (cell >> 3);
       T v = 0;
-      if (i >= 0 && i < nx && j >= 0 && j < ny) {
-        if (kr < 81) {
-          const int c2 = kr / 27, nd = kr - 27 * c2;
-          const int mx = 2 * i + nd % 3, my = 2 * j + (nd / 3) % 3, mz = 2 * k + nd / 9;
-          if (!ugrid_fixed(3, J.su, c2, mx, my, mz)) v = J.X[c2 * nu1 + mx + sy * my + sz * mz];
-        } else if (kr < 89 && J.npl > 0) {
-          const int g = kr - 81;
-          const long long o = (2 * i + (g & 1)) + (long long)J.sp[0] *
-                              ((2 * j + ((g >> 1) & 1)) + (long long)J.sp[1] * (2 * k + (g >> 2)));
-          T s = 0;
-          for (int l = 0; l < J.npl; ++l) s += J.pw[l] * J.P[l * J.plstride + o];
-          v = -J.cp * s;
-        }
+      if (kr < 89 && J.npl > 0 && i >= 0 && i < nx && j >= 0 && j < ny) {
+        const int g = kr - 81;
+        const long long o = (2 * i + (g & 1)) + (long long)J.sp[0] *
+                            ((2 * j + ((g >> 1) & 1)) + (long long)J.sp[1] * (2 * k + (g >> 2)));
+        T s = 0;
+        for (int l = 0; l < J.npl; ++l) s += J.pw[l] * J.P[l * J.plstride + o];
+        v = -J.cp * s;
       }
       Ul[kr * kLD3 + cell] = v;
     }
