@@ -18,12 +18,15 @@
 //
 // Work decomposition: one block = one tile of (TS-1)x(TS-1) owned cells plus a
 // one-cell halo on the low sides (TS x TS threads, one cell each; TS = 16 or
-// 8, chosen per handle by the tile autotuner: both give identical results).  Every
-// output DoF is written by exactly one block: u-rows are summed from the
-// per-cell element vectors staged in LDS in a fixed order (deterministic,
-// no atomics); q-rows are evaluated node by node from X; p-rows are
-// cell-local.  Halo cells are recomputed by both neighbours.
-#include "cell2d.h"
+// 8, chosen per handle by the tile autotuner: both give identical results).
+// Every cell computes its element rows (u, then flux), stages them in LDS,
+// and each owned cell sums its own nodes - the lower-left 2x2 node block of
+// the cell, plus the top/right boundary nodes of the last cells - from the
+// rows of the (up to four) cells sharing them, in a fixed order: every output
+// is written by exactly one thread, deterministically, without atomics or
+// index divisions.  p-rows are cell-local.  Halo cells are recomputed by both
+// neighbouring tiles.
+#include "common.h"
 #include "kernels.h"
 
 namespace bt {

@@ -116,7 +116,5 @@ __device__ __forceinline__ bool q_fixed(const InstDev& I, int c, int mc) {
   return mc == 0 || mc == I.su[c] - 1;
 }
 
-template <typename T>
-__device__ __forceinline__ T ld(const T* p, bool masked) { return masked ? T(0) : *p; }
 
 }  // namespace bt

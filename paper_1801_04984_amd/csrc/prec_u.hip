@@ -8,7 +8,7 @@
 // for non-nested meshes too); restriction is its transpose, applied as one
 // 1D pass per axis.  Essential rows are identity on every level; all level
 // vectors are kept zero there.
-#include "cell2d.h"
+#include "common.h"
 #include "prec.h"
 #include "rows.h"
 
