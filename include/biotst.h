@@ -65,7 +65,13 @@ typedef enum {
   BIOT_ERR_NONFINITE = 6   /* NaN/Inf met in a residual norm                     */
 } biot_status;
 
-typedef enum { BIOT_FP64 = 0, BIOT_MIXED = 1 } biot_precision;
+/* BIOT_FP64: everything in FP64.
+ * BIOT_MIXED: FP32 GMRES (FP32 operator apply and preconditioner, FP64 dot
+ *   accumulation, Hessenberg and coarse/diagonal inverses) as the inner solve of
+ *   FP64 iterative refinement on the FP64 residual.
+ * BIOT_FP32_PREC: FP64 flexible GMRES (FP64 apply and orthogonalisation) with
+ *   the whole preconditioner applied in FP32; one Krylov space, no refinement. */
+typedef enum { BIOT_FP64 = 0, BIOT_MIXED = 1, BIOT_FP32_PREC = 2 } biot_precision;
 typedef enum { BIOT_LOAD_STEP = 0, BIOT_LOAD_RAMP = 1 } biot_load_kind;
 
 /* One problem instance.  Section "Poroelasticity": isotropic C (lambda, mu),

@@ -1054,6 +1054,7 @@ struct SolveCtl {
   double rtol;
   int maxit, restart, qdeg;
   bool graph;
+  bool flex32 = false;   // FP64 flexible GMRES with the preconditioner applied in FP32
 };
 
 // y = b - A x into r (type T)
@@ -1115,7 +1116,22 @@ static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const Solv
     for (; jj < m && total < ctl.maxit; ++jj) {
       T* vj = B.V + (long long)jj * S;
       T* vn = B.V + (long long)(jj + 1) * S;
-      apply_prec_graph<T>(h, vj, B.t, ctl.qdeg, ctl.graph, s);
+      if constexpr (std::is_same<T, double>::value) {
+        if (ctl.flex32) {
+          // z_j = P32(v_j), kept in FP32 (the FP32 Krylov basis is unused in this mode);
+          // the Arnoldi relation uses exactly these values, so x += Z y stays consistent
+          auto& F = P->b32;
+          float* zj = F.V + (long long)jj * S;
+          vcast(vj, F.w, S, s);
+          apply_prec_graph<float>(h, F.w, F.t, ctl.qdeg, ctl.graph, s);
+          hip_check(hipMemcpyAsync(zj, F.t, sizeof(float) * S, hipMemcpyDeviceToDevice, s), "flexible basis");
+          vcast(zj, B.t, S, s);
+        } else {
+          apply_prec_graph<T>(h, vj, B.t, ctl.qdeg, ctl.graph, s);
+        }
+      } else {
+        apply_prec_graph<T>(h, vj, B.t, ctl.qdeg, ctl.graph, s);
+      }
       launch_apply(h, B.t, vn, transpose, std::is_same<T, float>::value ? 1 : 0, s);
       seg_mdot<T, T>(B.V, S, jj + 1, vn, P->d_gseg, cnt, dot_chunks(P->gmax), P->partial, P->dot1, s);
       seg_maxpy<T, T>(B.V, S, jj + 1, P->dot1, -1.0, vn, P->d_gseg, cnt, P->gmax, s);
@@ -1182,10 +1198,19 @@ static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const Solv
     }
     if (kmax > 0) {
       upload(coef, P->coef, s);
-      hip_check(hipMemsetAsync(B.w, 0, sizeof(T) * S, s), "zero");
-      seg_maxpy<T, T>(B.V, S, kmax, P->coef, 1.0, B.w, P->d_gseg, cnt, P->gmax, s);
-      apply_prec_graph<T>(h, B.w, B.t, ctl.qdeg, ctl.graph, s);
-      vaxpby<T>(1.0, B.t, 1.0, x, S, s);
+      bool done_update = false;
+      if constexpr (std::is_same<T, double>::value) {
+        if (ctl.flex32) {      // x += Z y
+          seg_maxpy<float, double>(P->b32.V, S, kmax, P->coef, 1.0, x, P->d_gseg, cnt, P->gmax, s);
+          done_update = true;
+        }
+      }
+      if (!done_update) {
+        hip_check(hipMemsetAsync(B.w, 0, sizeof(T) * S, s), "zero");
+        seg_maxpy<T, T>(B.V, S, kmax, P->coef, 1.0, B.w, P->d_gseg, cnt, P->gmax, s);
+        apply_prec_graph<T>(h, B.w, B.t, ctl.qdeg, ctl.graph, s);
+        vaxpby<T>(1.0, B.t, 1.0, x, S, s);
+      }
     }
     std::vector<double> prev = beta;
     residual<T>(h, b, x, B.r, transpose, s);
@@ -1220,7 +1245,8 @@ static void solve_impl(biot_problem_s* h, const double* b, double* x, int transp
   if (!(opts.rtol > 0) || !std::isfinite(opts.rtol)) throw BiotError{BIOT_ERR_ARG, "rtol must be > 0"};
   if (opts.maxit < 1) throw BiotError{BIOT_ERR_ARG, "maxit must be >= 1"};
   if (opts.restart < 1 || opts.restart > kMaxRestart) throw BiotError{BIOT_ERR_ARG, "restart must be in 1..64"};
-  if (opts.precision != BIOT_FP64 && opts.precision != BIOT_MIXED) throw BiotError{BIOT_ERR_ARG, "unknown precision"};
+  if (opts.precision != BIOT_FP64 && opts.precision != BIOT_MIXED && opts.precision != BIOT_FP32_PREC)
+    throw BiotError{BIOT_ERR_ARG, "unknown precision"};
   if (opts.cheb_degree < -1 || opts.cheb_degree > 64) throw BiotError{BIOT_ERR_ARG, "cheb_degree must be in -1..64"};
   if (opts.cheb_degree == -1) {
     // exact line solves need one thread per flux line: use them when the lines of
@@ -1231,8 +1257,9 @@ static void solve_impl(biot_problem_s* h, const double* b, double* x, int transp
   const int cnt = h->count;
   std::vector<int> its, rst, st;
   std::vector<double> rr;
-  if (opts.precision == BIOT_FP64) {
-    SolveCtl ctl{opts.rtol, opts.maxit, opts.restart, opts.cheb_degree, opts.graph != 0};
+  if (opts.precision == BIOT_FP64 || opts.precision == BIOT_FP32_PREC) {
+    SolveCtl ctl{opts.rtol, opts.maxit, opts.restart, opts.cheb_degree, opts.graph != 0,
+                 opts.precision == BIOT_FP32_PREC};
     gmres<double>(h, b, x, transpose, ctl, its, rst, rr, st, s);
     for (int k = 0; k < cnt; ++k) {
       info[k].iterations = its[k]; info[k].restarts = rst[k]; info[k].ir_sweeps = 0;

@@ -150,6 +150,8 @@ template void seg_maxpy<double, double>(const double*, long long, int, const dou
                                         int, long long, hipStream_t);
 template void seg_maxpy<float, float>(const float*, long long, int, const double*, double, float*, const VSeg*, int,
                                       long long, hipStream_t);
+template void seg_maxpy<float, double>(const float*, long long, int, const double*, double, double*, const VSeg*, int,
+                                       long long, hipStream_t);
 
 // ---- segmented scale: y[seg] = s[seg*64 + idx] * x[seg] (idx-th coefficient) ----------
 template <typename TX, typename TY>

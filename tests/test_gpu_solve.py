@@ -52,6 +52,23 @@ def test_solve_mixed_refined(r):
     h.close()
 
 
+@pytest.mark.parametrize("d,n,r", [(2, (20, 13), 1), (2, (33, 20), 2), (3, (5, 4, 6), 1)])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_solve_fp32_preconditioned_flexible(d, n, r, transpose):
+    """FP64 flexible GMRES with the preconditioner applied in FP32 reaches the
+    oracle's solution to the FP64 tolerance, forward and transposed."""
+    torch = torch_cuda()
+    wl = small_workload(d, n, r, seed=60 + d + r)
+    h, (prob,) = make_pair([wl])
+    b = _rhs(prob, seed=8)
+    ref = prob.solve(b, transpose=transpose)
+    x, info, st = h.solve(torch.tensor(b, device="cuda"), rtol=RT, precision=2, transpose=transpose)
+    assert st == 0 and info[0]["ir_sweeps"] == 0, info
+    err = field_rel(prob, x.cpu().numpy(), ref)
+    assert max(err.values()) < TOL, err
+    h.close()
+
+
 @pytest.mark.parametrize("r", [1, 2])
 def test_solve_batched_deep_hierarchy(r):
     """Equal-size and uneven instances whose elasticity multigrid has three
