@@ -183,11 +183,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c2", help="c1..c4; with --apply-only also c5 (64-instance batch)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the large-workload apply and batched objects")
-    ap.add_argument("--apply-only", action="store_true", help="only launch the operator apply (profiling)")
+    ap.add_argument("--apply-only", action="store_true", help="only time the operator apply (profiling target)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
@@ -199,20 +199,26 @@ def main():
     from paper_1801_04984_amd import BiotSlab, tuning
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.apply_only:
+        # profiling target: autotune, 50 FP64 and 50 FP32 applies, one 256 MiB copy
+        # (counter calibration); --workload c5 selects the 64-instance batch
+        wls = W.c5_batch() if args.workload == "c5" else [W.ALL[args.workload]()]
+        h = BiotSlab(wls, [w.log_k() for w in wls])
+        tuning.tune(h, path=None)
+        ms64, b64 = time_apply(torch, h, torch.float64, launches=50)
+        ms32, b32 = time_apply(torch, h, torch.float32, launches=50)
+        x = torch.randn(1 << 26, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": args.workload, "apply_ms": [ms64, ms32], "apply_bytes": [b64, b32],
+                          "tile_variant": h.get_tuning()["apply_variant"], "copy_bytes": 2 * x.numel() * 4}))
+        return
     wl = W.ALL[args.workload]()
     theta = wl.log_k()
     h = BiotSlab([wl], [theta])
     tune = tuning.tune(h, path=None)
     slab_dofs = h.slab_len
-
-    if args.apply_only:
-        ms64, b64 = time_apply(torch, h, torch.float64, launches=50)
-        x = torch.randn(1 << 26, device="cuda")       # 256 MiB copy for counter calibration
-        y = torch.empty_like(x)
-        y.copy_(x)
-        torch.cuda.synchronize()
-        print(json.dumps({"apply_ms": ms64, "apply_bytes": b64, "copy_bytes": 2 * x.numel() * 4}))
-        return
 
     state = h.zeros_state()
     march(h, args.warmup, 0.0, state, 0)
