@@ -39,8 +39,14 @@ constexpr double kULo = 1.0 / 15.0, kUHi = 1.1;
 constexpr double kQLo = 0.25, kQHi = 1.75;  // Gershgorin interval of Dq^-1 Mq
 constexpr long long kLineSolveMinLines = 16384;   // automatic flux-block choice
 constexpr int kQDegDefault = 8;                     // Chebyshev degree when line solves are not used
+// Coarsest multigrid levels: coarsening stops once the largest instance is
+// small, or once the dense inverses of the whole batch fit a byte budget that
+// keeps one dense coarse product cheaper than another level of the cycle
+// (the inverses stay resident in the last-level cache).
 constexpr long long kPCoarseCells = 256;
 constexpr long long kUCoarseDofs = 1100;
+constexpr long long kPCoarseBytes = 24LL << 20;   // sum over instances and levels j
+constexpr long long kUCoarseBytes = 48LL << 20;   // sum over instances (shared by the levels)
 
 template <typename T>
 struct PrecBufs {
@@ -96,6 +102,13 @@ struct PrecData {
   double *uAinv = nullptr, *pAinv = nullptr;
   int u_maxn = 0, p_maxn = 0;
   long long uAinv_len = 0, pAinv_len = 0;
+  // their in-place inversion on the device (one matrix per instance for u, per
+  // instance and level j for p)
+  std::vector<GJMat> gju, gjp;
+  GJMat *d_gju = nullptr, *d_gjp = nullptr;
+  double* gj_snap = nullptr;
+  long long gj_snap_len = 0;
+  int* gj_bad = nullptr;
   // GMRES segments
   std::vector<VSeg> gseg;
   VSeg* d_gseg = nullptr;
@@ -225,7 +238,9 @@ static void build_hierarchy(biot_problem_s* h, PrecData* P) {
     P->pc.push_back(lev);
     P->pc_total.push_back(voff / nl);
     P->pc_max.push_back(mx);
-    if (mx <= kPCoarseCells) break;
+    long long dbytes = 0;
+    for (const auto& c : lev) dbytes += 8LL * nl * c.ncells * c.ncells;
+    if (mx <= kPCoarseCells || dbytes <= kPCoarseBytes) break;
     for (int k = 0; k < cnt; ++k)
       for (int e = 0; e < d; ++e) n[k][e] = half(n[k][e]);
   }
@@ -281,7 +296,9 @@ static void build_hierarchy(biot_problem_s* h, PrecData* P) {
     P->u_total.push_back(lvtot);
     P->u_max.push_back(mx);
     ++level;
-    if (mx <= kUCoarseDofs) break;
+    long long dbytes = 0;
+    for (const auto& g : lev) dbytes += 8LL * g.nu * g.nu;
+    if (mx <= kUCoarseDofs || dbytes <= kUCoarseBytes) break;
     for (int k = 0; k < cnt; ++k)
       for (int e = 0; e < d; ++e) n[k][e] = half(n[k][e]);
   }
@@ -387,6 +404,13 @@ static void build_hierarchy(biot_problem_s* h, PrecData* P) {
     P->u_maxn = std::max(P->u_maxn, s.n);
   }
   P->uAinv_len = mo;
+  P->gju.clear();
+  long long so = 0;
+  for (const auto& d : P->ud) {
+    P->gju.push_back(GJMat{d.moff, so, d.n, 0});
+    so += 4LL * d.n;
+  }
+  P->gj_snap_len = so;
   mo = 0;
   for (int k = 0; k < cnt; ++k) {
     const PCellSeg& c = P->pc[P->npl - 1][k];
@@ -398,6 +422,15 @@ static void build_hierarchy(biot_problem_s* h, PrecData* P) {
     P->p_maxn = std::max(P->p_maxn, s.n);
   }
   P->pAinv_len = mo;
+  P->gjp.clear();
+  so = 0;
+  for (const auto& d : P->pd)
+    for (int j = 0; j < nl; ++j) {
+      P->gjp.push_back(GJMat{d.moff + j * d.mjstride, so, d.n, 0});
+      so += 4LL * d.n;
+    }
+  P->gj_snap_len = std::max(P->gj_snap_len, so);
+  if (P->u_maxn > 65535 || P->p_maxn > 65535) throw BiotError{BIOT_ERR_ARG, "coarse level too large"};
   // GMRES segments
   P->gseg.clear();
   P->gmax = 0;
@@ -483,6 +516,10 @@ void plan_solver_layout(biot_problem_s* h, Layout& L, bool carve) {
   P->d_pd = L.take<DSeg>(P->pd.size());
   P->uAinv = L.take<double>(P->uAinv_len);
   P->pAinv = L.take<double>(P->pAinv_len);
+  P->d_gju = L.take<GJMat>(P->gju.size());
+  P->d_gjp = L.take<GJMat>(P->gjp.size());
+  P->gj_snap = L.take<double>(std::max(1LL, P->gj_snap_len));
+  P->gj_bad = L.take<int>(1);
   P->d_gseg = L.take<VSeg>(P->gseg.size());
   const size_t nsc = (size_t)std::max(h->count * h->nl, h->count) * 64;
   P->partial = L.take<double>((size_t)std::max(h->count * h->nl, h->count) * kMaxChunks * 64);
@@ -505,39 +542,9 @@ void plan_solver_layout(biot_problem_s* h, Layout& L, bool carve) {
 // ---------------------------------------------------------------------------
 // host dense helpers
 // ---------------------------------------------------------------------------
-static void invert_dense(std::vector<double>& A, int n) {
-  // Gauss-Jordan with partial pivoting, in place
-  std::vector<int> piv(n);
-  std::vector<double> I(n * (size_t)n, 0.0);
-  for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
-  for (int k = 0; k < n; ++k) {
-    int p = k;
-    for (int i = k + 1; i < n; ++i)
-      if (std::fabs(A[(size_t)i * n + k]) > std::fabs(A[(size_t)p * n + k])) p = i;
-    if (A[(size_t)p * n + k] == 0.0) throw BiotError{BIOT_ERR_ARG, "singular coarse matrix"};
-    if (p != k) {
-      for (int j = 0; j < n; ++j) {
-        std::swap(A[(size_t)k * n + j], A[(size_t)p * n + j]);
-        std::swap(I[(size_t)k * n + j], I[(size_t)p * n + j]);
-      }
-    }
-    const double inv = 1.0 / A[(size_t)k * n + k];
-    for (int j = 0; j < n; ++j) { A[(size_t)k * n + j] *= inv; I[(size_t)k * n + j] *= inv; }
-    for (int i = 0; i < n; ++i) {
-      if (i == k) continue;
-      const double f = A[(size_t)i * n + k];
-      if (f == 0.0) continue;
-      double* Ai = &A[(size_t)i * n];
-      double* Ii = &I[(size_t)i * n];
-      const double* Ak = &A[(size_t)k * n];
-      const double* Ik = &I[(size_t)k * n];
-      for (int j = 0; j < n; ++j) { Ai[j] -= f * Ak[j]; Ii[j] -= f * Ik[j]; }
-    }
-  }
-  A.swap(I);
-}
-
-static std::vector<double> coarse_elast_inverse(const UGridSeg& g) {
+// assembled tau A of the coarsest elasticity level, essential rows and columns
+// replaced by the identity (inverted on the device)
+static std::vector<double> coarse_elast_matrix(const UGridSeg& g) {
   const int d = g.dim;
   const int n = (int)g.nu;
   const long long nn = (long long)g.su[0] * g.su[1] * g.su[2];
@@ -564,7 +571,6 @@ static std::vector<double> coarse_elast_inverse(const UGridSeg& g) {
       for (int q = 0; q < n; ++q) { A[(size_t)row * n + q] = 0.0; A[(size_t)q * n + row] = 0.0; }
       A[(size_t)row * n + row] = 1.0;
     }
-  invert_dense(A, n);
   return A;
 }
 
@@ -628,6 +634,16 @@ static void upload(const std::vector<X>& v, X* d, hipStream_t s) {
   if (v.empty()) return;
   hip_check(hipMemcpyAsync(d, v.data(), sizeof(X) * v.size(), hipMemcpyHostToDevice, s), "upload");
   hip_check(hipStreamSynchronize(s), "upload sync");
+}
+
+// invert the uploaded coarse matrices in place and fail on a zero pivot
+static void invert_on_device(PrecData* P, const GJMat* mats, int nmats, int maxn, double* A, hipStream_t s) {
+  hip_check(hipMemsetAsync(P->gj_bad, 0, sizeof(int), s), "gj flag clear");
+  dense_invert(mats, nmats, maxn, A, P->gj_snap, P->gj_bad, s);
+  int bad = 0;
+  hip_check(hipMemcpyAsync(&bad, P->gj_bad, sizeof(int), hipMemcpyDeviceToHost, s), "gj flag read");
+  hip_check(hipStreamSynchronize(s), "gj sync");
+  if (bad) throw BiotError{BIOT_ERR_ARG, "singular coarse matrix"};
 }
 
 // power iteration for lambda_max(Dinv S) per segment; apply(x, y) computes y = Dinv S x
@@ -749,11 +765,11 @@ static void setup_pressure(biot_problem_s* h, hipStream_t s) {
           }
           A[q * nc + q] += dg;
         }
-        invert_dense(A, (int)nc);
         std::copy(A.begin(), A.end(), all.begin() + P->pd[k].moff + j * P->pd[k].mjstride);
       }
     }
     upload(all, P->pAinv, s);
+    invert_on_device(P, P->d_gjp, (int)P->gjp.size(), P->p_maxn, P->pAinv, s);
   }
   // FP32 copies
   auto& F = P->b32;
@@ -820,10 +836,11 @@ static void setup_elasticity(biot_problem_s* h, hipStream_t s) {
   // coarse dense inverses
   std::vector<double> all(P->uAinv_len);
   for (int k = 0; k < cnt; ++k) {
-    auto A = coarse_elast_inverse(P->ug[P->nul - 1][k]);
+    auto A = coarse_elast_matrix(P->ug[P->nul - 1][k]);
     std::copy(A.begin(), A.end(), all.begin() + P->ud[k].moff);
   }
   upload(all, P->uAinv, s);
+  invert_on_device(P, P->d_gju, (int)P->gju.size(), P->u_maxn, P->uAinv, s);
   long long dt = 0;
   for (int l = 0; l < P->nul; ++l) dt += P->u_total[l];
   cast_to_f32(B.u_dinv[0], P->b32.u_dinv[0], dt, s);
@@ -848,6 +865,8 @@ void setup_solver(biot_problem_s* h, hipStream_t s) {
   upload(P->utab_h, P->d_utab, s);
   upload(P->ud, P->d_ud, s);
   upload(P->pd, P->d_pd, s);
+  upload(P->gju, P->d_gju, s);
+  upload(P->gjp, P->d_gjp, s);
   upload(P->gseg, P->d_gseg, s);
   for (int j = 0; j < 16; ++j) { P->Q.m[j] = h->tc.Q[j]; P->Qi.m[j] = h->tc.Qi[j]; }
   // initial guess of the next slab: the previous slab's solution extrapolated
@@ -898,7 +917,7 @@ static void p_vcycle(biot_problem_s* h, int l, hipStream_t s) {
   const int nl = h->nl, cnt = h->count;
   static const ChebSeq cs = cheb_seq(kPLo, kPHi, kPDeg);
   if (l == P->npl - 1) {
-    dense_solve<T>(P->d_pd, cnt, nl, P->p_maxn, P->pAinv, B.pc_b[l], B.pc_x[l], s);
+    dense_solve<T>(P->d_pd, cnt, nl, P->p_maxn, false, P->pAinv, B.pc_b[l], B.pc_x[l], s);
     return;
   }
   const PCellSeg* sg = P->d_pc[l];
@@ -955,7 +974,7 @@ static void u_vcycle(biot_problem_s* h, int l, T* x, const T* b, T* r, T* d0, T*
   const int ud = udeg(d);
   const ChebSeq cs = cheb_seq(kULo, kUHi, ud);
   if (l == P->nul - 1) {
-    dense_solve<T>(P->d_ud, cnt, nl, P->u_maxn, P->uAinv, b, x, s);
+    dense_solve<T>(P->d_ud, cnt, nl, P->u_maxn, true, P->uAinv, b, x, s);
     return;
   }
   const LSeg* ls = P->d_ul[l];

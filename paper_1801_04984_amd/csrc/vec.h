@@ -17,6 +17,10 @@ struct DSeg {          // dense coarse solve segment
   int n, pad;
   long long moff, mjstride;
 };
+struct GJMat {         // one dense matrix to invert in place: offset, snapshot offset, order
+  long long moff, soff;
+  int n, pad;
+};
 struct Mat4 { double m[16]; };
 
 constexpr int kMaxChunks = 2048;  // dot-product partial sums per segment (upper bound)
@@ -47,7 +51,15 @@ template <typename T>
 void seg_add(const LSeg* segs, int nseg, int nj, long long maxlen, const T* d, T* x, double a, hipStream_t s);
 template <typename T>
 void seg_zero(const LSeg* segs, int nseg, int nj, long long maxlen, T* x, hipStream_t s);
+// x_j = Ainv_j b_j per segment and level j; shared = every segment's matrix is
+// the same for all levels (mjstride 0): one pass over each row serves all j
 template <typename T>
-void dense_solve(const DSeg* segs, int nseg, int nj, int maxn, const double* Ainv, const T* b, T* x, hipStream_t s);
+void dense_solve(const DSeg* segs, int nseg, int nj, int maxn, bool shared, const double* Ainv, const T* b, T* x,
+                 hipStream_t s);
+// In-place inversion of a batch of dense matrices (symmetric positive definite,
+// or identity rows/columns plus an SPD block) by Gauss-Jordan exchange steps
+// without pivoting; snap holds 4 n doubles per matrix; *bad is set to 1 if a
+// pivot is zero or not finite (the caller clears it first).
+void dense_invert(const GJMat* mats, int nmats, int maxn, double* A, double* snap, int* bad, hipStream_t s);
 
 }  // namespace bt

@@ -308,13 +308,102 @@ __global__ __launch_bounds__(256) void dense_kernel(const DSeg* __restrict__ seg
     if ((threadIdx.x & 63) == 0) x[vo + row] = (T)s;
   }
 }
+// one wave per row, all levels at once (the matrix is read once per row)
+template <typename T, int NJ>
+__global__ __launch_bounds__(256) void dense_shared_kernel(const DSeg* __restrict__ segs,
+                                                           const double* __restrict__ Ainv, const T* __restrict__ b,
+                                                           T* __restrict__ x) {
+  const DSeg sg = segs[blockIdx.y];
+  const double* A = Ainv + sg.moff;
+  const int n = sg.n;
+  const int lane = threadIdx.x & 63;
+  for (int row = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); row < n; row += gridDim.x * (blockDim.x / 64)) {
+    const double* Ar = A + (long long)row * n;
+    double s[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) s[j] = 0.0;
+    for (int c = lane; c < n; c += 64) {
+      const double a = Ar[c];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) s[j] += a * (double)b[sg.off + j * sg.jstride + c];
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      double v = s[j];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+      if (lane == 0) x[sg.off + j * sg.jstride + row] = (T)v;
+    }
+  }
+}
+
 template <typename T>
-void dense_solve(const DSeg* segs, int nseg, int nj, int maxn, const double* Ainv, const T* b, T* x, hipStream_t s) {
-  unsigned gx = (unsigned)((maxn + 3) / 4);
-  if (gx > 64) gx = 64;
+void dense_solve(const DSeg* segs, int nseg, int nj, int maxn, bool shared, const double* Ainv, const T* b, T* x,
+                 hipStream_t s) {
+  unsigned gx = (unsigned)((maxn + 3) / 4);   // one wave per row
+  if (gx > 2048) gx = 2048;
+  if (shared) {
+    switch (nj) {
+      case 1: hipLaunchKernelGGL((dense_shared_kernel<T, 1>), dim3(gx, nseg), dim3(256), 0, s, segs, Ainv, b, x); break;
+      case 2: hipLaunchKernelGGL((dense_shared_kernel<T, 2>), dim3(gx, nseg), dim3(256), 0, s, segs, Ainv, b, x); break;
+      case 3: hipLaunchKernelGGL((dense_shared_kernel<T, 3>), dim3(gx, nseg), dim3(256), 0, s, segs, Ainv, b, x); break;
+      default: hipLaunchKernelGGL((dense_shared_kernel<T, 4>), dim3(gx, nseg), dim3(256), 0, s, segs, Ainv, b, x); break;
+    }
+    return;
+  }
   hipLaunchKernelGGL((dense_kernel<T>), dim3(gx, nseg, nj), dim3(256), maxn * sizeof(double), s, segs, Ainv, b, x);
 }
-template void dense_solve<double>(const DSeg*, int, int, int, const double*, const double*, double*, hipStream_t);
-template void dense_solve<float>(const DSeg*, int, int, int, const double*, const float*, float*, hipStream_t);
+template void dense_solve<double>(const DSeg*, int, int, int, bool, const double*, const double*, double*, hipStream_t);
+template void dense_solve<float>(const DSeg*, int, int, int, bool, const double*, const float*, float*, hipStream_t);
+
+// Gauss-Jordan exchange step k on every matrix of the batch.  With p = a_kk:
+//   a_kk <- 1/p,  a_kj <- -a_kj/p,  a_ik <- a_ik/p,  a_ij <- a_ij - a_ik a_kj/p,
+// which exchanges unknown k with equation k; after all n steps the array holds
+// the inverse.  Row and column k are read from a snapshot taken by the previous
+// step (parity k & 1), so every element is read and written by its own thread
+// only; the threads of row/column k+1 store the snapshot for the next step.
+__global__ __launch_bounds__(256) void gj_init_kernel(const GJMat* __restrict__ mats, const double* __restrict__ A,
+                                                      double* __restrict__ snap) {
+  const GJMat m = mats[blockIdx.y];
+  const double* a = A + m.moff;
+  double* S = snap + m.soff;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < m.n; t += gridDim.x * blockDim.x) {
+    S[t] = a[t];                              // row 0
+    S[m.n + t] = a[(long long)t * m.n];       // column 0
+  }
+}
+
+__global__ __launch_bounds__(256) void gj_step_kernel(const GJMat* __restrict__ mats, int k, double* __restrict__ A,
+                                                      double* __restrict__ snap, int* __restrict__ bad) {
+  const GJMat m = mats[blockIdx.z];
+  const int n = m.n;
+  const int i = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n || i >= n || j >= n) return;
+  const double* Rs = snap + m.soff + (k & 1) * 2 * (long long)n;
+  const double* Cs = Rs + n;
+  double* Rn = snap + m.soff + ((k & 1) ^ 1) * 2 * (long long)n;
+  double* Cn = Rn + n;
+  const double p = Cs[k];
+  const double ip = 1.0 / p;
+  double* a = A + m.moff + (long long)i * n + j;
+  double v;
+  if (i == k) v = (j == k) ? ip : -Rs[j] * ip;
+  else if (j == k) v = Cs[i] * ip;
+  else v = *a - Cs[i] * Rs[j] * ip;
+  *a = v;
+  if (k + 1 < n) {
+    if (i == k + 1) Rn[j] = v;
+    if (j == k + 1) Cn[i] = v;
+  }
+  if (i == k && j == k && !(p != 0.0 && isfinite(p))) *bad = 1;
+}
+
+void dense_invert(const GJMat* mats, int nmats, int maxn, double* A, double* snap, int* bad, hipStream_t s) {
+  if (nmats <= 0 || maxn <= 0) return;
+  const unsigned gx = (unsigned)((maxn + 255) / 256);
+  hipLaunchKernelGGL(gj_init_kernel, dim3(gx, nmats), dim3(256), 0, s, mats, (const double*)A, snap);
+  for (int k = 0; k < maxn; ++k)
+    hipLaunchKernelGGL(gj_step_kernel, dim3(gx, maxn, nmats), dim3(256), 0, s, mats, k, A, snap, bad);
+}
 
 }  // namespace bt
