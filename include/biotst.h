@@ -104,8 +104,9 @@ typedef struct {
   int32_t max_refine;   /* mixed: outer refinement sweeps                   [30]   */
   int32_t cheb_degree;  /* flux-mass block: 0 = exact line solves, k = 1..64 [-1]
                            Chebyshev-Jacobi of degree k, -1 = line solves
-                           when instances x levels x flux lines >= 16384,
-                           else degree 8                                  */
+                           when every line has <= 511 cells (one wavefront
+                           per line) or instances x levels x flux lines
+                           >= 16384 (one thread per line), else degree 8  */
   int32_t graph;        /* 1: replay the preconditioner as a captured      [1]
                            hipGraph (captured on first use); 0: eager     */
 } biot_solve_opts;

@@ -116,10 +116,14 @@ template <typename T>
 void launch_uapply(int dim, const UGridSeg* segs, const int4* work, int nwork, int nj, int mode, const T* x,
                    const T* b, T* y, const T* emat, hipStream_t s);
 int uapply_tile(int dim);
-// exact line solve of tau Mq x = b (q blocks of every level; w: q-sized scratch)
+// exact line solve of tau Mq x = b (q blocks of every level; w: q-sized scratch).
+// maxcells_line = the largest cell count along any axis of any instance: lines
+// of up to kPcrMaxCells cells are solved by one wavefront each (parallel cyclic
+// reduction), longer lines by one thread each (Thomas sweep).
+constexpr int kPcrMaxCells = 511;
 template <typename T>
-void launch_mq_lines(int dim, const InstDev* insts, int count, int nj, long long maxlines, const T* kinv, const T* b,
-                     T* x, T* w, hipStream_t s);
+void launch_mq_lines(int dim, const InstDev* insts, int count, int nj, long long maxlines, int maxcells_line,
+                     const T* kinv, const T* b, T* x, T* w, hipStream_t s);
 template <typename T>
 void launch_uapply3d(const UGridSeg* segs, const int4* work, int nwork, int nj, int mode, const T* x, const T* b,
                      T* y, const T* emat, hipStream_t s);

@@ -200,18 +200,151 @@ __global__ __launch_bounds__(256) void mq_line_kernel(const InstDev* __restrict_
     }
   }
 }
+// The same condensed tridiagonal system, one wavefront per line: lane l holds
+// the cell-end equations i = l, l + 64, ... (K per lane), and parallel cyclic
+// reduction eliminates the couplings at distance 1, 2, 4, ... until every
+// equation stands alone.  With a_i, b_i, c_i the couplings to i-s, i, i+s:
+//   al = -a_i / b_{i-s},  ga = -c_i / b_{i+s},
+//   a_i <- al a_{i-s},  c_i <- ga c_{i+s},
+//   b_i <- b_i + al c_{i-s} + ga a_{i+s},  d_i <- d_i + al d_{i-s} + ga d_{i+s}
+// (out-of-range neighbours are identity rows).  The condensed matrix is
+// strictly diagonally dominant (|S00| = 3 |S02| per cell), so no pivoting is
+// needed.  Equations beyond the line's end and essential nodes are identity rows.
+template <typename T, int DIM, int K>
+__global__ __launch_bounds__(64) void mq_pcr_kernel(const InstDev* __restrict__ insts, const T* __restrict__ kinv,
+                                                    const T* __restrict__ b, T* __restrict__ x) {
+  constexpr int M = 64 * K;
+  constexpr double kS00 = MC(0, 0) - MC(0, 1) * MC(1, 0) / MC(1, 1);
+  constexpr double kS02 = MC(0, 2) - MC(0, 1) * MC(1, 2) / MC(1, 1);
+  constexpr double kR = MC(0, 1) / MC(1, 1);
+  __shared__ T sa[M], sb[M], sc[M], sd[M];
+  const InstDev& I = insts[blockIdx.y];
+  int nlines[3] = {0, 0, 0};
+#pragma unroll
+  for (int e = 0; e < DIM; ++e) {
+    int c = 1;
+#pragma unroll
+    for (int f = 0; f < DIM; ++f)
+      if (f != e) c *= I.sp[f];
+    nlines[e] = c;
+  }
+  const int t = blockIdx.x;
+  if (t >= nlines[0] + nlines[1] + nlines[2]) return;   // whole block
+  const long long lo = I.x_off + blockIdx.z * I.N;
+  const T* kc = kinv + I.cell_off;
+  const int e = t < nlines[0] ? 0 : (t < nlines[0] + nlines[1] ? 1 : 2);
+  const int ln = t - (e == 0 ? 0 : (e == 1 ? nlines[0] : nlines[0] + nlines[1]));
+  const int fa = e == 0 ? 1 : 0, fb = e == 2 ? 1 : 2;
+  const int sa_ = I.sp[fa];
+  const int oa = ln % sa_, ob = DIM == 3 ? ln / sa_ : 0;
+  const int qs0 = I.sq[e][0], qs1 = I.sq[e][1];
+  const int qstr[3] = {1, qs0, qs0 * qs1};
+  const int cstr[3] = {1, I.n[0], I.n[0] * I.n[1]};
+  const int base = oa * qstr[fa] + (DIM == 3 ? ob * qstr[fb] : 0);
+  const int cbase = (oa >> 1) * cstr[fa] + (DIM == 3 ? (ob >> 1) * cstr[fb] : 0);
+  const int qs = qstr[e], cs = cstr[e];
+  const int n = I.n[e];
+  double hp = 1.0;
+#pragma unroll
+  for (int f = 0; f < DIM; ++f)
+    if (f != e) hp *= 0.5 * I.h[f];
+  const T fsc = T(I.tau * I.h[e] * hp);
+  const T* B = b + lo + I.off_q[e] + base;
+  T* X = x + lo + I.off_q[e] + base;
+  const bool top_free = e == DIM - 1;
+  const int lane = threadIdx.x;
+  T f_own[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = lane + 64 * k;
+    T a = 0, bd = 1, c = 0, d = 0, fi = 0;
+    if (i <= n) {
+      fi = i < n ? kc[cbase + i * cs] * fsc : T(0);
+      const bool fixed = i == 0 || (i == n && !top_free);
+      if (!fixed) {
+        const T fp = kc[cbase + (i - 1) * cs] * fsc;   // i >= 1 here
+        bd = T(kS00) * (fp + fi);
+        a = T(kS02) * fp;
+        c = T(kS02) * fi;
+        d = B[(2 * i) * qs] - T(kR) * B[(2 * i - 1) * qs];
+        if (i < n) d -= T(kR) * B[(2 * i + 1) * qs];
+      }
+    }
+    f_own[k] = fi;
+    sa[i] = a; sb[i] = bd; sc[i] = c; sd[i] = d;
+  }
+  __syncthreads();
+  for (int st = 1; st <= n; st <<= 1) {
+    T na[K], nb[K], nc[K], nd[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = lane + 64 * k;
+      const T ai = sa[i], ci = sc[i];
+      T al = 0, ga = 0, aL = 0, cL = 0, dL = 0, aR = 0, cR = 0, dR = 0;
+      if (i - st >= 0) { al = -ai / sb[i - st]; aL = sa[i - st]; cL = sc[i - st]; dL = sd[i - st]; }
+      if (i + st < M) { ga = -ci / sb[i + st]; aR = sa[i + st]; cR = sc[i + st]; dR = sd[i + st]; }
+      na[k] = al * aL;
+      nc[k] = ga * cR;
+      nb[k] = sb[i] + al * cL + ga * aR;
+      nd[k] = sd[i] + al * dL + ga * dR;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = lane + 64 * k;
+      sa[i] = na[k]; sb[i] = nb[k]; sc[i] = nc[k]; sd[i] = nd[k];
+    }
+    __syncthreads();
+  }
+  // every equation now stands alone: x_i = d_i / b_i; then the interior nodes
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = lane + 64 * k;
+    const T xi = sd[i] / sb[i];
+    sa[i] = xi;
+    if (i <= n) X[(2 * i) * qs] = xi;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = lane + 64 * k;
+    if (i < n)
+      X[(2 * i + 1) * qs] =
+          (B[(2 * i + 1) * qs] / f_own[k] - T(MC(1, 0)) * sa[i] - T(MC(1, 2)) * sa[i + 1]) / T(MC(1, 1));
+  }
+}
+
+template <typename T, int DIM>
+static void launch_pcr(int K, dim3 g, const InstDev* insts, const T* kinv, const T* b, T* x, hipStream_t s) {
+  switch (K) {
+    case 1: hipLaunchKernelGGL((mq_pcr_kernel<T, DIM, 1>), g, dim3(64), 0, s, insts, kinv, b, x); break;
+    case 2: hipLaunchKernelGGL((mq_pcr_kernel<T, DIM, 2>), g, dim3(64), 0, s, insts, kinv, b, x); break;
+    case 4: hipLaunchKernelGGL((mq_pcr_kernel<T, DIM, 4>), g, dim3(64), 0, s, insts, kinv, b, x); break;
+    default: hipLaunchKernelGGL((mq_pcr_kernel<T, DIM, 8>), g, dim3(64), 0, s, insts, kinv, b, x); break;
+  }
+}
+
 template <typename T>
-void launch_mq_lines(int dim, const InstDev* insts, int count, int nj, long long maxlines, const T* kinv, const T* b,
-                     T* x, T* w, hipStream_t s) {
+void launch_mq_lines(int dim, const InstDev* insts, int count, int nj, long long maxlines, int maxcells_line,
+                     const T* kinv, const T* b, T* x, T* w, hipStream_t s) {
+  if (maxcells_line <= kPcrMaxCells) {
+    // equations per line = cells + 1, K per lane (a power of two)
+    int K = 1;
+    while (64 * K < maxcells_line + 1) K *= 2;
+    const dim3 g((unsigned)maxlines, (unsigned)count, (unsigned)nj);
+    if (dim == 2) launch_pcr<T, 2>(K, g, insts, kinv, b, x, s);
+    else launch_pcr<T, 3>(K, g, insts, kinv, b, x, s);
+    return;
+  }
   if (dim == 2)
     hipLaunchKernelGGL((mq_line_kernel<T, 2>), grid3(maxlines, count, nj), dim3(kBlk), 0, s, insts, kinv, b, x, w);
   else
     hipLaunchKernelGGL((mq_line_kernel<T, 3>), grid3(maxlines, count, nj), dim3(kBlk), 0, s, insts, kinv, b, x, w);
 }
-template void launch_mq_lines<double>(int, const InstDev*, int, int, long long, const double*, const double*, double*,
-                                      double*, hipStream_t);
-template void launch_mq_lines<float>(int, const InstDev*, int, int, long long, const float*, const float*, float*,
-                                     float*, hipStream_t);
+template void launch_mq_lines<double>(int, const InstDev*, int, int, long long, int, const double*, const double*,
+                                      double*, double*, hipStream_t);
+template void launch_mq_lines<float>(int, const InstDev*, int, int, long long, int, const float*, const float*,
+                                     float*, float*, hipStream_t);
 
 // ---- finalize -----------------------------------------------------------------------------------
 template <typename T, int NL>

@@ -131,6 +131,7 @@ struct PrecData {
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int gdeg[2] = {0, 0};
   long long maxN = 0, maxcells = 0, maxlines = 0;
+  int maxcells_line = 0;   // most cells along any axis of any instance
 };
 
 template <typename T>
@@ -178,7 +179,7 @@ static void interp_table(int nf, int nc, std::vector<double>& prol, std::vector<
 static void build_hierarchy(biot_problem_s* h, PrecData* P) {
   const int d = h->dim, nl = h->nl, cnt = h->count;
   P->nl = nl; P->dim = d; P->count = cnt;
-  P->maxN = 0; P->maxcells = 0; P->maxlines = 0;
+  P->maxN = 0; P->maxcells = 0; P->maxlines = 0; P->maxcells_line = 0;
   for (auto& I : h->inst) {
     P->maxN = std::max(P->maxN, I.N);
     P->maxcells = std::max(P->maxcells, I.ncells);
@@ -190,6 +191,7 @@ static void build_hierarchy(biot_problem_s* h, PrecData* P) {
       lines += c;
     }
     P->maxlines = std::max(P->maxlines, lines);
+    for (int e = 0; e < d; ++e) P->maxcells_line = std::max(P->maxcells_line, I.n[e]);
   }
   // ---- pressure: DG level segments
   P->pdg.clear();
@@ -1020,7 +1022,7 @@ static void apply_prec(biot_problem_s* h, const T* rin, T* z, int qdeg, hipStrea
   launch_coupling<T>(d, h->d_inst, cnt, nl, P->maxN, B.Wr, B.Wz, B.Wf, B.Wf, s);
   // 3) flux: tau Mq q = f_q  (exact line solves, or Chebyshev-Jacobi of degree qdeg on the Gershgorin interval)
   if (qdeg == 0) {
-    launch_mq_lines<T>(d, h->d_inst, cnt, nl, P->maxlines, B.kinv, B.Wf, B.Wz, B.T1, s);
+    launch_mq_lines<T>(d, h->d_inst, cnt, nl, P->maxlines, P->maxcells_line, B.kinv, B.Wf, B.Wz, B.T1, s);
   } else {
     const ChebSeq cs = cheb_seq(kQLo, kQHi, qdeg);
     launch_mq<T>(d, h->d_inst, cnt, nl, P->maxN, kResInitZero, ChebCoef{cs.s0, 0, 0, 1}, B.kinv, nullptr, B.Wf, B.Wz,
@@ -1268,10 +1270,12 @@ static void solve_impl(biot_problem_s* h, const double* b, double* x, int transp
     throw BiotError{BIOT_ERR_ARG, "unknown precision"};
   if (opts.cheb_degree < -1 || opts.cheb_degree > 64) throw BiotError{BIOT_ERR_ARG, "cheb_degree must be in -1..64"};
   if (opts.cheb_degree == -1) {
-    // exact line solves need one thread per flux line: use them when the lines of
-    // all instances and time levels fill the device, Chebyshev-Jacobi otherwise
+    // exact line solves: one wavefront per line up to kPcrMaxCells cells per line;
+    // longer lines take one thread each, which pays only when the lines of all
+    // instances and time levels fill the device (Chebyshev-Jacobi otherwise)
     const long long lines = (long long)h->count * h->nl * h->prec->maxlines;
-    opts.cheb_degree = lines >= kLineSolveMinLines ? 0 : kQDegDefault;
+    const bool wave_lines = h->prec->maxcells_line <= kPcrMaxCells;
+    opts.cheb_degree = (wave_lines || lines >= kLineSolveMinLines) ? 0 : kQDegDefault;
   }
   const int cnt = h->count;
   std::vector<int> its, rst, st;

@@ -224,13 +224,17 @@ def test_solve3d_fp64_and_mixed(n, r):
     h.close()
 
 
-@pytest.mark.parametrize("d,n", [(2, (20, 13)), (3, (5, 4, 6))])
-def test_flux_block_variants(d, n):
+# lines of 20 and 130 cells: one wavefront per line (1 and 4 equations per
+# lane); 520 cells: one thread per line (Thomas sweep).  The strips keep
+# square cells (length 0.01 per cell).
+@pytest.mark.parametrize("d,n,length", [(2, (20, 13), (1.0, 1.0)), (2, (130, 3), (1.3, 0.03)),
+                                        (2, (520, 2), (5.2, 0.02)), (3, (5, 4, 6), (1.0, 1.0, 1.0))])
+def test_flux_block_variants(d, n, length):
     """The flux-mass block of the preconditioner solved exactly line by line
     (default) or by Chebyshev-Jacobi: both preconditioned solves reach the
     oracle's solution; the exact block needs no more iterations."""
     torch = torch_cuda()
-    wl = small_workload(d, n, 1, seed=90 + d)
+    wl = small_workload(d, n, 1, seed=90 + d, length=tuple(length) + (1.0,) * (3 - d))
     h, (prob,) = make_pair([wl])
     b = _rhs(prob, seed=4)
     ref = prob.solve(b)
