@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <random>
 #include <string>
 #include <type_traits>
@@ -130,6 +131,10 @@ struct PrecData {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int gdeg[2] = {0, 0};
+  // captured Arnoldi steps (preconditioner, operator, CGS2, normalisation), one
+  // per Krylov index and variant; their dot products land in pinned host memory
+  std::map<long long, hipGraphExec_t> arnoldi;
+  double* hdots = nullptr;   // 3 x count x 64: V^T w (two passes) and ||w||^2
   long long maxN = 0, maxcells = 0, maxlines = 0;
   int maxcells_line = 0;   // most cells along any axis of any instance
 };
@@ -850,6 +855,9 @@ static void setup_elasticity(biot_problem_s* h, hipStream_t s) {
 
 void setup_solver(biot_problem_s* h, hipStream_t s) {
   PrecData* P = h->prec;
+  if (!P->hdots)
+    hip_check(hipHostMalloc((void**)&P->hdots, sizeof(double) * 3 * 64 * h->count, hipHostMallocDefault),
+              "pinned dot buffer");
   // descriptors
   upload(P->pdg, P->d_pdg, s);
   for (int l = 0; l < P->npl; ++l) upload(P->pc[l], P->d_pc[l], s);
@@ -903,7 +911,9 @@ void destroy_solver(biot_problem_s* h) {
   if (P) {
     for (int q = 0; q < 2; ++q)
       if (P->gexec[q]) (void)hipGraphExecDestroy(P->gexec[q]);
+    for (auto& kv : P->arnoldi) (void)hipGraphExecDestroy(kv.second);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+    if (P->hdots) (void)hipHostFree(P->hdots);
   }
   delete h->prec;
   h->prec = nullptr;
@@ -1095,6 +1105,79 @@ static void seg_norms(PrecData* P, const T* v, int cnt, hipStream_t s, std::vect
   for (int k = 0; k < cnt; ++k) out[k] = std::sqrt(std::max(tmp[k * 64], 0.0));
 }
 
+// One Arnoldi step at Krylov index jj: w = A P^-1 v_jj, two classical
+// Gram-Schmidt passes against v_0..v_jj, v_{jj+1} = w / ||w||.  The three dot
+// product sets are also written to P->hdots for the host's Givens update.
+template <typename T>
+static void arnoldi_step(biot_problem_s* h, int jj, int transpose, const SolveCtl& ctl, hipStream_t s) {
+  PrecData* P = h->prec;
+  auto& B = bufs<T>(P);
+  const int cnt = h->count;
+  const long long S = h->slab_len;
+  T* vj = B.V + (long long)jj * S;
+  T* vn = B.V + (long long)(jj + 1) * S;
+  bool done_prec = false;
+  if constexpr (std::is_same<T, double>::value) {
+    if (ctl.flex32) {
+      // z_j = P32(v_j), kept in FP32 (the FP32 Krylov basis is unused in this mode);
+      // the Arnoldi relation uses exactly these values, so x += Z y stays consistent
+      auto& F = P->b32;
+      float* zj = F.V + (long long)jj * S;
+      vcast(vj, F.w, S, s);
+      apply_prec<float>(h, F.w, F.t, ctl.qdeg, s);
+      vcopy<float>(F.t, zj, S, s);
+      vcast(zj, B.t, S, s);
+      done_prec = true;
+    }
+  }
+  if (!done_prec) apply_prec<T>(h, vj, B.t, ctl.qdeg, s);
+  launch_apply(h, B.t, vn, transpose, std::is_same<T, float>::value ? 1 : 0, s);
+  const int nch = dot_chunks(P->gmax);
+  double* hd = P->hdots;
+  seg_mdot<T, T>(B.V, S, jj + 1, vn, P->d_gseg, cnt, nch, P->partial, P->dot1, s, hd);
+  seg_maxpy<T, T>(B.V, S, jj + 1, P->dot1, -1.0, vn, P->d_gseg, cnt, P->gmax, s);
+  seg_mdot<T, T>(B.V, S, jj + 1, vn, P->d_gseg, cnt, nch, P->partial, P->dot2, s, hd + 64 * cnt);
+  seg_maxpy<T, T>(B.V, S, jj + 1, P->dot2, -1.0, vn, P->d_gseg, cnt, P->gmax, s);
+  seg_mdot<T, T>(vn, 0, 1, vn, P->d_gseg, cnt, nch, P->partial, P->dot3, s, hd + 128 * cnt);
+  seg_scale<T, T>(vn, vn, P->dot3, 0, 2, P->d_gseg, cnt, P->gmax, s);   // 0 for a zero norm
+}
+
+// the Arnoldi step through a graph captured once per (index, variant), replayed on s
+template <typename T>
+static void arnoldi_step_graph(biot_problem_s* h, int jj, int transpose, const SolveCtl& ctl, hipStream_t s) {
+  PrecData* P = h->prec;
+  if (!ctl.graph) {
+    arnoldi_step<T>(h, jj, transpose, ctl, s);
+    return;
+  }
+  const long long key =
+      ((((long long)jj * 2 + (transpose ? 1 : 0)) * 2 + (ctl.flex32 ? 1 : 0)) * 2 +
+       (std::is_same<T, float>::value ? 1 : 0)) * 128 + ctl.qdeg;
+  auto it = P->arnoldi.find(key);
+  if (it == P->arnoldi.end()) {
+    if (!P->cap_stream) hip_check(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking), "capture stream");
+    hip_check(hipStreamSynchronize(s), "pre-capture sync");
+    hipGraph_t g;
+    hip_check(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeRelaxed), "begin capture");
+    arnoldi_step<T>(h, jj, transpose, ctl, P->cap_stream);
+    hip_check(hipStreamEndCapture(P->cap_stream, &g), "end capture");
+    hipGraphExec_t ge;
+    hip_check(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0), "graph instantiate");
+    hip_check(hipGraphDestroy(g), "graph destroy");
+    it = P->arnoldi.emplace(key, ge).first;
+  }
+  hip_check(hipGraphLaunch(it->second, s), "graph launch");
+}
+
+// wait for the stream by polling (the host has nothing else to do, and the
+// Arnoldi loop waits once per iteration)
+static void spin_wait(hipStream_t s) {
+  hipError_t e;
+  while ((e = hipStreamQuery(s)) == hipErrorNotReady) {
+  }
+  hip_check(e, "stream wait");
+}
+
 template <typename T>
 static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const SolveCtl& ctl, std::vector<int>& its,
                   std::vector<int>& rst, std::vector<double>& relres, std::vector<int>& status, hipStream_t s) {
@@ -1117,7 +1200,7 @@ static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const Solv
   }
   std::vector<double> H((size_t)cnt * (kMaxRestart + 1) * kMaxRestart), cs(cnt * kMaxRestart), sn(cnt * kMaxRestart),
       g(cnt * (kMaxRestart + 1));
-  std::vector<double> h1(cnt * 64), h2(cnt * 64), hn(cnt * 64), coef(cnt * 64);
+  std::vector<double> coef(cnt * 64);
   std::vector<int> stall(cnt, 0);
   int total = 0;
   while (true) {
@@ -1135,36 +1218,11 @@ static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const Solv
     }
     int jj = 0;
     for (; jj < m && total < ctl.maxit; ++jj) {
-      T* vj = B.V + (long long)jj * S;
-      T* vn = B.V + (long long)(jj + 1) * S;
-      if constexpr (std::is_same<T, double>::value) {
-        if (ctl.flex32) {
-          // z_j = P32(v_j), kept in FP32 (the FP32 Krylov basis is unused in this mode);
-          // the Arnoldi relation uses exactly these values, so x += Z y stays consistent
-          auto& F = P->b32;
-          float* zj = F.V + (long long)jj * S;
-          vcast(vj, F.w, S, s);
-          apply_prec_graph<float>(h, F.w, F.t, ctl.qdeg, ctl.graph, s);
-          hip_check(hipMemcpyAsync(zj, F.t, sizeof(float) * S, hipMemcpyDeviceToDevice, s), "flexible basis");
-          vcast(zj, B.t, S, s);
-        } else {
-          apply_prec_graph<T>(h, vj, B.t, ctl.qdeg, ctl.graph, s);
-        }
-      } else {
-        apply_prec_graph<T>(h, vj, B.t, ctl.qdeg, ctl.graph, s);
-      }
-      launch_apply(h, B.t, vn, transpose, std::is_same<T, float>::value ? 1 : 0, s);
-      seg_mdot<T, T>(B.V, S, jj + 1, vn, P->d_gseg, cnt, dot_chunks(P->gmax), P->partial, P->dot1, s);
-      seg_maxpy<T, T>(B.V, S, jj + 1, P->dot1, -1.0, vn, P->d_gseg, cnt, P->gmax, s);
-      seg_mdot<T, T>(B.V, S, jj + 1, vn, P->d_gseg, cnt, dot_chunks(P->gmax), P->partial, P->dot2, s);
-      seg_maxpy<T, T>(B.V, S, jj + 1, P->dot2, -1.0, vn, P->d_gseg, cnt, P->gmax, s);
-      seg_mdot<T, T>(vn, 0, 1, vn, P->d_gseg, cnt, dot_chunks(P->gmax), P->partial, P->dot3, s);
-      hip_check(hipMemcpyAsync(h1.data(), P->dot1, 8 * cnt * 64, hipMemcpyDeviceToHost, s), "h read");
-      hip_check(hipMemcpyAsync(h2.data(), P->dot2, 8 * cnt * 64, hipMemcpyDeviceToHost, s), "h read");
-      hip_check(hipMemcpyAsync(hn.data(), P->dot3, 8 * cnt * 64, hipMemcpyDeviceToHost, s), "h read");
-      hip_check(hipStreamSynchronize(s), "gmres sync");
-      // v_{j+1} = w / ||w|| on the device (0 for a zero norm)
-      seg_scale<T, T>(vn, vn, P->dot3, 0, 2, P->d_gseg, cnt, P->gmax, s);
+      arnoldi_step_graph<T>(h, jj, transpose, ctl, s);
+      spin_wait(s);
+      const double* h1 = P->hdots;
+      const double* h2 = P->hdots + 64 * cnt;
+      const double* hn = P->hdots + 128 * cnt;
       for (int k = 0; k < cnt; ++k) {
         const double nrm = std::sqrt(std::max(hn[k * 64], 0.0));
         if (!std::isfinite(nrm)) throw BiotError{BIOT_ERR_NONFINITE, "non-finite Krylov vector"};
@@ -1411,11 +1469,20 @@ biot_status biot_get_tuning(biot_problem h, biot_tuning* out) {
   BIOT_CATCH
 }
 
+// captured Arnoldi steps hold the operator kernel of the tile variant in use
+// when they were captured: drop them when the selection changes (every solve
+// has completed by then: the solver waits on its stream before returning)
+static void drop_arnoldi_graphs(PrecData* P) {
+  for (auto& kv : P->arnoldi) (void)hipGraphExecDestroy(kv.second);
+  P->arnoldi.clear();
+}
+
 biot_status biot_set_tuning(biot_problem h, const biot_tuning* t) {
   BIOT_TRY
   need(h && t, "handle and tuning must be non-null");
   for (int q = 0; q < 2; ++q)
     need(t->apply_variant[q] >= 0 && t->apply_variant[q] < h->nvariants, "apply_variant out of range");
+  if (h->variant[0] != t->apply_variant[0] || h->variant[1] != t->apply_variant[1]) drop_arnoldi_graphs(h->prec);
   h->variant[0] = t->apply_variant[0];
   h->variant[1] = t->apply_variant[1];
   BIOT_CATCH
@@ -1459,6 +1526,7 @@ biot_status biot_autotune(biot_problem h, int32_t reps, biot_tuning* out, void* 
   }
   hip_check(hipEventDestroy(e0), "event");
   hip_check(hipEventDestroy(e1), "event");
+  if (h->variant[0] != saved[0] || h->variant[1] != saved[1]) drop_arnoldi_graphs(P);
   if (out) *out = res;
   BIOT_CATCH
 }

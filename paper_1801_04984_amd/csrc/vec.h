@@ -32,9 +32,12 @@ void vcast(const float* x, double* y, long long n, hipStream_t s);
 template <typename T>
 void vaxpby(double a, const T* x, double b, T* y, long long n, hipStream_t s);
 void vacc(const float* x, double* y, long long n, hipStream_t s);
+// out[seg * 64 + k] = V_k[seg] . w[seg]; hout (optional): the same values also
+// written to host-mapped pinned memory
 template <typename TV, typename TW>
 void seg_mdot(const TV* V, long long ldv, int nk, const TW* w, const VSeg* segs, int nseg, int nchunk,
-              double* partial, double* out, hipStream_t s);
+              double* partial, double* out, hipStream_t s, double* hout = nullptr);
+template <typename T> void vcopy(const T* x, T* y, long long n, hipStream_t s);
 template <typename TV, typename TW>
 void seg_maxpy(const TV* V, long long ldv, int nk, const double* c, double csign, TW* w, const VSeg* segs, int nseg,
                long long maxlen, hipStream_t s);

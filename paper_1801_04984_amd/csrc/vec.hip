@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kDotThreads) void mdot_stage1(const TV* __restrict_
 }
 // stage 2: one block per (vector k, segment); fixed-order tree over the chunk partials
 __global__ __launch_bounds__(256) void mdot_stage2(const double* __restrict__ partial, int nchunk,
-                                                   double* __restrict__ out) {
+                                                   double* __restrict__ out, double* __restrict__ hout) {
   const int k = blockIdx.x, s = blockIdx.y;
   const double* p = partial + ((long long)s * 64 + k) * nchunk;
   double v = 0.0;
@@ -103,7 +103,11 @@ __global__ __launch_bounds__(256) void mdot_stage2(const double* __restrict__ pa
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  if (threadIdx.x == 0) out[s * 64 + k] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) {
+    const double r = (red[0] + red[1]) + (red[2] + red[3]);
+    out[s * 64 + k] = r;
+    if (hout) hout[s * 64 + k] = r;   // host-mapped copy (read after the stream completes)
+  }
 }
 
 int dot_chunks(long long maxlen) {
@@ -113,18 +117,33 @@ int dot_chunks(long long maxlen) {
 
 template <typename TV, typename TW>
 void seg_mdot(const TV* V, long long ldv, int nk, const TW* w, const VSeg* segs, int nseg, int nchunk,
-              double* partial, double* out, hipStream_t s) {
+              double* partial, double* out, hipStream_t s, double* hout) {
   for (int k0 = 0; k0 < nk; k0 += kKB) {
     int kk = nk - k0 < kKB ? nk - k0 : kKB;
     hipLaunchKernelGGL((mdot_stage1<TV, TW>), dim3(nchunk, nseg), dim3(kDotThreads), 0, s, V, ldv, k0, kk, w, segs,
                        nchunk, partial);
   }
-  hipLaunchKernelGGL(mdot_stage2, dim3(nk, nseg), dim3(256), 0, s, partial, nchunk, out);
+  hipLaunchKernelGGL(mdot_stage2, dim3(nk, nseg), dim3(256), 0, s, partial, nchunk, out, hout);
 }
 template void seg_mdot<double, double>(const double*, long long, int, const double*, const VSeg*, int, int, double*,
-                                       double*, hipStream_t);
+                                       double*, hipStream_t, double*);
 template void seg_mdot<float, float>(const float*, long long, int, const float*, const VSeg*, int, int, double*,
-                                     double*, hipStream_t);
+                                     double*, hipStream_t, double*);
+
+// ---- plain copy (a kernel, so that it can sit in a captured graph) ----------------
+template <typename T>
+__global__ __launch_bounds__(256) void vcopy_kernel(const T* __restrict__ x, T* __restrict__ y, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = x[i];
+}
+template <typename T>
+void vcopy(const T* x, T* y, long long n, hipStream_t s) {
+  long long b = (n + 255) / 256;
+  unsigned gx = (unsigned)(b > 4096 ? 4096 : (b < 1 ? 1 : b));
+  hipLaunchKernelGGL((vcopy_kernel<T>), dim3(gx), dim3(256), 0, s, x, y, n);
+}
+template void vcopy<double>(const double*, double*, long long, hipStream_t);
+template void vcopy<float>(const float*, float*, long long, hipStream_t);
 
 // ---- segmented multi-axpy: w[seg] += sum_k c[seg][k] V_k[seg] -----------------
 template <typename TV, typename TW>

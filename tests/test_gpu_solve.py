@@ -278,19 +278,29 @@ def test_step3d_and_adjoint():
     h.close()
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_graph_replay_matches_eager(precision):
-    """The captured preconditioner graph, replayed many times with eager work and
-    host synchronisations in between, gives bit-identical solves."""
+@pytest.mark.parametrize("transpose", [False, True])
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_graph_replay_matches_eager(precision, transpose):
+    """The captured graphs (the preconditioner, and every Arnoldi step:
+    preconditioner, operator, Gram-Schmidt, normalisation), replayed many
+    times with eager work and host synchronisations in between, give
+    bit-identical solves; so do graphs captured again after the operator's
+    tile variant changes."""
     torch = torch_cuda()
     wls = [small_workload(2, n, 1, seed=90 + i) for i, n in enumerate([(17, 12), (9, 9)])]
     h, probs = make_pair(wls)
     b = torch.tensor(np.concatenate([_rhs(p, seed=i) for i, p in enumerate(probs)]), device="cuda")
-    xe, ie, se = h.solve(b, precision=precision, graph=0)
+    xe, ie, se = h.solve(b, precision=precision, graph=0, transpose=transpose)
     for rep in range(3):
-        xg, ig, sg = h.solve(b, precision=precision, graph=1)
+        xg, ig, sg = h.solve(b, precision=precision, graph=1, transpose=transpose)
         torch.cuda.synchronize()
         assert se == 0 and sg == 0
         assert torch.equal(xg, xe), rep
         assert [i["iterations"] for i in ig] == [i["iterations"] for i in ie]
+        _ = (b * 2.0).sum().item()      # eager work and a host synchronisation between replays
+    tun = h.get_tuning()
+    v = tun["apply_variant"]
+    h.set_tuning([(v[0] + 1) % tun["n_variants"], (v[1] + 1) % tun["n_variants"]])
+    xg, ig, sg = h.solve(b, precision=precision, graph=1, transpose=transpose)
+    assert sg == 0 and torch.equal(xg, xe)
     h.close()
