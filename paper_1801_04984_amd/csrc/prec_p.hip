@@ -126,9 +126,13 @@ __device__ __forceinline__ void pdg_cell(const InstDev& I, const T* __restrict__
           lb += gf * pstr[f];
           qb += (long long)(2 * ce[f] + gf) * qs[f];
         }
+      // neighbour loads at clamped (in-range) indices, masked afterwards: no
+      // load sits behind a branch, so all of them are in flight together
+      const long long lo_b = has_lo ? lb - 2 * pstr[e] : lb, hi_b = has_hi ? lb + 2 * pstr[e] : lb;
       const T x0 = x[lb], x1 = x[lb + pstr[e]];
-      const T xl0 = has_lo ? x[lb - 2 * pstr[e]] : T(0), xl1 = has_lo ? x[lb - pstr[e]] : T(0);
-      const T xh0 = has_hi ? x[lb + 2 * pstr[e]] : T(0), xh1 = has_hi ? x[lb + 3 * pstr[e]] : T(0);
+      const T vl0 = x[lo_b], vl1 = x[lo_b + pstr[e]], vh0 = x[hi_b], vh1 = x[hi_b + pstr[e]];
+      const T xl0 = has_lo ? vl0 : T(0), xl1 = has_lo ? vl1 : T(0);
+      const T xh0 = has_hi ? vh0 : T(0), xh1 = has_hi ? vh1 : T(0);
       const long long qn = qb + (long long)(2 * ce[e]) * qs[e];
       const T d0 = dqi[qn], d1 = dqi[qn + qs[e]], d2 = dqi[qn + 2 * qs[e]];
       const T own2 = T(GB(2, 0)) * x0 + T(GB(2, 1)) * x1, own0 = T(GB(0, 0)) * x0 + T(GB(0, 1)) * x1;
@@ -180,24 +184,33 @@ __global__ __launch_bounds__(256) void pdg_kernel(const InstDev* __restrict__ in
         dout[vo + oo[g]] = T(cc.s0) * dinv[dof + oo[g]] * rr;
       }
     } else if (mode == kResInit) {         // r = bsign b - S x, d = s0 Dinv r
-      T Sx[NG];
+      // every load precedes every store, so the loads are all in flight together
+      T bv[NG], dv[NG], Sx[NG];
+#pragma unroll
+      for (int g = 0; g < NG; ++g) { bv[g] = b[vo + oo[g]]; dv[g] = dinv[dof + oo[g]]; }
       pdg_cell<T, DIM>(I, x + vo, dqi, ce, cm, Sx);
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
-        const T rr = T(cc.bsign) * b[vo + oo[g]] - Sx[g];
+        const T rr = T(cc.bsign) * bv[g] - Sx[g];
         r[vo + oo[g]] = rr;
-        dout[vo + oo[g]] = T(cc.s0) * dinv[dof + oo[g]] * rr;
+        dout[vo + oo[g]] = T(cc.s0) * dv[g] * rr;
       }
     } else if (mode == kStep) {            // x += d; r -= S d; d' = rho d + sig Dinv r
-      T Sd[NG];
+      T dd[NG], xv[NG], rv[NG], dv[NG], Sd[NG];
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        dd[g] = din[vo + oo[g]];
+        xv[g] = x[vo + oo[g]];
+        rv[g] = r[vo + oo[g]];
+        dv[g] = dinv[dof + oo[g]];
+      }
       pdg_cell<T, DIM>(I, din + vo, dqi, ce, cm, Sd);
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
-        const T dd = din[vo + oo[g]];
-        x[vo + oo[g]] += dd;
-        const T rr = r[vo + oo[g]] - Sd[g];
+        x[vo + oo[g]] = xv[g] + dd[g];
+        const T rr = rv[g] - Sd[g];
         r[vo + oo[g]] = rr;
-        dout[vo + oo[g]] = T(cc.rho) * dd + T(cc.sig) * dinv[dof + oo[g]] * rr;
+        dout[vo + oo[g]] = T(cc.rho) * dd[g] + T(cc.sig) * dv[g] * rr;
       }
     } else {                               // y = Dinv S x  (power iteration)
       T Sx[NG];
