@@ -64,6 +64,10 @@ __global__ __launch_bounds__(kT2 * kT2) void apply2d_kernel(const InstDev* __res
   const T cqx = tau * hx * hy * T(0.5) * kc, cbx = tau * hy * T(0.5);
   const T cqy = tau * hx * hy * T(0.5) * kc, cby = tau * hx * T(0.5);
 
+  // Loads use clamped in-range offsets and are masked afterwards, so that no
+  // load waits behind a branch; the raw values of the cell's own nodes also
+  // serve the identity rows of essential nodes.
+  const int ubc = valid ? ub : 0, qybc = valid ? qyb : 0;
   // pressure of every level (p is never constrained)
   T pl[NL][2][2];
 #pragma unroll
@@ -71,7 +75,10 @@ __global__ __launch_bounds__(kT2 * kT2) void apply2d_kernel(const InstDev* __res
 #pragma unroll
     for (int gy = 0; gy < 2; ++gy)
 #pragma unroll
-      for (int gx = 0; gx < 2; ++gx) pl[l][gy][gx] = valid ? Xb[l * N + op + qyb + gx + spx * gy] : T(0);
+      for (int gx = 0; gx < 2; ++gx) {
+        const T v = Xb[l * N + op + qybc + gx + spx * gy];
+        pl[l][gy][gx] = valid ? v : T(0);
+      }
 
   // forward p-rows accumulate over levels: yp_i = tau dq_i + sum_j T_ij zeta_j
   // (register arrays are only indexed with compile-time indices)
@@ -85,7 +92,23 @@ __global__ __launch_bounds__(kT2 * kT2) void apply2d_kernel(const InstDev* __res
   for (int lev = 0; lev < NL; ++lev) {
     const T* Xl = Xb + lev * N;
     T* Yl = Yb + lev * N;
-    // ---- cell data of this level, essential values masked
+    // ---- cell data of this level (raw), then with essential values masked
+    T uxr[3][3], uyr[3][3], qxr[2][3], qyr[3][2];
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int o = ubc + a + sux * b;
+        uxr[b][a] = Xl[ou0 + o];
+        uyr[b][a] = Xl[ou1 + o];
+      }
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        qxr[g][a] = Xl[oq0 + ubc + a + sux * g];
+        qyr[a][g] = Xl[oq1 + qybc + g + spx * a];
+      }
     T ux[3][3], uy[3][3], qx[2][3], qy[3][2];
 #pragma unroll
     for (int b = 0; b < 3; ++b)
@@ -93,9 +116,8 @@ __global__ __launch_bounds__(kT2 * kT2) void apply2d_kernel(const InstDev* __res
       for (int a = 0; a < 3; ++a) {
         const bool bot = b == 0 && j == 0;
         const bool fx = bot || (a == 0 && i == 0) || (a == 2 && lastx);
-        const int o = ub + a + sux * b;
-        ux[b][a] = (valid && !fx) ? Xl[ou0 + o] : T(0);
-        uy[b][a] = (valid && !bot) ? Xl[ou1 + o] : T(0);
+        ux[b][a] = (valid && !fx) ? uxr[b][a] : T(0);
+        uy[b][a] = (valid && !bot) ? uyr[b][a] : T(0);
       }
 #pragma unroll
     for (int g = 0; g < 2; ++g)
@@ -103,8 +125,8 @@ __global__ __launch_bounds__(kT2 * kT2) void apply2d_kernel(const InstDev* __res
       for (int a = 0; a < 3; ++a) {
         const bool fqx = (a == 0 && i == 0) || (a == 2 && lastx);   // no-flow on the x faces
         const bool fqy = a == 0 && j == 0;                           // no-flow at the bottom
-        qx[g][a] = (valid && !fqx) ? Xl[oq0 + ub + a + sux * g] : T(0);
-        qy[a][g] = (valid && !fqy) ? Xl[oq1 + qyb + g + spx * a] : T(0);
+        qx[g][a] = (valid && !fqx) ? qxr[g][a] : T(0);
+        qy[a][g] = (valid && !fqy) ? qyr[a][g] : T(0);
       }
     T pcur[2][2], pc[2][2];
 #pragma unroll
@@ -130,7 +152,9 @@ __global__ __launch_bounds__(kT2 * kT2) void apply2d_kernel(const InstDev* __res
       for (int b = 0; b < 3; ++b)
 #pragma unroll
         for (int a = 0; a < 3; ++a) { uu[b * 3 + a] = ux[b][a]; uu[9 + b * 3 + a] = uy[b][a]; }
-#pragma unroll
+      // one row of the uniform element matrices per iteration (scalar loads;
+      // unrolling all 18 rows would spill the scalar registers)
+#pragma unroll 1
       for (int rr = 0; rr < 18; ++rr) {
         T acc = 0;
 #pragma unroll
@@ -215,7 +239,7 @@ __global__ __launch_bounds__(kT2 * kT2) void apply2d_kernel(const InstDev* __res
             const bool fixed = my == 0 || (c == 0 && (mx == 0 || mx == 2 * nx));
             T v;
             if (fixed) {
-              v = Xl[go];
+              v = c ? uyr[b][a] : uxr[b][a];
             } else {
               v = 0;
 #pragma unroll
@@ -256,7 +280,7 @@ __global__ __launch_bounds__(kT2 * kT2) void apply2d_kernel(const InstDev* __res
             const int go = oq0 + ub + a + sux * g;
             const bool fixed = (a == 0 && i == 0) || (a == 2 && lastx);
             T v;
-            if (fixed) v = Xl[go];
+            if (fixed) v = g ? qxr[1][a] : qxr[0][a];
             else if (a == 0) v = E[g * 3 + 2][tid - 1] + E[g * 3 + 0][tid];
             else v = E[g * 3 + a][tid];
             Yl[go] = v;
@@ -266,7 +290,7 @@ __global__ __launch_bounds__(kT2 * kT2) void apply2d_kernel(const InstDev* __res
             const int go = oq1 + qyb + g + spx * a;
             const bool fixed = a == 0 && j == 0;
             T v;
-            if (fixed) v = Xl[go];
+            if (fixed) v = g ? qyr[a][1] : qyr[a][0];
             else if (a == 0) v = E[6 + 2 * 2 + g][tid - kT2] + E[6 + 0 * 2 + g][tid];
             else v = E[6 + a * 2 + g][tid];
             Yl[go] = v;

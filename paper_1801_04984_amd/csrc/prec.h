@@ -112,10 +112,12 @@ struct UProl {
   long long foff, fjstride, coff, cjstride;
   long long tab[3];            // per axis: per fine node (coarse cell, w0, w1, w2)
 };
+// 2D: variant 0 = 16x16-thread tiles, 1 = 8x8 (owned cells per tile edge:
+// uapply_tile(2, variant)); 3D ignores the variant
 template <typename T>
 void launch_uapply(int dim, const UGridSeg* segs, const int4* work, int nwork, int nj, int mode, const T* x,
-                   const T* b, T* y, const T* emat, hipStream_t s);
-int uapply_tile(int dim);
+                   const T* b, T* y, const T* emat, hipStream_t s, int variant);
+int uapply_tile(int dim, int variant);
 // exact line solve of tau Mq x = b (q blocks of every level; w: q-sized scratch).
 // maxcells_line = the largest cell count along any axis of any instance: lines
 // of up to kPcrMaxCells cells are solved by one wavefront each (parallel cyclic

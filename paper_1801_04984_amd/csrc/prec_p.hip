@@ -262,31 +262,37 @@ void launch_pdg_diag(int dim, const InstDev* insts, const PDgSeg* segs, int nseg
 }
 
 // ---- cell levels ------------------------------------------------------------------------
+// Loads at clamped in-range indices, masked afterwards (a missing neighbour
+// contributes a zero transmissibility), so no load sits behind a branch.
 template <typename T>
 __device__ __forceinline__ void pcell_eval(const PCellSeg& sg, const T* __restrict__ coef, const T* __restrict__ x,
                                            int c, T cm, T& Sx, T& diag) {
   const long long nc = sg.ncells;
-  int ce3[3];
-  unrank((unsigned)c, sg.n, ce3);
-  const int i = ce3[0], jy = ce3[1], k = ce3[2];
+  int ce[3];
+  unrank((unsigned)c, sg.n, ce);
   const T* C = coef + sg.coff;
+  const long long str[3] = {1, (long long)sg.n[0], (long long)sg.n[0] * sg.n[1]};
+  T tl[3], th[3], xl[3], xh[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const bool lo = e < sg.dim && ce[e] > 0, hi = e < sg.dim && ce[e] + 1 < sg.n[e];
+    const long long cl = lo ? c - str[e] : c, ch = hi ? c + str[e] : c;
+    const T* t = C + e * nc;
+    const T a = t[c], bq = t[ch], xa = x[cl], xb = x[ch];
+    tl[e] = lo ? a : T(0);
+    th[e] = hi ? bq : T(0);
+    xl[e] = xa;
+    xh[e] = xb;
+  }
   const T xc = x[c];
   T dg = cm * C[4 * nc + c] + C[3 * nc + c];
   T s = dg * xc;
-  const int ce[3] = {i, jy, k};
-  const long long str[3] = {1, (long long)sg.n[0], (long long)sg.n[0] * sg.n[1]};
-  for (int e = 0; e < sg.dim; ++e) {
-    const T* t = C + e * nc;
-    if (ce[e] > 0) {
-      const T tl = t[c];
-      dg += tl;
-      s += tl * (xc - x[c - str[e]]);
-    }
-    if (ce[e] + 1 < sg.n[e]) {
-      const T th = t[c + str[e]];
-      dg += th;
-      s += th * (xc - x[c + str[e]]);
-    }
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    dg += tl[e];
+    s += tl[e] * (xc - xl[e]);
+    dg += th[e];
+    s += th[e] * (xc - xh[e]);
   }
   Sx = s;
   diag = dg;
@@ -304,23 +310,25 @@ __global__ __launch_bounds__(256) void pcell_kernel(const PCellSeg* __restrict__
   const int ncl = (int)sg.ncells;
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncl; c += gridDim.x * blockDim.x) {
     const T di = dinv[dof + c];
+    // every load of a mode precedes its stores
     if (mode == kResInitZero) {
       const T rr = T(cc.bsign) * b[vo + c];
       x[vo + c] = 0;
       r[vo + c] = rr;
       dout[vo + c] = T(cc.s0) * di * rr;
     } else if (mode == kResInit) {
+      const T bb = b[vo + c];
       T Sx, dg;
       pcell_eval<T>(sg, coef, x + vo, c, cm, Sx, dg);
-      const T rr = T(cc.bsign) * b[vo + c] - Sx;
+      const T rr = T(cc.bsign) * bb - Sx;
       r[vo + c] = rr;
       dout[vo + c] = T(cc.s0) * di * rr;
     } else if (mode == kStep) {
+      const T dd = din[vo + c], xv = x[vo + c], rv = r[vo + c];
       T Sd, dg;
       pcell_eval<T>(sg, coef, din + vo, c, cm, Sd, dg);
-      const T dd = din[vo + c];
-      x[vo + c] += dd;
-      const T rr = r[vo + c] - Sd;
+      x[vo + c] = xv + dd;
+      const T rr = rv - Sd;
       r[vo + c] = rr;
       dout[vo + c] = T(cc.rho) * dd + T(cc.sig) * di * rr;
     } else {

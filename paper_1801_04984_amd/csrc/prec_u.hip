@@ -14,20 +14,23 @@
 
 namespace bt {
 
-constexpr int kUT = 16;
-constexpr int kUO = kUT - 1;
-
-int uapply_tile(int dim) { return dim == 2 ? kUO : -1; }
+// tile variants of the 2D operator: 16x16 threads (15x15 owned cells) or
+// 8x8 (7x7); the small tile spreads small levels over more compute units
+int uapply_tile(int dim, int variant) { return dim == 2 ? (variant == 1 ? 7 : 15) : -1; }
 
 // y = tau A x (mode 0) or y = b - tau A x (mode 1); essential rows: y = 0 (mode 0), y = b (mode 1).
-// One block = 16x16 cells (15x15 owned + low-side halo); each owned cell sums
+// One block = UT x UT cells ((UT-1)^2 owned + low-side halo); each owned cell sums
 // its lower-left 2x2 nodes (and the top/right boundary nodes of the last
 // cells) from the element rows of the cells sharing them, staged in LDS.
-template <typename T>
-__global__ __launch_bounds__(256) void uapply2d_kernel(const UGridSeg* __restrict__ segs, const int4* __restrict__ work,
-                                                       int mode, const T* __restrict__ X, const T* __restrict__ Bv,
-                                                       T* __restrict__ Y, const T* __restrict__ emat) {
-  __shared__ T E[18][kUT * kUT];
+// Every global load of a thread (the cell's x values and, for mode 1, its b
+// values) is issued before the first use, at clamped in-range indices.
+template <typename T, int UT>
+__global__ __launch_bounds__(UT * UT) void uapply2d_kernel(const UGridSeg* __restrict__ segs,
+                                                           const int4* __restrict__ work, int mode,
+                                                           const T* __restrict__ X, const T* __restrict__ Bv,
+                                                           T* __restrict__ Y, const T* __restrict__ emat) {
+  constexpr int UO = UT - 1;
+  __shared__ T E[18][UT * UT];
   const int4 w = work[blockIdx.x];
   const UGridSeg& G = segs[w.x];
   const int j = blockIdx.y;
@@ -35,29 +38,47 @@ __global__ __launch_bounds__(256) void uapply2d_kernel(const UGridSeg* __restric
   const T* Xl = X + vo;
   const T* Bl = Bv + vo;
   T* Yl = Y + vo;
-  const int lx = threadIdx.x, ly = threadIdx.y, tid = ly * kUT + lx;
+  const int lx = threadIdx.x, ly = threadIdx.y, tid = ly * UT + lx;
   const int nx = G.n[0], ny = G.n[1];
-  const int i = w.y * kUO - 1 + lx, jc = w.z * kUO - 1 + ly;
+  const int i = w.y * UO - 1 + lx, jc = w.z * UO - 1 + ly;
   const bool valid = (i >= 0) && (i < nx) && (jc >= 0) && (jc < ny);
   const bool owned = valid && lx >= 1 && ly >= 1;
   const bool lastx = i == nx - 1, lasty = jc == ny - 1;
   const int sux = G.su[0];
   const int nu1 = G.su[0] * G.su[1];
-  const int ub = 2 * i + sux * (2 * jc);
-  T uu[18];
+  const int ub = valid ? 2 * i + sux * (2 * jc) : 0;
+  T uu[18], bv[18] = {};
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int o = ub + a + sux * b;
+      uu[b * 3 + a] = Xl[o];
+      uu[9 + b * 3 + a] = Xl[nu1 + o];
+    }
+  if (mode == 1 && owned) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int o = ub + a + sux * b;
+        bv[b * 3 + a] = Bl[o];
+        bv[9 + b * 3 + a] = Bl[nu1 + o];
+      }
+  }
 #pragma unroll
   for (int b = 0; b < 3; ++b)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const bool bot = b == 0 && jc == 0;
       const bool fx = bot || (a == 0 && i == 0) || (a == 2 && lastx);
-      const int o = ub + a + sux * b;
-      uu[b * 3 + a] = (valid && !fx) ? Xl[o] : T(0);
-      uu[9 + b * 3 + a] = (valid && !bot) ? Xl[nu1 + o] : T(0);
+      if (!valid || fx) uu[b * 3 + a] = T(0);
+      if (!valid || bot) uu[9 + b * 3 + a] = T(0);
     }
   {
     const T* AE = emat + G.emat_off;   // tau A_e of this level (18x18)
-#pragma unroll
+    // one row per iteration (scalar loads; unrolling all rows would spill the scalar registers)
+#pragma unroll 1
     for (int rr = 0; rr < 18; ++rr) {
       T acc = 0;
 #pragma unroll
@@ -67,7 +88,7 @@ __global__ __launch_bounds__(256) void uapply2d_kernel(const UGridSeg* __restric
   }
   __syncthreads();
   if (!owned) return;
-#pragma unroll 1
+#pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
     for (int b = 0; b < 3; ++b)
@@ -83,7 +104,7 @@ __global__ __launch_bounds__(256) void uapply2d_kernel(const UGridSeg* __restric
           for (int sy = 0; sy < 2; ++sy) {
             if (b != 0 && sy == 0) continue;
             const int lb = b != 0 ? b : (sy == 0 ? 2 : 0);
-            const int dy = (b == 0 && sy == 0) ? -kUT : 0;
+            const int dy = (b == 0 && sy == 0) ? -UT : 0;
 #pragma unroll
             for (int sx = 0; sx < 2; ++sx) {
               if (a != 0 && sx == 0) continue;
@@ -93,23 +114,27 @@ __global__ __launch_bounds__(256) void uapply2d_kernel(const UGridSeg* __restric
             }
           }
         }
-        Yl[go] = mode == 0 ? v : Bl[go] - v;
+        Yl[go] = mode == 0 ? v : bv[c * 9 + b * 3 + a] - v;
       }
 }
 
 template <typename T>
 void launch_uapply(int dim, const UGridSeg* segs, const int4* work, int nwork, int nj, int mode, const T* x,
-                   const T* b, T* y, const T* emat, hipStream_t s) {
+                   const T* b, T* y, const T* emat, hipStream_t s, int variant) {
   if (dim == 2) {
-    hipLaunchKernelGGL((uapply2d_kernel<T>), dim3(nwork, nj), dim3(kUT, kUT), 0, s, segs, work, mode, x, b, y, emat);
+    if (variant == 1)
+      hipLaunchKernelGGL((uapply2d_kernel<T, 8>), dim3(nwork, nj), dim3(8, 8), 0, s, segs, work, mode, x, b, y, emat);
+    else
+      hipLaunchKernelGGL((uapply2d_kernel<T, 16>), dim3(nwork, nj), dim3(16, 16), 0, s, segs, work, mode, x, b, y,
+                         emat);
   } else {
     launch_uapply3d<T>(segs, work, nwork, nj, mode, x, b, y, emat, s);
   }
 }
 template void launch_uapply<double>(int, const UGridSeg*, const int4*, int, int, int, const double*, const double*,
-                                    double*, const double*, hipStream_t);
+                                    double*, const double*, hipStream_t, int);
 template void launch_uapply<float>(int, const UGridSeg*, const int4*, int, int, int, const float*, const float*,
-                                   float*, const float*, hipStream_t);
+                                   float*, const float*, hipStream_t, int);
 
 // ---- restriction pass ------------------------------------------------------------------------
 template <typename T>

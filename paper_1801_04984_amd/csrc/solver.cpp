@@ -46,6 +46,11 @@ constexpr int kQDegDefault = 8;                     // Chebyshev degree when lin
 // (the inverses stay resident in the last-level cache).
 constexpr long long kPCoarseCells = 256;
 constexpr long long kUCoarseDofs = 1100;
+#ifndef BT_UTILE16_MIN
+#define BT_UTILE16_MIN 1024
+#endif
+// 2D elasticity levels with fewer 16x16 tiles (times levels j) than this use 8x8 tiles
+constexpr long long kUTile16MinTiles = BT_UTILE16_MIN;
 constexpr long long kPCoarseBytes = 24LL << 20;   // sum over instances and levels j
 constexpr long long kUCoarseBytes = 48LL << 20;   // sum over instances (shared by the levels)
 
@@ -81,6 +86,7 @@ struct PrecData {
   UGridSeg* d_ug0c = nullptr;
   std::vector<long long> u_total, u_max;
   std::vector<std::vector<int4>> uwork;
+  std::vector<int> utile;   // 2D tile variant per u level
   std::vector<int4*> d_uwork;
   std::vector<std::vector<std::vector<RPass>>> rp;   // [transition][pass][inst]
   std::vector<std::vector<RPass*>> d_rp;
@@ -311,12 +317,19 @@ static void build_hierarchy(biot_problem_s* h, PrecData* P) {
   }
   P->nul = (int)P->ug.size();
   P->uemat_len = uemat_off;
-  // work lists per u level
+  // work lists per u level; 2D levels with few 16x16 tiles use 8x8 tiles
   P->uwork.assign(P->nul, {});
-  const int t = uapply_tile(d);
+  P->utile.assign(P->nul, 0);
+  for (int l = 0; l < P->nul; ++l) {
+    if (d != 2) continue;
+    long long t16 = 0;
+    for (const auto& g : P->ug[l]) t16 += (long long)((g.n[0] + 14) / 15) * ((g.n[1] + 14) / 15);
+    P->utile[l] = t16 * nl < kUTile16MinTiles ? 1 : 0;
+  }
   for (int l = 0; l < P->nul; ++l)
     for (int k = 0; k < cnt; ++k) {
       const UGridSeg& g = P->ug[l][k];
+      const int t = uapply_tile(d, P->utile[l]);
       if (d == 2) {
         for (int ty = 0; ty < (g.n[1] + t - 1) / t; ++ty)
           for (int tx = 0; tx < (g.n[0] + t - 1) / t; ++tx) P->uwork[l].push_back(make_int4(k, tx, ty, 0));
@@ -832,7 +845,7 @@ static void setup_elasticity(biot_problem_s* h, hipStream_t s) {
     const int nwork = (int)P->uwork[l].size();
     const long long mx = P->u_max[l];
     auto apply = [&](double* xx, double* yy) {
-      launch_uapply<double>(d, dseg, work, nwork, 1, 0, xx, nullptr, yy, P->d_uemat64, s);
+      launch_uapply<double>(d, dseg, work, nwork, 1, 0, xx, nullptr, yy, P->d_uemat64, s, P->utile[l]);
       launch_mul_dinv<double>(dls, cnt, 1, mx, B.u_dinv[0], yy, yy, s);
     };
     auto lam = power_max(P, apply, x, y, segs, s);
@@ -998,7 +1011,7 @@ static void u_vcycle(biot_problem_s* h, int l, T* x, const T* b, T* r, T* d0, T*
   // pre-smoothing from x = 0
   cheb_update<T>(ls, cnt, nl, mx, 2, 0.0, cs.s0, x, r, d0, nullptr, dinv, b, s);
   for (int k = 0; k < ud; ++k) {
-    launch_uapply<T>(d, gs, work, nwork, nl, 0, d0, nullptr, y, uemat<T>(P), s);
+    launch_uapply<T>(d, gs, work, nwork, nl, 0, d0, nullptr, y, uemat<T>(P), s, P->utile[l]);
     cheb_update<T>(ls, cnt, nl, mx, 1, cs.steps[k].first, cs.steps[k].second, x, r, d0, y, dinv, nullptr, s);
   }
   // restriction of r
@@ -1011,10 +1024,10 @@ static void u_vcycle(biot_problem_s* h, int l, T* x, const T* b, T* r, T* d0, T*
   u_vcycle<T>(h, l + 1, B.u_x[l + 1], B.u_b[l + 1], B.u_r[l + 1], B.u_d0[l + 1], B.u_y[l + 1], s);
   launch_uprolong<T>(P->d_up[l], cnt, nl, mx, P->d_utab, B.u_x[l + 1], x, s);
   // post-smoothing
-  launch_uapply<T>(d, gs, work, nwork, nl, 1, x, b, r, uemat<T>(P), s);
+  launch_uapply<T>(d, gs, work, nwork, nl, 1, x, b, r, uemat<T>(P), s, P->utile[l]);
   cheb_update<T>(ls, cnt, nl, mx, 0, 0.0, cs.s0, x, r, d0, nullptr, dinv, nullptr, s);
   for (int k = 0; k < ud; ++k) {
-    launch_uapply<T>(d, gs, work, nwork, nl, 0, d0, nullptr, y, uemat<T>(P), s);
+    launch_uapply<T>(d, gs, work, nwork, nl, 0, d0, nullptr, y, uemat<T>(P), s, P->utile[l]);
     cheb_update<T>(ls, cnt, nl, mx, 1, cs.steps[k].first, cs.steps[k].second, x, r, d0, y, dinv, nullptr, s);
   }
 }
