@@ -133,11 +133,14 @@ __device__ __forceinline__ T ep_node(const InstDev& I, const T* __restrict__ P, 
 }
 
 // div u of one level at the 2^DIM Gauss points of cell ce (x fastest),
-// essential values masked.  All node loops are compile-time.
+// essential values masked.  Sum factorisation: per component c the nodal
+// values are contracted axis by axis with the 2x3 tables DG (derivative, axis
+// c) and VG (value, other axes), which keeps the constants to those two tables.
 template <typename T, int DIM>
 __device__ __forceinline__ void cell_divu(const InstDev& I, const T* __restrict__ Xl, const int ce[3],
                                           T du[1 << DIM]) {
   constexpr int NG = 1 << DIM;
+  constexpr int NZ = DIM == 3 ? 3 : 1, GZ = DIM == 3 ? 2 : 1;
 #pragma unroll
   for (int g = 0; g < NG; ++g) du[g] = 0;
   const int su0 = I.su[0], su1 = I.su[1];
@@ -149,11 +152,9 @@ __device__ __forceinline__ void cell_divu(const InstDev& I, const T* __restrict_
   for (int c = 0; c < DIM; ++c) {
     const T ih = T(1.0 / I.h[c]);
     const T* U = Xl + I.off_u[c] + nb;
-    T s[NG];
+    T v[NZ][3][3];
 #pragma unroll
-    for (int g = 0; g < NG; ++g) s[g] = 0;
-#pragma unroll
-    for (int az = 0; az < (DIM == 3 ? 3 : 1); ++az)
+    for (int az = 0; az < NZ; ++az)
 #pragma unroll
       for (int ay = 0; ay < 3; ++ay)
 #pragma unroll
@@ -162,17 +163,49 @@ __device__ __forceinline__ void cell_divu(const InstDev& I, const T* __restrict_
           bool fx = DIM == 3 ? (az == 0 && bz0) : (ay == 0 && by0);
           if (c == 0) fx = fx || (ax == 0 && bx0) || (ax == 2 && bx1);
           if (DIM == 3 && c == 1) fx = fx || (ay == 0 && by0) || (ay == 2 && by1);
-          const T v = fx ? T(0) : U[ax + su0 * (ay + su1 * az)];
+          const T raw = U[ax + su0 * (ay + su1 * az)];
+          v[az][ay][ax] = fx ? T(0) : raw;
+        }
+    // contract x, then y, then z
+    T tx[NZ][3][2];
 #pragma unroll
-          for (int g = 0; g < NG; ++g) {
-            const int gx = g & 1, gy = (g >> 1) & 1, gz = (g >> 2) & 1;
-            double f = (c == 0 ? DG(gx, ax) : VG(gx, ax)) * (c == 1 ? DG(gy, ay) : VG(gy, ay));
-            if (DIM == 3) f *= c == 2 ? DG(gz, az) : VG(gz, az);
-            s[g] += T(f) * v;
-          }
+    for (int az = 0; az < NZ; ++az)
+#pragma unroll
+      for (int ay = 0; ay < 3; ++ay)
+#pragma unroll
+        for (int gx = 0; gx < 2; ++gx) {
+          T s = 0;
+#pragma unroll
+          for (int ax = 0; ax < 3; ++ax) s += T(c == 0 ? DG(gx, ax) : VG(gx, ax)) * v[az][ay][ax];
+          tx[az][ay][gx] = s;
+        }
+    T ty[NZ][2][2];
+#pragma unroll
+    for (int az = 0; az < NZ; ++az)
+#pragma unroll
+      for (int gy = 0; gy < 2; ++gy)
+#pragma unroll
+        for (int gx = 0; gx < 2; ++gx) {
+          T s = 0;
+#pragma unroll
+          for (int ay = 0; ay < 3; ++ay) s += T(c == 1 ? DG(gy, ay) : VG(gy, ay)) * tx[az][ay][gx];
+          ty[az][gy][gx] = s;
         }
 #pragma unroll
-    for (int g = 0; g < NG; ++g) du[g] += ih * s[g];
+    for (int gz = 0; gz < GZ; ++gz)
+#pragma unroll
+      for (int gy = 0; gy < 2; ++gy)
+#pragma unroll
+        for (int gx = 0; gx < 2; ++gx) {
+          T s = 0;
+          if (DIM == 3) {
+#pragma unroll
+            for (int az = 0; az < NZ; ++az) s += T(c == 2 ? DG(gz, az) : VG(gz, az)) * ty[az][gy][gx];
+          } else {
+            s = ty[0][gy][gx];
+          }
+          du[gx + 2 * gy + 4 * gz] += ih * s;
+        }
   }
 }
 

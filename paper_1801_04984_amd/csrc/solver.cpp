@@ -32,10 +32,18 @@ constexpr int kMaxRestart = 64;
 // coarse-correction over-relaxation of the aggregation multigrid (2^d cells per
 // aggregate; measured best on the 2D 128^2 / 3D 48^3 workloads: 2.1 / 1.9)
 inline double omega_p(int dim) { return dim == 2 ? 2.1 : 1.9; }
-constexpr int kPDeg = 3;                 // Chebyshev smoothing degree, pressure levels
+#ifndef BT_PDEG3
+#define BT_PDEG3 5
+#endif
+#ifndef BT_UDEG
+#define BT_UDEG 2
+#endif
+// Chebyshev smoothing degree on the pressure levels: 3 in 2D; in 3D degree 5
+// costs fewer slab iterations than it adds per iteration (measured on 32^3)
+inline int pdeg(int dim) { return dim == 2 ? 3 : BT_PDEG3; }
 constexpr double kPLo = 1.0 / 8.0, kPHi = 1.1;
 // Chebyshev degree of the elasticity smoother
-inline int udeg(int) { return 2; }
+inline int udeg(int) { return BT_UDEG; }
 constexpr double kULo = 1.0 / 15.0, kUHi = 1.1;
 constexpr double kQLo = 0.25, kQHi = 1.75;  // Gershgorin interval of Dq^-1 Mq
 constexpr long long kLineSolveMinLines = 16384;   // automatic flux-block choice
@@ -940,7 +948,8 @@ static void p_vcycle(biot_problem_s* h, int l, hipStream_t s) {
   PrecData* P = h->prec;
   auto& B = bufs<T>(P);
   const int nl = h->nl, cnt = h->count;
-  static const ChebSeq cs = cheb_seq(kPLo, kPHi, kPDeg);
+  const int pd = pdeg(h->dim);
+  const ChebSeq cs = cheb_seq(kPLo, kPHi, pd);
   if (l == P->npl - 1) {
     dense_solve<T>(P->d_pd, cnt, nl, P->p_maxn, false, P->pAinv, B.pc_b[l], B.pc_x[l], s);
     return;
@@ -950,7 +959,7 @@ static void p_vcycle(biot_problem_s* h, int l, hipStream_t s) {
   T *x = B.pc_x[l], *b = B.pc_b[l], *r = B.pc_r[l], *d0 = B.pc_d0[l], *d1 = B.pc_d1[l];
   launch_pcell<T>(sg, cnt, nl, mx, kResInitZero, ChebCoef{cs.s0, 0, 0, 1}, B.pc_coef[l], B.pc_dinv[l], b, x, r,
                   nullptr, d0, s);
-  for (int k = 0; k < kPDeg; ++k) {
+  for (int k = 0; k < pd; ++k) {
     launch_pcell<T>(sg, cnt, nl, mx, kStep, ChebCoef{0, cs.steps[k].first, cs.steps[k].second, 1}, B.pc_coef[l],
                     B.pc_dinv[l], b, x, r, (k & 1) ? d1 : d0, (k & 1) ? d0 : d1, s);
   }
@@ -959,7 +968,7 @@ static void p_vcycle(biot_problem_s* h, int l, hipStream_t s) {
   launch_p_prolong_cell<T>(sg, P->d_pc[l + 1], cnt, nl, mx, omega_p(h->dim), B.pc_x[l + 1], x, s);
   launch_pcell<T>(sg, cnt, nl, mx, kResInit, ChebCoef{cs.s0, 0, 0, 1}, B.pc_coef[l], B.pc_dinv[l], b, x, r, nullptr,
                   d0, s);
-  for (int k = 0; k < kPDeg; ++k) {
+  for (int k = 0; k < pd; ++k) {
     launch_pcell<T>(sg, cnt, nl, mx, kStep, ChebCoef{0, cs.steps[k].first, cs.steps[k].second, 1}, B.pc_coef[l],
                     B.pc_dinv[l], b, x, r, (k & 1) ? d1 : d0, (k & 1) ? d0 : d1, s);
   }
@@ -971,11 +980,12 @@ static void p_solve(biot_problem_s* h, const T* b, T* x, hipStream_t s) {
   PrecData* P = h->prec;
   auto& B = bufs<T>(P);
   const int nl = h->nl, cnt = h->count, d = h->dim;
-  static const ChebSeq cs = cheb_seq(kPLo, kPHi, kPDeg);
+  const int pd = pdeg(h->dim);
+  const ChebSeq cs = cheb_seq(kPLo, kPHi, pd);
   T *r = B.T1, *d0 = B.T2, *d1 = B.T3;
   launch_pdg<T>(d, h->d_inst, P->d_pdg, cnt, nl, P->pdg_max, kResInitZero, ChebCoef{cs.s0, 0, 0, -1}, B.dqinv,
                 B.pdg_dinv, b, x, r, nullptr, d0, s);
-  for (int k = 0; k < kPDeg; ++k)
+  for (int k = 0; k < pd; ++k)
     launch_pdg<T>(d, h->d_inst, P->d_pdg, cnt, nl, P->pdg_max, kStep,
                   ChebCoef{0, cs.steps[k].first, cs.steps[k].second, -1}, B.dqinv, B.pdg_dinv, b, x, r,
                   (k & 1) ? d1 : d0, (k & 1) ? d0 : d1, s);
@@ -984,7 +994,7 @@ static void p_solve(biot_problem_s* h, const T* b, T* x, hipStream_t s) {
   launch_p_prolong_dg<T>(h->d_inst, P->d_pdg, P->d_pc[0], cnt, nl, P->pdg_max, omega_p(h->dim), B.pc_x[0], x, s);
   launch_pdg<T>(d, h->d_inst, P->d_pdg, cnt, nl, P->pdg_max, kResInit, ChebCoef{cs.s0, 0, 0, -1}, B.dqinv,
                 B.pdg_dinv, b, x, r, nullptr, d0, s);
-  for (int k = 0; k < kPDeg; ++k)
+  for (int k = 0; k < pd; ++k)
     launch_pdg<T>(d, h->d_inst, P->d_pdg, cnt, nl, P->pdg_max, kStep,
                   ChebCoef{0, cs.steps[k].first, cs.steps[k].second, -1}, B.dqinv, B.pdg_dinv, b, x, r,
                   (k & 1) ? d1 : d0, (k & 1) ? d0 : d1, s);
