@@ -31,13 +31,21 @@
 
 namespace bt {
 
-template <typename T, int NL, bool TR, int kT2>
-__global__ __launch_bounds__(kT2 * kT2) void apply2d_kernel(const InstDev* __restrict__ insts,
-                                                            const int4* __restrict__ work, TimeMat tm,
-                                                            const T* __restrict__ kinv_all, const T* __restrict__ emat,
-                                                            const T* __restrict__ X, T* __restrict__ Y) {
+// LP (level-parallel): the block holds one kT2 x kT2 thread layer per time
+// level (threadIdx.z = level), each layer doing that level's rows; the forward
+// p-rows, which sum over levels, exchange the per-level values through LDS
+// and add them in the same order as the level loop, so both forms give
+// bitwise the same result.
+template <typename T, int NL, bool TR, int kT2, bool LP>
+__global__ __launch_bounds__(kT2 * kT2 * (LP ? NL : 1)) void apply2d_kernel(
+    const InstDev* __restrict__ insts, const int4* __restrict__ work, TimeMat tm, const T* __restrict__ kinv_all,
+    const T* __restrict__ emat, const T* __restrict__ X, T* __restrict__ Y) {
   constexpr int kO2 = kT2 - 1;
-  __shared__ T E[18][kT2 * kT2];
+  constexpr int kLay = LP ? NL : 1;
+  __shared__ T Es[kLay][18][kT2 * kT2];
+  __shared__ T Zs[LP && !TR ? NL : 1][4][LP && !TR ? kT2 * kT2 : 1];
+  const int lev0 = LP ? (int)threadIdx.z : 0, lev1 = LP ? lev0 + 1 : NL;
+  T(*E)[kT2 * kT2] = Es[LP ? lev0 : 0];
   const int4 w = work[blockIdx.x];
   const InstDev& I = insts[w.x];
   const int lx = threadIdx.x, ly = threadIdx.y, tid = ly * kT2 + lx;
@@ -54,7 +62,8 @@ __global__ __launch_bounds__(kT2 * kT2) void apply2d_kernel(const InstDev* __res
   const T ihx = T(1.0 / I.h[0]), ihy = T(1.0 / I.h[1]);
   const T tau = T(I.tau), bb = T(I.b), Minv = T(I.Minv);
   const T w2 = hx * hy * T(0.25);
-  const T kc = valid ? kinv_all[I.cell_off + i + nx * j] : T(0);
+  const T kraw = kinv_all[I.cell_off + (valid ? i + nx * j : 0)];
+  const T kc = valid ? kraw : T(0);
   // offsets of the cell's lowest node in each nodal array (x fastest)
   const int ub = 2 * i + sux * (2 * j);      // u_c (su0 x su1) and q_x (su0 x sp1) arrays
   const int qyb = 2 * i + spx * (2 * j);     // q_y (sp0 x su1) and p (sp0 x sp1) arrays
@@ -88,8 +97,9 @@ __global__ __launch_bounds__(kT2 * kT2) void apply2d_kernel(const InstDev* __res
 #pragma unroll
     for (int g = 0; g < 4; ++g) yp[l][g >> 1][g & 1] = T(0);
 
+  T tdq[2][2];   // level-parallel forward: tau div q of this thread's level
 #pragma unroll 1
-  for (int lev = 0; lev < NL; ++lev) {
+  for (int lev = lev0; lev < lev1; ++lev) {
     const T* Xl = Xb + lev * N;
     T* Yl = Yb + lev * N;
     // ---- cell data of this level (raw), then with essential values masked
@@ -207,9 +217,14 @@ __global__ __launch_bounds__(kT2 * kT2) void apply2d_kernel(const InstDev* __res
 #pragma unroll
         for (int gx = 0; gx < 2; ++gx) {
           const T z = bb * du[gy][gx] + Minv * pcur[gy][gx];
+          if constexpr (LP) {
+            Zs[LP && !TR ? lev : 0][gy * 2 + gx][LP && !TR ? tid : 0] = z;
+            tdq[gy][gx] = tau * dq[gy][gx];
+          } else {
 #pragma unroll
-          for (int l = 0; l < NL; ++l)
-            yp[l][gy][gx] += T(tm.T[l * 4 + lev]) * z + ((l == lev) ? tau * dq[gy][gx] : T(0));
+            for (int l = 0; l < NL; ++l)
+              yp[l][gy][gx] += T(tm.T[l * 4 + lev]) * z + ((l == lev) ? tau * dq[gy][gx] : T(0));
+          }
         }
     } else if (owned) {
 #pragma unroll
@@ -301,30 +316,47 @@ __global__ __launch_bounds__(kT2 * kT2) void apply2d_kernel(const InstDev* __res
   }
 
   if (!TR && owned) {
-#pragma unroll
-    for (int lev = 0; lev < NL; ++lev)
+    if constexpr (LP) {
+      // the level loop's sum for this thread's level, same terms in the same order
+      // (the loop's last barrier made every level's values visible)
 #pragma unroll
       for (int gy = 0; gy < 2; ++gy)
 #pragma unroll
-        for (int gx = 0; gx < 2; ++gx) Yb[lev * N + op + qyb + gx + spx * gy] = -w2 * yp[lev][gy][gx];
+        for (int gx = 0; gx < 2; ++gx) {
+          T y = T(0);
+#pragma unroll
+          for (int l = 0; l < NL; ++l)
+            y += T(tm.T[lev0 * 4 + l]) * Zs[LP && !TR ? l : 0][gy * 2 + gx][LP && !TR ? tid : 0] +
+                 ((l == lev0) ? tdq[gy][gx] : T(0));
+          Yb[lev0 * N + op + qyb + gx + spx * gy] = -w2 * y;
+        }
+    } else {
+#pragma unroll
+      for (int lev = 0; lev < NL; ++lev)
+#pragma unroll
+        for (int gy = 0; gy < 2; ++gy)
+#pragma unroll
+          for (int gx = 0; gx < 2; ++gx) Yb[lev * N + op + qyb + gx + spx * gy] = -w2 * yp[lev][gy][gx];
+    }
   }
 }
 
-template <typename T, int NL, int TS>
+template <typename T, int NL, int TS, bool LP>
 static void launch_ts(const ApplyArgs& a, const void* x, void* y, int transpose) {
-  dim3 blk(TS, TS);
+  dim3 blk(TS, TS, LP ? NL : 1);
   if (transpose)
-    hipLaunchKernelGGL((apply2d_kernel<T, NL, true, TS>), dim3(a.nwork), blk, 0, a.stream, a.inst, a.work, *a.tm,
+    hipLaunchKernelGGL((apply2d_kernel<T, NL, true, TS, LP>), dim3(a.nwork), blk, 0, a.stream, a.inst, a.work, *a.tm,
                        (const T*)a.kinv, (const T*)a.emat, (const T*)x, (T*)y);
   else
-    hipLaunchKernelGGL((apply2d_kernel<T, NL, false, TS>), dim3(a.nwork), blk, 0, a.stream, a.inst, a.work, *a.tm,
-                       (const T*)a.kinv, (const T*)a.emat, (const T*)x, (T*)y);
+    hipLaunchKernelGGL((apply2d_kernel<T, NL, false, TS, LP>), dim3(a.nwork), blk, 0, a.stream, a.inst, a.work,
+                       *a.tm, (const T*)a.kinv, (const T*)a.emat, (const T*)x, (T*)y);
 }
 
 template <typename T, int NL>
 static void launch_nl(const ApplyArgs& a, const void* x, void* y, int transpose) {
-  if (a.variant == 1) launch_ts<T, NL, 8>(a, x, y, transpose);
-  else launch_ts<T, NL, 16>(a, x, y, transpose);
+  if (a.variant == 2) launch_ts<T, NL, 8, true>(a, x, y, transpose);
+  else if (a.variant == 1) launch_ts<T, NL, 8, false>(a, x, y, transpose);
+  else launch_ts<T, NL, 16, false>(a, x, y, transpose);
 }
 
 template <typename T>
@@ -340,8 +372,9 @@ void launch_apply2d(const ApplyArgs& a, const void* x, void* y, int transpose) {
 template void launch_apply2d<double>(const ApplyArgs&, const void*, void*, int);
 template void launch_apply2d<float>(const ApplyArgs&, const void*, void*, int);
 
-// tile variants: 0 = 16x16 threads (15x15 owned cells), 1 = 8x8 (7x7)
-int apply2d_variants() { return 2; }
-int apply2d_tile_cells(int variant) { return variant == 1 ? 7 : 15; }
+// tile variants: 0 = 16x16 threads (15x15 owned cells), 1 = 8x8 (7x7),
+// 2 = 8x8 per time level, the levels in parallel (7x7)
+int apply2d_variants() { return 3; }
+int apply2d_tile_cells(int variant) { return variant >= 1 ? 7 : 15; }
 
 }  // namespace bt

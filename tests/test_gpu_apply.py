@@ -106,20 +106,21 @@ def test_slab_rhs_3d(r):
     h.close()
 
 
-@pytest.mark.parametrize("d", [2, 3])
-def test_tile_variants_identical_and_autotune(d, tmp_path):
-    """Every tile variant of the apply gives bitwise the same y (FP64, FP32,
-    transposed), the autotuner selects a valid variant per precision, and a
-    cached selection is restored by the tuning module."""
+@pytest.mark.parametrize("d,r", [(2, 1), (2, 2), (3, 1)])
+def test_tile_variants_identical_and_autotune(d, r, tmp_path):
+    """Every tile variant of the apply (2D: 16x16 and 8x8 tiles with a level
+    loop, 8x8 tiles with the levels in parallel; 3D: z-chunks) gives bitwise
+    the same y (FP64, FP32, transposed), the autotuner selects a valid variant
+    per precision, and a cached selection is restored by the tuning module."""
     torch = torch_cuda()
     from paper_1801_04984_amd import BiotSlab, native, tuning
     if d == 2:
-        wls = [small_workload(2, (37, 21), 1, seed=5), small_workload(2, (9, 30), 1, seed=6)]
+        wls = [small_workload(2, (37, 21), r, seed=5), small_workload(2, (9, 30), r, seed=6)]
     else:
-        wls = [small_workload(3, (9, 8, 19), 1, seed=7), small_workload(3, (4, 6, 5), 1, seed=8)]
+        wls = [small_workload(3, (9, 8, 19), r, seed=7), small_workload(3, (4, 6, 5), r, seed=8)]
     h = BiotSlab(wls, [w.log_k() for w in wls])
     nv = h.get_tuning()["n_variants"]
-    assert nv == (2 if d == 2 else 3)
+    assert nv == 3
     rng = np.random.default_rng(3)
     x64 = torch.tensor(rng.standard_normal(h.slab_len), device="cuda")
     for dtype in (torch.float64, torch.float32):
