@@ -263,8 +263,9 @@ def main():
     ms32, by32 = time_apply(torch, h, torch.float32)
     out["apply"] = {"fp64": {"dof_applies_per_s": slab_dofs / (ms64 * 1e-3), "us": ms64 * 1e3},
                     "fp32": {"dof_applies_per_s": slab_dofs / (ms32 * 1e-3), "us": ms32 * 1e3}}
-    ts = 8 if tune["apply_variant"][0] == 1 else 16
-    kkey = f"bt::apply2d_kernel<double, 2, false, {ts}>"
+    # tile variants: 0 = 16x16 tiles, 1 = 8x8 tiles, 2 = 8x8 tiles with the time levels in parallel
+    ts, lp = {0: (16, "false"), 1: (8, "false"), 2: (8, "true")}[tune["apply_variant"][0]]
+    kkey = f"bt::apply2d_kernel<double, 2, false, {ts}, {lp}>"
     out["roofline"] = dict(roofline_of(ms64, by64), kernel=kkey + " (space-time operator apply, FP64)",
                            traffic=measured_traffic(kkey))
     h.close()
