@@ -148,7 +148,7 @@ struct PrecData {
   // captured Arnoldi steps (preconditioner, operator, CGS2, normalisation), one
   // per Krylov index and variant; their dot products land in pinned host memory
   std::map<long long, hipGraphExec_t> arnoldi;
-  double* hdots = nullptr;   // 3 x count x 64: V^T w (two passes) and ||w||^2
+  double* hdots = nullptr;   // 3 x count x 64: V^T w of the two Gram-Schmidt passes, |w|^2
   long long maxN = 0, maxcells = 0, maxlines = 0;
   int maxcells_line = 0;   // most cells along any axis of any instance
 };
@@ -1128,6 +1128,11 @@ static void seg_norms(PrecData* P, const T* v, int cnt, hipStream_t s, std::vect
   for (int k = 0; k < cnt; ++k) out[k] = std::sqrt(std::max(tmp[k * 64], 0.0));
 }
 
+// Dot-product sets hold 64 values per instance: the combined second pass (jj + 2
+// values) fits up to Krylov index 62; the last index of a 64-step cycle takes a
+// separate norm pass.
+static inline bool pythagorean_norm(int jj) { return jj + 2 <= 64; }
+
 // One Arnoldi step at Krylov index jj: w = A P^-1 v_jj, two classical
 // Gram-Schmidt passes against v_0..v_jj, v_{jj+1} = w / ||w||.  The three dot
 // product sets are also written to P->hdots for the host's Givens update.
@@ -1159,10 +1164,19 @@ static void arnoldi_step(biot_problem_s* h, int jj, int transpose, const SolveCt
   double* hd = P->hdots;
   seg_mdot<T, T>(B.V, S, jj + 1, vn, P->d_gseg, cnt, nch, P->partial, P->dot1, s, hd);
   seg_maxpy<T, T>(B.V, S, jj + 1, P->dot1, -1.0, vn, P->d_gseg, cnt, P->gmax, s);
-  seg_mdot<T, T>(B.V, S, jj + 1, vn, P->d_gseg, cnt, nch, P->partial, P->dot2, s, hd + 64 * cnt);
-  seg_maxpy<T, T>(B.V, S, jj + 1, P->dot2, -1.0, vn, P->d_gseg, cnt, P->gmax, s);
-  seg_mdot<T, T>(vn, 0, 1, vn, P->d_gseg, cnt, nch, P->partial, P->dot3, s, hd + 128 * cnt);
-  seg_scale<T, T>(vn, vn, P->dot3, 0, 2, P->d_gseg, cnt, P->gmax, s);   // 0 for a zero norm
+  if (pythagorean_norm(jj)) {
+    // second pass; w itself is basis slot jj+1, so the same pass gives |w|^2, and
+    // the norm after the update follows by Pythagoras (the second-pass components
+    // are at rounding level, so no cancellation)
+    seg_mdot<T, T>(B.V, S, jj + 2, vn, P->d_gseg, cnt, nch, P->partial, P->dot2, s, hd + 64 * cnt);
+    seg_maxpy<T, T>(B.V, S, jj + 1, P->dot2, -1.0, vn, P->d_gseg, cnt, P->gmax, s);
+    seg_scale<T, T>(vn, vn, P->dot2, jj + 1, 3, P->d_gseg, cnt, P->gmax, s);   // 0 for a zero norm
+  } else {
+    seg_mdot<T, T>(B.V, S, jj + 1, vn, P->d_gseg, cnt, nch, P->partial, P->dot2, s, hd + 64 * cnt);
+    seg_maxpy<T, T>(B.V, S, jj + 1, P->dot2, -1.0, vn, P->d_gseg, cnt, P->gmax, s);
+    seg_mdot<T, T>(vn, 0, 1, vn, P->d_gseg, cnt, nch, P->partial, P->dot3, s, hd + 128 * cnt);
+    seg_scale<T, T>(vn, vn, P->dot3, 0, 2, P->d_gseg, cnt, P->gmax, s);
+  }
 }
 
 // the Arnoldi step through a graph captured once per (index, variant), replayed on s
@@ -1247,7 +1261,14 @@ static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const Solv
       const double* h2 = P->hdots + 64 * cnt;
       const double* hn = P->hdots + 128 * cnt;
       for (int k = 0; k < cnt; ++k) {
-        const double nrm = std::sqrt(std::max(hn[k * 64], 0.0));
+        double n2;
+        if (pythagorean_norm(jj)) {
+          n2 = h2[k * 64 + jj + 1];
+          for (int i = 0; i <= jj; ++i) n2 -= h2[k * 64 + i] * h2[k * 64 + i];
+        } else {
+          n2 = hn[k * 64];
+        }
+        const double nrm = std::sqrt(std::max(n2, 0.0));
         if (!std::isfinite(nrm)) throw BiotError{BIOT_ERR_NONFINITE, "non-finite Krylov vector"};
         if (!act[k]) continue;
         double* Hk = &H[(size_t)k * (kMaxRestart + 1) * kMaxRestart];

@@ -42,6 +42,9 @@ template <typename TV, typename TW>
 void seg_maxpy(const TV* V, long long ldv, int nk, const double* c, double csign, TW* w, const VSeg* segs, int nseg,
                long long maxlen, hipStream_t s);
 template <typename TX, typename TY>
+// y[seg] = f x[seg] with f = sc[seg*64+idx] (inv 0), its inverse (1), its inverse
+// square root (2), or 1 / sqrt(sc[idx] - sum_{i<idx} sc[i]^2) (3); zero for a
+// non-positive argument (1-3)
 void seg_scale(const TX* x, TY* y, const double* sc, int idx, int inv, const VSeg* segs, int nseg, long long maxlen,
                hipStream_t s);
 template <typename T>

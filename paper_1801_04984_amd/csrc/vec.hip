@@ -178,6 +178,13 @@ __global__ __launch_bounds__(256) void sscale_kernel(const TX* __restrict__ x, T
                               int inv, const VSeg* __restrict__ segs) {
   const VSeg sg = segs[blockIdx.y];
   double f = sc[blockIdx.y * 64 + idx];
+  if (inv == 3) {
+    // squared norm by Pythagoras: sc[idx] = |w|^2 before removing the components
+    // sc[0..idx-1] along orthonormal vectors
+    const double* c = sc + blockIdx.y * 64;
+    for (int i = 0; i < idx; ++i) f -= c[i] * c[i];
+    inv = 2;
+  }
   if (inv == 1) f = f > 0.0 ? 1.0 / f : 0.0;
   else if (inv == 2) f = f > 0.0 ? 1.0 / sqrt(f) : 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < sg.len;

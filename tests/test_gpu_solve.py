@@ -304,3 +304,19 @@ def test_graph_replay_matches_eager(precision, transpose):
     xg, ig, sg = h.solve(b, precision=precision, graph=1, transpose=transpose)
     assert sg == 0 and torch.equal(xg, xe)
     h.close()
+
+
+def test_full_length_restart_cycle():
+    """A 64-step restart cycle run to its end (tolerance out of reach): the last
+    Krylov index takes the separate norm pass, and the solution still matches
+    the oracle's."""
+    torch = torch_cuda()
+    wl = small_workload(2, (12, 10), 1, seed=77)
+    h, (prob,) = make_pair([wl])
+    b = _rhs(prob, seed=3)
+    ref = prob.solve(b)
+    x, info, st = h.solve(torch.tensor(b, device="cuda"), rtol=1e-30, restart=64, maxit=64)
+    assert info[0]["iterations"] == 64, info
+    err = field_rel(prob, x.cpu().numpy(), ref)
+    assert max(err.values()) < TOL, err
+    h.close()
