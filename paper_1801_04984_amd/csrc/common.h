@@ -20,6 +20,22 @@ namespace bt {
 #endif
 constexpr int kBlk = BT_BLK;
 
+// The 8 XCDs of the chip each have their own L2, and consecutive workgroup ids
+// go to consecutive XCDs.  xcd_order(n)[b] = the tile that workgroup b should
+// take so that every XCD gets one contiguous run of tiles (neighbouring tiles
+// share halo data through that XCD's L2): XCD x = b % 8 takes its k-th
+// (k = b / 8) tile from the x-th run.
+#ifndef BT_NO_XCD_ORDER
+constexpr int kXcds = 8;
+#else
+constexpr int kXcds = 1;
+#endif
+inline long long xcd_tile(long long b, long long n) {
+  const long long x = b % kXcds, k = b / kXcds;
+  const long long base = n / kXcds, rem = n % kXcds;   // run x holds base + (x < rem) tiles
+  return x * base + (x < rem ? x : rem) + k;
+}
+
 // ---------------------------------------------------------------------------
 // 1D bases on [0, 1]
 //   closed:  phi_0 = (2s-1)(s-1), phi_1 = 4s(1-s), phi_2 = s(2s-1)

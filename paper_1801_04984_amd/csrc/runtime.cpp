@@ -95,6 +95,14 @@ static InstDev make_inst(const biot_problem_desc& d) {
   return I;
 }
 
+// work list reordered so that each XCD processes one contiguous run of tiles
+std::vector<int4> xcd_ordered(const std::vector<int4>& w) {
+  const long long n = (long long)w.size();
+  std::vector<int4> o(w.size());
+  for (long long b = 0; b < n; ++b) o[b] = w[xcd_tile(b, n)];
+  return o;
+}
+
 static std::vector<int4> make_work(const biot_problem_s* h, int variant) {
   std::vector<int4> w;
   for (int k = 0; k < h->count; ++k) {
@@ -110,7 +118,7 @@ static std::vector<int4> make_work(const biot_problem_s* h, int variant) {
           for (int tx = 0; tx < (I.n[0] + t - 1) / t; ++tx) w.push_back(make_int4(k, tx, ty, z));
     }
   }
-  return w;
+  return xcd_ordered(w);
 }
 
 // layout of everything the handle keeps on the device

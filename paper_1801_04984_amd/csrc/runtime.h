@@ -12,6 +12,9 @@
 
 namespace bt {
 
+// work list reordered so that each XCD processes one contiguous run of tiles
+std::vector<int4> xcd_ordered(const std::vector<int4>& w);
+
 // workspace layout builder: the same code sizes and carves the workspace
 struct Layout {
   size_t off = 0;

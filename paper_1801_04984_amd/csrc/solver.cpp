@@ -348,6 +348,7 @@ static void build_hierarchy(biot_problem_s* h, PrecData* P) {
             for (int tx = 0; tx < (g.n[0] + txy - 1) / txy; ++tx) P->uwork[l].push_back(make_int4(k, tx, ty, z));
       }
     }
+  for (int l = 0; l < P->nul; ++l) P->uwork[l] = xcd_ordered(P->uwork[l]);
   // transfers per transition l -> l+1
   P->utab_h.clear();
   P->rp.assign(std::max(0, P->nul - 1), {});
