@@ -101,16 +101,44 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
     // and every node is written to the element-vector slot of each cell that
     // shares it (essential u masked).  Cells outside the mesh get partial
     // vectors; their rows are never summed into an owned node.
-    constexpr int NX = 2 * kT3 + 1, NP = NX * NX;
-    for (int idx = tid; idx < 9 * NP; idx += NT) {
-      const int cz = idx / NP;                 // comp * 3 + plane
+    constexpr int NX = 2 * kT3 + 1, NP = NX * NX, NGA = 9 * NP;
+    // FP64: all of a thread's loads first (clamped in-range addresses, masked
+    // after), so that they are in flight together, then the scatter into LDS.
+    // FP32 keeps the single loop: there the unrolled form spills scalar
+    // registers and measured slower.
+    constexpr int NIT = sizeof(T) == 8 ? (NGA + NT - 1) / NT : 1;
+    T gv[NIT];
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        const int idx = min(tid + it * NT, NGA - 1);
+        const int cz = idx / NP;               // comp * 3 + plane
+        const int r = idx - cz * NP;
+        const int c2 = cz / 3, z = cz - 3 * c2;
+        const int ny_ = r / NX, nx_ = r - NX * ny_;
+        const int mx = 2 * (i0 - 1) + nx_, my = 2 * (j0 - 1) + ny_, mz = 2 * k + z;
+        const int mxc = min(max(mx, 0), J.su[0] - 1), myc = min(max(my, 0), J.su[1] - 1);
+        const T raw = J.X[c2 * nu1 + mxc + sy * myc + sz * mz];
+        const bool in = mx >= 0 && mx < J.su[0] && my >= 0 && my < J.su[1] && !ugrid_fixed(3, J.su, c2, mx, my, mz);
+        gv[it] = in ? raw : T(0);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < (sizeof(T) == 8 ? NIT : 1); ++it)
+    for (int idx = tid + it * NT; idx < NGA; idx += (sizeof(T) == 8 ? NGA : NT)) {
+      const int cz = idx / NP;
       const int r = idx - cz * NP;
       const int c2 = cz / 3, z = cz - 3 * c2;
       const int ny_ = r / NX, nx_ = r - NX * ny_;
-      const int mx = 2 * (i0 - 1) + nx_, my = 2 * (j0 - 1) + ny_, mz = 2 * k + z;
-      T v = 0;
-      if (mx >= 0 && mx < J.su[0] && my >= 0 && my < J.su[1] && !ugrid_fixed(3, J.su, c2, mx, my, mz))
-        v = J.X[c2 * nu1 + mx + sy * my + sz * mz];
+      T v;
+      if constexpr (sizeof(T) == 8) {
+        v = gv[it];
+      } else {
+        const int mx = 2 * (i0 - 1) + nx_, my = 2 * (j0 - 1) + ny_, mz = 2 * k + z;
+        v = 0;
+        if (mx >= 0 && mx < J.su[0] && my >= 0 && my < J.su[1] && !ugrid_fixed(3, J.su, c2, mx, my, mz))
+          v = J.X[c2 * nu1 + mx + sy * my + sz * mz];
+      }
       // cells of the tile sharing the node along x and y (local node a, b)
 #pragma unroll
       for (int sj = 0; sj < 2; ++sj) {
@@ -166,7 +194,24 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
     __syncthreads();
     // ---- owned node planes 2k (bottom slice + carried top slice) and 2k+1
     if (k >= k0) {
-      for (int idx = tid; idx < 6 * nplane; idx += NT) {
+      // FP64 residual mode: the right-hand side values first, all in flight
+      // together (FP32 keeps the single loop, as for the gather)
+      constexpr int NOW = sizeof(T) == 8 ? (6 * (2 * kO3 + 1) * (2 * kO3 + 1) + NT - 1) / NT : 1;
+      T bvv[NOW];
+      if (sizeof(T) == 8 && J.mode != 0) {
+#pragma unroll
+        for (int it = 0; it < NOW; ++it) {
+          const int idx = min(tid + it * NT, 6 * nplane - 1);
+          const int c = idx / (2 * nplane);
+          const int rem = idx - c * 2 * nplane;
+          const int zl = rem >= nplane;
+          const int r2 = rem - zl * nplane;
+          bvv[it] = J.Bv[c * nu1 + (2 * i0 + r2 % nmx) + sy * (2 * j0 + r2 / nmx) + sz * (2 * k + zl)];
+        }
+      }
+#pragma unroll
+      for (int it = 0; it < NOW; ++it)
+      for (int idx = tid + it * NT; idx < 6 * nplane; idx += (sizeof(T) == 8 ? 6 * nplane : NT)) {
         const int c = idx / (2 * nplane);
         const int rem = idx - c * 2 * nplane;
         const int zl = rem >= nplane;
@@ -175,7 +220,7 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
         const int go = c * nu1 + mx + sy * my + sz * mz;
         T v;
         if (ugrid_fixed(3, J.su, c, mx, my, mz)) {
-          v = J.mode == 0 ? J.X[go] : J.Bv[go];
+          v = J.mode == 0 ? J.X[go] : (sizeof(T) == 8 ? bvv[it] : J.Bv[go]);
         } else {
           const bool xo = mx & 1, yo = my & 1;
           const int cx0 = xo ? (mx - 1) / 2 : mx / 2 - 1, ax0 = xo ? 1 : 2;
@@ -193,7 +238,7 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
             v += Ul[(c * 27 + zl * 9 + nd) * kLD3 + cell];
             if (zl == 0) v += Cc[(c * 9 + nd) * NC + cell];
           }
-          if (J.mode != 0) v = J.Bv[go] - v;
+          if (J.mode != 0) v = (sizeof(T) == 8 ? bvv[it] : J.Bv[go]) - v;
         }
         J.Y[go] = v;
       }
