@@ -32,17 +32,16 @@ __global__ __launch_bounds__(256) void coupling_kernel(const InstDev* __restrict
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nuq; t += gridDim.x * blockDim.x) {
     int blk, comp, co[3];
     decode_dof(I, t, blk, comp, co);
-    T v = 0;
+    const T r = rt[lo + t];
+    // the gathers run for essential rows too (their result is discarded), so
+    // that no load waits behind a per-lane branch
     if (blk == 0) {
-      if (!u_fixed(I, comp, co[0], co[1], co[2])) v = rt[lo + t] + T(I.b * I.tau) * ep_node<T, DIM>(I, P, comp, co);
-      fu[lo + t] = v;
+      const T ep = ep_node<T, DIM>(I, P, comp, co);
+      fu[lo + t] = u_fixed(I, comp, co[0], co[1], co[2]) ? T(0) : r + T(I.b * I.tau) * ep;
     } else {
-      if (!q_fixed(I, comp, co[comp])) {
-        T mq, dg, bp;
-        flux_row<T, false>(I, nullptr, zp + lo, comp, co, t - (int)I.off_q[comp], mq, dg, bp);
-        v = rt[lo + t] - T(I.tau) * bp;
-      }
-      fq[lo + t] = v;
+      T mq, dg, bp;
+      flux_row<T, false>(I, nullptr, zp + lo, comp, co, t - (int)I.off_q[comp], mq, dg, bp);
+      fq[lo + t] = q_fixed(I, comp, co[comp]) ? T(0) : r - T(I.tau) * bp;
     }
   }
 }
