@@ -287,9 +287,11 @@ __device__ __forceinline__ void cell_divq(const InstDev& I, const T* __restrict_
       if (c == 1) o[1] = mc0;
       if (c == 2) o[2] = mc0;
       const T* Q = Xl + I.off_q[c] + (o[0] + qs0 * (o[1] + qs1 * o[2]));
-      T acc = T(DG(gc, 1)) * Q[cstr];
-      if (!lo_fixed) acc += T(DG(gc, 0)) * Q[0];
-      if (!hi_fixed) acc += T(DG(gc, 2)) * Q[2 * cstr];
+      // essential end nodes masked by their weight, not by a branch around the load
+      const T q0 = Q[0], q1 = Q[cstr], q2 = Q[2 * cstr];
+      T acc = T(DG(gc, 1)) * q1;
+      acc += (lo_fixed ? T(0) : T(DG(gc, 0))) * q0;
+      acc += (hi_fixed ? T(0) : T(DG(gc, 2))) * q2;
       dq[g] += ih * acc;
     }
   }
