@@ -106,7 +106,7 @@ def test_slab_rhs_3d(r):
     h.close()
 
 
-@pytest.mark.parametrize("d,r", [(2, 1), (2, 2), (3, 1)])
+@pytest.mark.parametrize("d,r", [(2, 1), (2, 2), (2, 3), (3, 1)])
 def test_tile_variants_identical_and_autotune(d, r, tmp_path):
     """Every tile variant of the apply (2D: 16x16 and 8x8 tiles with a level
     loop, 8x8 tiles with the levels in parallel; 3D: z-chunks) gives bitwise
