@@ -153,8 +153,11 @@ biot_status apply_operator(biot_problem h, const void* x, void* y, int32_t trans
 
 /* Tile shapes of the operator apply.  Every variant computes bitwise the same
  * y; they differ only in the work decomposition (2D: 0 = 16x16-thread tiles,
- * 1 = 8x8; 3D: z-chunk of 0 = 8, 1 = 4, 2 = 16 cell layers per block).
- * apply_variant[0] is used for FP64 applies, [1] for FP32. */
+ * 1 = 8x8, 2 = 8x8 with one thread layer per time level, the levels in
+ * parallel; 3D: z-chunk of 0 = 8, 1 = 4, 2 = 16 cell layers per block).
+ * apply_variant[0] is used for FP64 applies, [1] for FP32.  Changing the
+ * selection drops the solver's captured Arnoldi-step graphs (they are
+ * captured again on the next solve). */
 typedef struct {
   int32_t apply_variant[2];
   int32_t n_variants;        /* out: variants available for the handle's dimension */
