@@ -94,18 +94,17 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
 #pragma unroll
   for (int s = 0; s < KS; ++s) af[s] = J.A[(wv * KS + s) * 64 + lane];
   for (int idx = tid; idx < 27 * NC; idx += NT) Cc[idx] = T(0);
-  // node-plane gather: 3 planes x 3 components of 17 x 17 nodes per layer.  FP64
-  // issues all of a thread's loads before the LDS scatter; their offsets (less
+  // node-plane gather: 3 planes x 3 components of 17 x 17 nodes per layer.  All
+  // of a thread's loads are issued before the LDS scatter; their offsets (less
   // the layer term) and masks do not depend on the layer and are computed here.
-  // FP32 keeps a single loop: the unrolled form spilled there and measured slower.
   constexpr int NX = 2 * kT3 + 1, NP = NX * NX, NGA = 9 * NP;
-  constexpr int NIT = sizeof(T) == 8 ? (NGA + NT - 1) / NT : 1;
+  constexpr int NIT = (NGA + NT - 1) / NT;
   // per load: bits 0..29 the in-range offset, bit 30 = plane z 0 (bottom face at
   // k = 0), bit 31 = masked (outside the tile's node range or essential).  The
   // offset is below the size of one level's u block, which the host's limit of
   // 2^31 slab unknowns keeps under 2^30.
   unsigned gcode[NIT];
-  if constexpr (sizeof(T) == 8) {
+  {
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
       const int idx = min(tid + it * NT, NGA - 1);
@@ -129,32 +128,23 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
     // shares it (essential u masked).  Cells outside the mesh get partial
     // vectors; their rows are never summed into an owned node.
     T gv[NIT];
-    if constexpr (sizeof(T) == 8) {
 #pragma unroll
-      for (int it = 0; it < NIT; ++it) {
-        // bottom face (plane mz = 0) is essential for every component
-        const unsigned g = gcode[it];
-        const bool in = !(g >> 31) && !(k == 0 && ((g >> 30) & 1u));
-        const T raw = J.X[(int)(g & 0x3fffffffu) + sz * (2 * k)];
-        gv[it] = in ? raw : T(0);
-      }
+    for (int it = 0; it < NIT; ++it) {
+      // bottom face (plane mz = 0) is essential for every component
+      const unsigned g = gcode[it];
+      const bool in = !(g >> 31) && !(k == 0 && ((g >> 30) & 1u));
+      const T raw = J.X[(int)(g & 0x3fffffffu) + sz * (2 * k)];
+      gv[it] = in ? raw : T(0);
     }
 #pragma unroll
-    for (int it = 0; it < (sizeof(T) == 8 ? NIT : 1); ++it)
-    for (int idx = tid + it * NT; idx < NGA; idx += (sizeof(T) == 8 ? NGA : NT)) {
+    for (int it = 0; it < NIT; ++it) {
+      const int idx = tid + it * NT;
+      if (idx >= NGA) break;
       const int cz = idx / NP;
       const int r = idx - cz * NP;
       const int c2 = cz / 3, z = cz - 3 * c2;
       const int ny_ = r / NX, nx_ = r - NX * ny_;
-      T v;
-      if constexpr (sizeof(T) == 8) {
-        v = gv[it];
-      } else {
-        const int mx = 2 * (i0 - 1) + nx_, my = 2 * (j0 - 1) + ny_, mz = 2 * k + z;
-        v = 0;
-        if (mx >= 0 && mx < J.su[0] && my >= 0 && my < J.su[1] && !ugrid_fixed(3, J.su, c2, mx, my, mz))
-          v = J.X[c2 * nu1 + mx + sy * my + sz * mz];
-      }
+      const T v = gv[it];
       // cells of the tile sharing the node along x and y (local node a, b)
 #pragma unroll
       for (int sj = 0; sj < 2; ++sj) {
