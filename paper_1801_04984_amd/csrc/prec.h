@@ -32,6 +32,7 @@ struct PDgSeg {
   long long dqoff;             // Dq^-1 (state layout) of this instance
   long long doff, djstride;    // Dinv of S_j (normalised), per time level
   double cm[4];                // alpha_j (1/M + L) for each time level
+  InstDev I;                   // copy of the instance descriptor (one indirection less per launch)
 };
 // pressure Schur, cell levels
 struct PCellSeg {

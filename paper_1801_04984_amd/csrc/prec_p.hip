@@ -146,14 +146,14 @@ __device__ __forceinline__ void pdg_cell(const InstDev& I, const T* __restrict__
   }
 }
 
-template <typename T, int DIM>
-__global__ __launch_bounds__(256) void pdg_kernel(const InstDev* __restrict__ insts, const PDgSeg* __restrict__ segs, int mode, ChebCoef cc,
+template <typename T, int DIM, int MODE>
+__global__ __launch_bounds__(256) void pdg_kernel(const PDgSeg* __restrict__ segs, ChebCoef cc,
                            const T* __restrict__ dqinv, const T* __restrict__ dinv,
                            const T* __restrict__ b, T* __restrict__ x, T* __restrict__ r,
                            const T* __restrict__ din, T* __restrict__ dout) {
   constexpr int NG = 1 << DIM;
-  const PDgSeg sg = segs[blockIdx.y];
-  const InstDev& I = insts[sg.inst];
+  const PDgSeg& sg = segs[blockIdx.y];
+  const InstDev& I = sg.I;
   const int j = blockIdx.z;
   const long long vo = sg.voff + j * sg.vjstride;
   const long long dof = sg.doff + j * sg.djstride;
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void pdg_kernel(const InstDev* __restrict__ in
       for (int e = 0; e < DIM; ++e) o += ((g >> e) & 1) * pstr[e];
       oo[g] = o;
     }
-    if (mode == kResInitZero) {            // x = 0: r = bsign b, d = s0 Dinv r
+    if constexpr (MODE == kResInitZero) {            // x = 0: r = bsign b, d = s0 Dinv r
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
         const T rr = T(cc.bsign) * b[vo + oo[g]];
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) void pdg_kernel(const InstDev* __restrict__ in
         r[vo + oo[g]] = rr;
         dout[vo + oo[g]] = T(cc.s0) * dinv[dof + oo[g]] * rr;
       }
-    } else if (mode == kResInit) {         // r = bsign b - S x, d = s0 Dinv r
+    } else if constexpr (MODE == kResInit) {         // r = bsign b - S x, d = s0 Dinv r
       // every load precedes every store, so the loads are all in flight together
       T bv[NG], dv[NG], Sx[NG];
 #pragma unroll
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(256) void pdg_kernel(const InstDev* __restrict__ in
         r[vo + oo[g]] = rr;
         dout[vo + oo[g]] = T(cc.s0) * dv[g] * rr;
       }
-    } else if (mode == kStep) {            // x += d; r -= S d; d' = rho d + sig Dinv r
+    } else if constexpr (MODE == kStep) {            // x += d; r -= S d; d' = rho d + sig Dinv r
       T dd[NG], xv[NG], rv[NG], dv[NG], Sd[NG];
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
@@ -236,17 +236,36 @@ __global__ __launch_bounds__(256) void pdg_diag_kernel(const InstDev* __restrict
   }
 }
 
+template <typename T, int D>
+static void launch_pdg_dim(dim3 g, int mode, hipStream_t s, const PDgSeg* segs, ChebCoef cc, const T* dqinv,
+                           const T* dinv, const T* b, T* x, T* r, const T* din, T* dout) {
+  switch (mode) {
+    case kResInitZero:
+      hipLaunchKernelGGL((pdg_kernel<T, D, kResInitZero>), g, dim3(kBlk), 0, s, segs, cc, dqinv, dinv, b, x, r, din,
+                         dout);
+      break;
+    case kResInit:
+      hipLaunchKernelGGL((pdg_kernel<T, D, kResInit>), g, dim3(kBlk), 0, s, segs, cc, dqinv, dinv, b, x, r, din, dout);
+      break;
+    case kStep:
+      hipLaunchKernelGGL((pdg_kernel<T, D, kStep>), g, dim3(kBlk), 0, s, segs, cc, dqinv, dinv, b, x, r, din, dout);
+      break;
+    default:
+      hipLaunchKernelGGL((pdg_kernel<T, D, kApplyDinv>), g, dim3(kBlk), 0, s, segs, cc, dqinv, dinv, b, x, r, din,
+                         dout);
+      break;
+  }
+}
+
 template <typename T>
 void launch_pdg(int dim, const InstDev* insts, const PDgSeg* segs, int nseg, int nj, long long maxnp, int mode,
                 ChebCoef cc, const T* dqinv, const T* dinv, const T* b, T* x, T* r, const T* din, T* dout,
                 hipStream_t s) {
+  (void)insts;   // the segments carry a copy of their instance descriptor
   const long long maxc = maxnp >> dim;      // one thread per cell
-  if (dim == 2)
-    hipLaunchKernelGGL((pdg_kernel<T, 2>), grid3(maxc, nseg, nj), dim3(kBlk), 0, s, insts, segs, mode, cc, dqinv, dinv,
-                       b, x, r, din, dout);
-  else
-    hipLaunchKernelGGL((pdg_kernel<T, 3>), grid3(maxc, nseg, nj), dim3(kBlk), 0, s, insts, segs, mode, cc, dqinv, dinv,
-                       b, x, r, din, dout);
+  const dim3 g = grid3(maxc, nseg, nj);
+  if (dim == 2) launch_pdg_dim<T, 2>(g, mode, s, segs, cc, dqinv, dinv, b, x, r, din, dout);
+  else launch_pdg_dim<T, 3>(g, mode, s, segs, cc, dqinv, dinv, b, x, r, din, dout);
 }
 template void launch_pdg<double>(int, const InstDev*, const PDgSeg*, int, int, long long, int, ChebCoef,
                                  const double*, const double*, const double*, double*, double*, const double*,

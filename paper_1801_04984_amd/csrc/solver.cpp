@@ -222,6 +222,7 @@ static void build_hierarchy(biot_problem_s* h, PrecData* P) {
     PDgSeg s;
     std::memset(&s, 0, sizeof(s));
     s.inst = k;
+    s.I = I;
     s.voff = I.x_off + I.off_p;
     s.vjstride = I.N;
     s.dqoff = I.state_off;
