@@ -317,8 +317,8 @@ __device__ __forceinline__ void pcell_eval(const PCellSeg& sg, const T* __restri
   diag = dg;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void pcell_kernel(const PCellSeg* __restrict__ segs, int mode, ChebCoef cc, const T* __restrict__ coef,
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void pcell_kernel(const PCellSeg* __restrict__ segs, ChebCoef cc, const T* __restrict__ coef,
                              const T* __restrict__ dinv, const T* __restrict__ b, T* __restrict__ x,
                              T* __restrict__ r, const T* __restrict__ din, T* __restrict__ dout) {
   const PCellSeg sg = segs[blockIdx.y];
@@ -330,19 +330,19 @@ __global__ __launch_bounds__(256) void pcell_kernel(const PCellSeg* __restrict__
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncl; c += gridDim.x * blockDim.x) {
     const T di = dinv[dof + c];
     // every load of a mode precedes its stores
-    if (mode == kResInitZero) {
+    if constexpr (MODE == kResInitZero) {
       const T rr = T(cc.bsign) * b[vo + c];
       x[vo + c] = 0;
       r[vo + c] = rr;
       dout[vo + c] = T(cc.s0) * di * rr;
-    } else if (mode == kResInit) {
+    } else if constexpr (MODE == kResInit) {
       const T bb = b[vo + c];
       T Sx, dg;
       pcell_eval<T>(sg, coef, x + vo, c, cm, Sx, dg);
       const T rr = T(cc.bsign) * bb - Sx;
       r[vo + c] = rr;
       dout[vo + c] = T(cc.s0) * di * rr;
-    } else if (mode == kStep) {
+    } else if constexpr (MODE == kStep) {
       const T dd = din[vo + c], xv = x[vo + c], rv = r[vo + c];
       T Sd, dg;
       pcell_eval<T>(sg, coef, din + vo, c, cm, Sd, dg);
@@ -371,8 +371,22 @@ __global__ __launch_bounds__(256) void pcell_diag_kernel(const PCellSeg* __restr
 template <typename T>
 void launch_pcell(const PCellSeg* segs, int nseg, int nj, long long maxc, int mode, ChebCoef cc, const T* coef,
                   const T* dinv, const T* b, T* x, T* r, const T* din, T* dout, hipStream_t s) {
-  hipLaunchKernelGGL((pcell_kernel<T>), grid3(maxc, nseg, nj), dim3(kBlk), 0, s, segs, mode, cc, coef, dinv, b, x, r,
-                     din, dout);
+  const dim3 g = grid3(maxc, nseg, nj);
+  switch (mode) {
+    case kResInitZero:
+      hipLaunchKernelGGL((pcell_kernel<T, kResInitZero>), g, dim3(kBlk), 0, s, segs, cc, coef, dinv, b, x, r, din,
+                         dout);
+      break;
+    case kResInit:
+      hipLaunchKernelGGL((pcell_kernel<T, kResInit>), g, dim3(kBlk), 0, s, segs, cc, coef, dinv, b, x, r, din, dout);
+      break;
+    case kStep:
+      hipLaunchKernelGGL((pcell_kernel<T, kStep>), g, dim3(kBlk), 0, s, segs, cc, coef, dinv, b, x, r, din, dout);
+      break;
+    default:
+      hipLaunchKernelGGL((pcell_kernel<T, kApplyDinv>), g, dim3(kBlk), 0, s, segs, cc, coef, dinv, b, x, r, din, dout);
+      break;
+  }
 }
 template void launch_pcell<double>(const PCellSeg*, int, int, long long, int, ChebCoef, const double*, const double*,
                                    const double*, double*, double*, const double*, double*, hipStream_t);
@@ -478,9 +492,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void p_restrict_dg_kernel(const InstDev* __restrict__ insts, const PDgSeg* __restrict__ fine,
                                      const PCellSeg* __restrict__ coarse, const T* __restrict__ r,
                                      T* __restrict__ b) {
-  const PDgSeg fs = fine[blockIdx.y];
+  const PDgSeg& fs = fine[blockIdx.y];
   const PCellSeg cs = coarse[blockIdx.y];
-  const InstDev& I = insts[fs.inst];
+  const InstDev& I = fs.I;
   const int j = blockIdx.z;
   const T* R = r + fs.voff + j * fs.vjstride;
   T* Bc = b + cs.voff + j * cs.vjstride;
@@ -503,9 +517,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void p_prolong_dg_kernel(const InstDev* __restrict__ insts, const PDgSeg* __restrict__ fine,
                                     const PCellSeg* __restrict__ coarse, double w, const T* __restrict__ e,
                                     T* __restrict__ x) {
-  const PDgSeg fs = fine[blockIdx.y];
+  const PDgSeg& fs = fine[blockIdx.y];
   const PCellSeg cs = coarse[blockIdx.y];
-  const InstDev& I = insts[fs.inst];
+  const InstDev& I = fs.I;
   const int j = blockIdx.z;
   const long long np = (long long)I.sp[0] * I.sp[1] * I.sp[2];
   T* X = x + fs.voff + j * fs.vjstride;

@@ -242,8 +242,8 @@ template void time_transform<float>(const InstDev*, int, long long, int, const M
 // ---- Chebyshev update on level segments -------------------------------------------
 // x += d; r -= y; d = rho d + sig Dinv r      (y = A d computed by the caller)
 // first step (init != 0): r = b - y0 is not touched; d = sig Dinv r; x untouched.
-template <typename T>
-__global__ __launch_bounds__(256) void cheb_kernel(const LSeg* __restrict__ segs, int mode, double rho, double sig, T* __restrict__ x,
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void cheb_kernel(const LSeg* __restrict__ segs, double rho, double sig, T* __restrict__ x,
                             T* __restrict__ r, T* __restrict__ d, const T* __restrict__ y,
                             const T* __restrict__ dinv, const T* __restrict__ b) {
   const LSeg sg = segs[blockIdx.y];
@@ -252,9 +252,9 @@ __global__ __launch_bounds__(256) void cheb_kernel(const LSeg* __restrict__ segs
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < sg.len;
        i += (long long)gridDim.x * blockDim.x) {
     const T di = dinv[doff + i];
-    if (mode == 0) {         // init: d = sig Dinv r
+    if constexpr (MODE == 0) {         // init: d = sig Dinv r
       d[off + i] = T(sig) * di * r[off + i];
-    } else if (mode == 2) {  // init from x = 0: x = 0, r = b, d = sig Dinv b
+    } else if constexpr (MODE == 2) {  // init from x = 0: x = 0, r = b, d = sig Dinv b
       const T bb = b[off + i];
       x[off + i] = T(0);
       r[off + i] = bb;
@@ -284,8 +284,13 @@ static dim3 lgrid(long long maxlen, int nseg, int nj) {
 template <typename T>
 void cheb_update(const LSeg* segs, int nseg, int nj, long long maxlen, int mode, double rho, double sig, T* x, T* r,
                  T* d, const T* y, const T* dinv, const T* b, hipStream_t s) {
-  hipLaunchKernelGGL((cheb_kernel<T>), lgrid(maxlen, nseg, nj), dim3(kBlk), 0, s, segs, mode, rho, sig, x, r, d, y,
-                     dinv, b);
+  const dim3 g = lgrid(maxlen, nseg, nj);
+  if (mode == 0)
+    hipLaunchKernelGGL((cheb_kernel<T, 0>), g, dim3(kBlk), 0, s, segs, rho, sig, x, r, d, y, dinv, b);
+  else if (mode == 2)
+    hipLaunchKernelGGL((cheb_kernel<T, 2>), g, dim3(kBlk), 0, s, segs, rho, sig, x, r, d, y, dinv, b);
+  else
+    hipLaunchKernelGGL((cheb_kernel<T, 1>), g, dim3(kBlk), 0, s, segs, rho, sig, x, r, d, y, dinv, b);
 }
 template <typename T>
 void seg_add(const LSeg* segs, int nseg, int nj, long long maxlen, const T* d, T* x, double a, hipStream_t s) {
