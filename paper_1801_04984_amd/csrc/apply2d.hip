@@ -18,7 +18,8 @@
 //
 // Work decomposition: one block = one tile of (TS-1)x(TS-1) owned cells plus a
 // one-cell halo on the low sides (TS x TS threads, one cell each; TS = 16 or
-// 8, chosen per handle by the tile autotuner: both give identical results).
+// 8, with the time levels in a loop or, for 8, in parallel thread layers;
+// chosen per handle by the tile autotuner: all give identical results).
 // Every cell computes its element rows (u, then flux), stages them in LDS,
 // and each owned cell sums its own nodes - the lower-left 2x2 node block of
 // the cell, plus the top/right boundary nodes of the last cells - from the
