@@ -24,3 +24,48 @@ def _run(src, tmp_path):
 
 def test_xcd_tile_order_is_a_contiguous_permutation(tmp_path):
     _run("xcd_order_check.cpp", tmp_path)
+
+
+def test_temporal_constants_match_oracle(tmp_path):
+    """The library's dG(r) constants (temporal.cpp, host code) against the
+    oracle's: Radau nodes and weights, T = W^-1 D, g = W^-1 phi(0), and the
+    real block eigenform Q^-1 T Q (2x2 blocks [[alpha, beta], [-beta, alpha]]
+    for complex pairs, alpha on the diagonal for real eigenvalues)."""
+    import json
+
+    import numpy as np
+
+    from oracle import temporal
+    gxx = shutil.which("g++")
+    if not gxx:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path / "dump")
+    r = subprocess.run([gxx, "-O1", "-std=c++17", "-I", CSRC, os.path.join(ROOT, "tests", "host", "temporal_dump.cpp"),
+                        os.path.join(CSRC, "temporal.cpp"), "-o", exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=60).stdout.strip().splitlines()
+    for line in out:
+        c = json.loads(line)
+        rr = c["r"]
+        L = rr + 1
+        s, w, D, T, g = temporal.dg_matrices(rr)
+        np.testing.assert_allclose(c["s"][:L], s, rtol=0, atol=1e-14)
+        np.testing.assert_allclose(c["w"][:L], w, rtol=0, atol=1e-14)
+        Tl = np.array(c["T"]).reshape(4, 4)[:L, :L]
+        np.testing.assert_allclose(Tl, T, rtol=1e-12, atol=1e-12 * np.abs(T).max())
+        np.testing.assert_allclose(c["g"][:L], g, rtol=1e-12, atol=1e-12 * np.abs(g).max())
+        Q = np.array(c["Q"]).reshape(4, 4)[:L, :L]
+        Qi = np.array(c["Qi"]).reshape(4, 4)[:L, :L]
+        np.testing.assert_allclose(Qi @ Q, np.eye(L), atol=1e-11)
+        Lam = Qi @ Tl @ Q
+        alpha = np.array(c["alpha"][:L], dtype=float)
+        beta = np.array(c["beta"][:L], dtype=float)
+        expect = np.diag(alpha)
+        for i in range(L):
+            if beta[i] > 0:   # columns i, i+1 form a complex pair alpha_i +- i beta_i
+                expect[i, i + 1], expect[i + 1, i] = beta[i], -beta[i]
+        np.testing.assert_allclose(Lam, expect, atol=1e-10 * np.abs(Tl).max())
+        # the eigenvalues of T are the alpha +- i beta the block form reports
+        ev = np.sort_complex(np.linalg.eigvals(T))
+        got = np.sort_complex(np.linalg.eigvals(expect))
+        np.testing.assert_allclose(got, ev, atol=1e-10 * np.abs(ev).max())
