@@ -69,3 +69,35 @@ def test_temporal_constants_match_oracle(tmp_path):
         ev = np.sort_complex(np.linalg.eigvals(T))
         got = np.sort_complex(np.linalg.eigvals(expect))
         np.testing.assert_allclose(got, ev, atol=1e-10 * np.abs(ev).max())
+
+
+def test_element_matrices_match_oracle(tmp_path):
+    """The library's element matrices (element.cpp, host code; tau = 1):
+    elasticity a(u, v) and the coupling (psi_g, d_c phi) on a 2D and a 3D box
+    cell with unequal edges, against the oracle's quadrature of its own basis
+    (both ordered component-major, nodes x fastest)."""
+    import json
+
+    import numpy as np
+
+    from oracle import fe
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path / "edump")
+    r = subprocess.run([hipcc, "-O1", "-std=c++17", "-x", "hip", "-I", CSRC,
+                        os.path.join(ROOT, "tests", "host", "element_dump.cpp"), os.path.join(CSRC, "element.cpp"),
+                        "--offload-arch=gfx950", "-o", exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=60).stdout.strip().splitlines()
+    assert len(out) == 2
+    h = [0.3, 0.7, 1.1]
+    for line in out:
+        c = json.loads(line)
+        d = c["d"]
+        em = fe.element_matrices(d, np.array(h[:d]), fe.Material(1.3, 0.7, 0.8, 10.0, 1.0))
+        nu, npd = len(em["iu"]), len(em["ip"])
+        A = np.array(c["A"]).reshape(nu, nu)
+        E = np.array(c["E"]).reshape(nu, npd)
+        np.testing.assert_allclose(A, em["A"], rtol=0, atol=1e-12 * np.abs(em["A"]).max())
+        np.testing.assert_allclose(E, em["E"], rtol=0, atol=1e-12 * np.abs(em["E"]).max())
