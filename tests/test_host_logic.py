@@ -101,3 +101,31 @@ def test_element_matrices_match_oracle(tmp_path):
         E = np.array(c["E"]).reshape(nu, npd)
         np.testing.assert_allclose(A, em["A"], rtol=0, atol=1e-12 * np.abs(em["A"]).max())
         np.testing.assert_allclose(E, em["E"], rtol=0, atol=1e-12 * np.abs(em["E"]).max())
+
+
+def test_binding_structs_match_header_layout(tmp_path):
+    """Every struct of include/biotst.h, compiled with the host C compiler,
+    has the size and field offsets of its ctypes mirror in the binding (the
+    binding renames the descriptor's `lambda`, a Python keyword, to `lam`)."""
+    import ctypes
+    import json
+
+    from paper_1801_04984_amd import native
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    exe = str(tmp_path / "layout")
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-I", os.path.join(ROOT, "include"),
+                        os.path.join(ROOT, "tests", "host", "abi_layout.c"), "-o", exe],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    rows = [json.loads(l) for l in subprocess.run([exe], capture_output=True, text=True,
+                                                  timeout=60).stdout.splitlines()]
+    mirrors = {"biot_problem_desc": native.Desc, "biot_solve_opts": native.SolveOpts,
+               "biot_solve_info": native.SolveInfo, "biot_tuning": native.Tuning}
+    assert sorted(r["name"] for r in rows) == sorted(mirrors)
+    for row in rows:
+        S = mirrors[row["name"]]
+        assert ctypes.sizeof(S) == row["size"], row["name"]
+        py = {("lambda" if n == "lam" else n): getattr(S, n).offset for n, _ in S._fields_}
+        assert py == row["fields"], row["name"]
