@@ -1,0 +1,100 @@
+"""Convergence rates of the oracle on smooth manufactured solutions.
+
+Pins the oracle's time and space discretisations by their rates, which no
+polynomial-exactness check can show:
+
+- time: with fields exact in space (the spatial part lies in the discrete
+  spaces) and a smooth time factor, the slab-end error of dG(r) on right
+  Gauss-Radau points is that of the (r+1)-stage Radau IIA method, order
+  2r+1 (section "Discretisation in Time"; dG(r) with Radau quadrature is
+  Radau IIA collocation, and u, q are index-1 algebraic components).  The
+  test runs in the non-stiff regime (large viscosity); a wrong g or T, or a
+  load sampled at the wrong instants, loses the superconvergence.
+- space: with fields exact in time (linear, dG(1)) and smooth in space, the
+  nodal error against the interpolant falls at least like h^3 for the Q2
+  displacement and at the Gauss points of the DG-Q1 pressure
+  (superconvergence of the mixed RT1 pair), and at least like h^2 for the
+  RT1 flux (section "Discretisation in Space").
+
+The smooth factors are truncated Taylor series of exponentials (degree 18,
+so the truncation is far below the errors measured).
+"""
+from math import factorial
+
+import numpy as np
+import pytest
+from numpy.polynomial import Polynomial as Pn
+
+from oracle import fe, slab
+from tests.polyfields import Manufactured, SepPoly
+
+X = Pn([0.0, 1.0])
+
+
+def exp_series(a, deg=18):
+    """exp(a x) as a polynomial (Taylor series to degree deg)."""
+    return Pn([a ** k / factorial(k) for k in range(deg + 1)])
+
+
+def _errors(ms, n, r, tau, nslabs):
+    """Relative max nodal error of (u, q, p) at the end of the march."""
+    mesh = fe.Mesh(n, (1.0, 1.0, 1.0))
+    mat = fe.Material(ms.lam, ms.mu, ms.b, ms.M, ms.eta)
+    theta = np.random.default_rng(7).normal(0.0, 1.0, mesh.ncells)
+
+    def load(t):
+        return fe.load_vector(mesh, mat, theta, t, fu=ms.fu, fq=ms.fq, fp=ms.fp,
+                              traction=ms.traction, p_drained=ms.p_drained)
+
+    prob = slab.SlabProblem(mesh, mat, r, tau, theta, load)
+    Xs = prob.march(nslabs, fe.interpolate(mesh, ms.u_fn, ms.q_fn, ms.p_fn, 0.0))
+    ex = fe.interpolate(mesh, ms.u_fn, ms.q_fn, ms.p_fn, nslabs * tau)
+    e = prob.level(Xs[-1], r) - ex
+    parts = (slice(0, mesh.off_q[0]), slice(mesh.off_q[0], mesh.off_p), slice(mesh.off_p, mesh.N))
+    return np.array([np.abs(e[s]).max() / np.abs(ex[s]).max() for s in parts])
+
+
+def _time_fields(eta):
+    """Spatial parts in (Q2, RT1, DG-Q1) with the boundary structure of the
+    box (u = 0 at the bottom, u.n = q.n = 0 on the sides and the bottom);
+    time factor exp(-2 t)."""
+    T = SepPoly.term
+    ft = exp_series(-2.0)
+    u = [T(2, 1.0, [[0, 1, -1], [0, 1]], ft), T(2, 1.0, [[1, 1], [0, 1, 1]], ft)]
+    q = [T(2, 1.0, [[0, 1, -1], [1, 1]], ft), T(2, 1.0, [[1, 1], [0, 2, -1]], ft)]
+    p = T(2, 1.0, [[1, 2], [2, -1]], ft)
+    return Manufactured(2, u, q, p, 1.3, 0.7, 0.8, 7.0, eta)
+
+
+def _space_fields():
+    """Smooth non-polynomial fields with the same boundary structure, linear in t."""
+    T = SepPoly.term
+    tl = [1.0, 0.5]
+    u = [T(2, 1.0, [X * (1 - X) * exp_series(1.5), X * exp_series(-1.2)], tl),
+         T(2, 1.0, [exp_series(-0.8), X * exp_series(0.7)], tl)]
+    q = [T(2, 1.0, [X * (1 - X) * exp_series(-0.8), exp_series(0.9)], tl),
+         T(2, 1.0, [exp_series(-1.1), X * exp_series(0.6)], tl)]
+    p = T(2, 1.0, [exp_series(1.3), exp_series(-0.9)], tl)
+    return Manufactured(2, u, q, p, 1.3, 0.7, 0.8, 7.0, 1.5)
+
+
+@pytest.mark.parametrize("r", [0, 1, 2])
+def test_dg_radau_slab_end_order_2r_plus_1(r):
+    ms = _time_fields(eta=1000.0)
+    errs = [_errors(ms, (2, 3), r, 0.4 / 2 ** k, 2 ** k).max() for k in (1, 2, 3)]
+    rate = np.log2(errs[-2] / errs[-1])
+    assert abs(rate - (2 * r + 1)) < 0.1, (errs, rate)
+
+
+def test_dg_error_falls_with_r_at_fixed_tau():
+    ms = _time_fields(eta=1000.0)
+    errs = [_errors(ms, (2, 3), r, 0.05, 8).max() for r in (0, 1, 2)]
+    assert errs[0] > 1e3 * errs[1] > 1e6 * errs[2], errs
+
+
+def test_space_rates_on_smooth_fields():
+    ms = _space_fields()
+    e8 = _errors(ms, (8, 8), 1, 0.1, 1)
+    e16 = _errors(ms, (16, 16), 1, 0.1, 1)
+    rates = np.log2(e8 / e16)
+    assert rates[0] > 2.6 and rates[2] > 2.6 and rates[1] > 2.0, rates
