@@ -54,16 +54,23 @@ def _errors(ms, n, r, tau, nslabs):
     return np.array([np.abs(e[s]).max() / np.abs(ex[s]).max() for s in parts])
 
 
-def _time_fields(eta):
+def _time_fields(d, eta):
     """Spatial parts in (Q2, RT1, DG-Q1) with the boundary structure of the
     box (u = 0 at the bottom, u.n = q.n = 0 on the sides and the bottom);
     time factor exp(-2 t)."""
     T = SepPoly.term
     ft = exp_series(-2.0)
-    u = [T(2, 1.0, [[0, 1, -1], [0, 1]], ft), T(2, 1.0, [[1, 1], [0, 1, 1]], ft)]
-    q = [T(2, 1.0, [[0, 1, -1], [1, 1]], ft), T(2, 1.0, [[1, 1], [0, 2, -1]], ft)]
-    p = T(2, 1.0, [[1, 2], [2, -1]], ft)
-    return Manufactured(2, u, q, p, 1.3, 0.7, 0.8, 7.0, eta)
+    if d == 2:
+        u = [T(2, 1.0, [[0, 1, -1], [0, 1]], ft), T(2, 1.0, [[1, 1], [0, 1, 1]], ft)]
+        q = [T(2, 1.0, [[0, 1, -1], [1, 1]], ft), T(2, 1.0, [[1, 1], [0, 2, -1]], ft)]
+        p = T(2, 1.0, [[1, 2], [2, -1]], ft)
+        return Manufactured(2, u, q, p, 1.3, 0.7, 0.8, 7.0, eta)
+    u = [T(3, 1.0, [[0, 1, -1], [1, 1], [0, 1]], ft), T(3, 1.0, [[1, 1], [0, 1, -1], [0, 1]], ft),
+         T(3, 1.0, [[1, 1], [1, 0.5], [0, 1, 1]], ft)]
+    q = [T(3, 1.0, [[0, 1, -1], [1, 1], [1, 1]], ft), T(3, 1.0, [[1, 1], [0, 1, -1], [2, -1]], ft),
+         T(3, 1.0, [[1, 1], [1, 1], [0, 2, -1]], ft)]
+    p = T(3, 1.0, [[1, 1], [1, 2], [2, -1]], ft)
+    return Manufactured(3, u, q, p, 2.0, 1.0, 0.9, 5.0, eta)
 
 
 def _space_fields():
@@ -78,16 +85,17 @@ def _space_fields():
     return Manufactured(2, u, q, p, 1.3, 0.7, 0.8, 7.0, 1.5)
 
 
+@pytest.mark.parametrize("d,n", [(2, (2, 3)), (3, (2, 2, 2))])
 @pytest.mark.parametrize("r", [0, 1, 2])
-def test_dg_radau_slab_end_order_2r_plus_1(r):
-    ms = _time_fields(eta=1000.0)
-    errs = [_errors(ms, (2, 3), r, 0.4 / 2 ** k, 2 ** k).max() for k in (1, 2, 3)]
+def test_dg_radau_slab_end_order_2r_plus_1(d, n, r):
+    ms = _time_fields(d, eta=1000.0)
+    errs = [_errors(ms, n, r, 0.4 / 2 ** k, 2 ** k).max() for k in (1, 2, 3)]
     rate = np.log2(errs[-2] / errs[-1])
     assert abs(rate - (2 * r + 1)) < 0.1, (errs, rate)
 
 
 def test_dg_error_falls_with_r_at_fixed_tau():
-    ms = _time_fields(eta=1000.0)
+    ms = _time_fields(2, eta=1000.0)
     errs = [_errors(ms, (2, 3), r, 0.05, 8).max() for r in (0, 1, 2)]
     assert errs[0] > 1e3 * errs[1] > 1e6 * errs[2], errs
 
