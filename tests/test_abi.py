@@ -119,3 +119,46 @@ def test_tuning_calls_reject_null():
     assert L.biot_get_tuning(None, ctypes.byref(t)) == 1
     assert L.biot_set_tuning(None, ctypes.byref(t)) == 1
     assert L.biot_autotune(None, 5, ctypes.byref(t), None) == 1
+
+
+def _header_signatures():
+    src = open(os.path.join(ROOT, "include", "biotst.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = {}
+    for m in re.finditer(r"^\s*(biot_status|const char\*)\s+(\w+)\s*\(([^)]*)\)\s*;", src, flags=re.M):
+        params = [" ".join(p.split()) for p in m.group(3).split(",")]
+        out[m.group(2)] = (m.group(1), [] if params == ["void"] else params)
+    return out
+
+
+def test_binding_argtypes_match_header_signatures():
+    """Every function of the binding declares the header's arity, and each
+    argument's ctypes kind matches the C type: scalars by width, struct
+    pointers to the struct's mirror, other pointers as pointers."""
+    from paper_1801_04984_amd import native
+    L = lib()
+    structs = {"biot_problem_desc": native.Desc, "biot_solve_opts": native.SolveOpts,
+               "biot_solve_info": native.SolveInfo, "biot_tuning": native.Tuning}
+    scalars = {"int32_t": ctypes.c_int32, "double": ctypes.c_double, "size_t": ctypes.c_size_t}
+    sigs = _header_signatures()
+    assert sorted(sigs) == sorted(native.EXPORTS)
+    for name, (ret, params) in sigs.items():
+        fn = getattr(L, name)
+        assert fn.restype is (ctypes.c_char_p if ret == "const char*" else ctypes.c_int32), name
+        if not params:
+            continue
+        assert fn.argtypes is not None and len(fn.argtypes) == len(params), name
+        for p, t in zip(params, fn.argtypes):
+            ctype = p.rsplit(" ", 1)[0].replace("const ", "").strip()
+            where = f"{name}: {p}"
+            if ctype == "biot_problem" or "*" in ctype:
+                assert t is ctypes.c_void_p or issubclass(t, ctypes._Pointer), where
+                base = ctype.rstrip("* ").strip()
+                if base in structs:
+                    assert t._type_ is structs[base], where
+                elif base in ("int64_t", "size_t") and issubclass(t, ctypes._Pointer):
+                    assert t._type_ is {"int64_t": ctypes.c_int64, "size_t": ctypes.c_size_t}[base], where
+                elif base == "double" and ctype.count("*") == 1 and issubclass(t, ctypes._Pointer):
+                    assert t._type_ is ctypes.c_double, where
+            else:
+                assert t is scalars[ctype], where
