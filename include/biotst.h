@@ -11,7 +11,7 @@
  *   - section "Preconditioning technology": GMRES with a fixed-stress,
  *     level-blockwise (L_j) preconditioner.
  *
- * Discretisation contract (shared with any independent checker):
+ * Discretisation contract (shared with the FP64 CPU oracle in oracle/):
  *   Mesh: box [0,L_0] x .. x [0,L_{d-1}], n_e uniform cells per axis, cells
  *   lexicographic x fastest.  1D bases: closed = quadratic Lagrange on
  *   {0, 1/2, 1}; open = linear Lagrange on the two Gauss points.
