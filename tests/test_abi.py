@@ -162,3 +162,31 @@ def test_binding_argtypes_match_header_signatures():
                     assert t._type_ is ctypes.c_double, where
             else:
                 assert t is scalars[ctype], where
+
+
+def test_product_path_fails_loudly_without_the_library(monkeypatch):
+    """With the shared library absent the binding raises before any device
+    work; there is no fallback path."""
+    from paper_1801_04984_amd import native
+    monkeypatch.setattr(native, "_lib", None)
+    monkeypatch.setattr(native.load_library, "__defaults__", (os.path.join(ROOT, "no_such_dir", "libbiotst.so"),))
+    wl = W.Workload("t", 2, (4, 4), 1, 0.1, 1)
+    with pytest.raises(OSError, match="missing"):
+        native.BiotSlab([wl], [np.zeros(16)])
+
+
+def test_product_package_never_imports_the_oracle():
+    """The package and the benchmark's GPU legs do not reach the oracle: only
+    tests, the smoke check and the benchmark's CPU baseline may."""
+    pkg = os.path.join(ROOT, "paper_1801_04984_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle\b", src, flags=re.M), f
+    bench = open(os.path.join(ROOT, "bench.py")).read()
+    uses = [m.start() for m in re.finditer(r"from oracle import|import oracle", bench)]
+    assert uses, "the CPU baseline leg times the oracle"
+    for u in uses:
+        fn = bench.rfind("\ndef ", 0, u)
+        assert bench[fn:].startswith("\ndef cpu_baseline("), bench[fn:fn + 40]
