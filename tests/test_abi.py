@@ -190,3 +190,15 @@ def test_product_package_never_imports_the_oracle():
     for u in uses:
         fn = bench.rfind("\ndef ", 0, u)
         assert bench[fn:].startswith("\ndef cpu_baseline("), bench[fn:fn + 40]
+
+
+def test_oracle_and_generators_never_reach_the_hip_package():
+    """The oracle and the shared input generators import nothing of the HIP
+    package and load no part of its library."""
+    for sub in ("oracle", "workloads"):
+        for dirpath, _, files in os.walk(os.path.join(ROOT, sub)):
+            for f in files:
+                if f.endswith(".py"):
+                    src = open(os.path.join(dirpath, f)).read()
+                    for word in ("paper_1801_04984_amd", "libbiotst", "csrc", "ctypes"):
+                        assert word not in src, (f, word)
