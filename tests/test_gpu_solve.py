@@ -320,3 +320,10 @@ def test_full_length_restart_cycle():
     err = field_rel(prob, x.cpu().numpy(), ref)
     assert max(err.values()) < TOL, err
     h.close()
+
+
+def test_flux_line_solve_full_wavefront():
+    """Lines of 511 cells, the longest the wavefront line solve takes: 512
+    cell-end equations, eight per lane, every slot of the reduction in use
+    (the cross lines of 2 cells run in the same launch)."""
+    test_flux_block_variants(2, (511, 2), (5.11, 0.02))
