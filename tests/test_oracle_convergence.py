@@ -86,12 +86,14 @@ def _space_fields():
 
 
 @pytest.mark.parametrize("d,n", [(2, (2, 3)), (3, (2, 2, 2))])
-@pytest.mark.parametrize("r", [0, 1, 2])
+@pytest.mark.parametrize("r", [0, 1, 2, 3])
 def test_dg_radau_slab_end_order_2r_plus_1(d, n, r):
     ms = _time_fields(d, eta=1000.0)
-    errs = [_errors(ms, n, r, 0.4 / 2 ** k, 2 ** k).max() for k in (1, 2, 3)]
+    # dG(3) (order 7) reaches the rounding floor below tau = 0.1: larger slabs
+    t_end, ks = (0.8, (0, 1, 2)) if r == 3 else (0.4, (1, 2, 3))
+    errs = [_errors(ms, n, r, t_end / 2 ** k, 2 ** k).max() for k in ks]
     rate = np.log2(errs[-2] / errs[-1])
-    assert abs(rate - (2 * r + 1)) < 0.1, (errs, rate)
+    assert abs(rate - (2 * r + 1)) < 0.15, (errs, rate)
 
 
 def test_dg_error_falls_with_r_at_fixed_tau():
