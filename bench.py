@@ -183,15 +183,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", help="c1..c4; with --apply-only also c5 (64-instance batch)")
+    ap.add_argument("--workload", default="c2",
+                    help="c1 2D Terzaghi 8x8 dG(0); c2 2D 128x128 dG(1) heterogeneous; c3 3D 32^3 dG(1); "
+                         "c4 3D 48^3 dG(2); with --apply-only also c5 (64 uneven 2D instances)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the large-workload apply and batched objects")
     ap.add_argument("--apply-only", action="store_true", help="only time the operator apply (profiling target)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
-                                   "not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "biotst runs on one GPU only: sharding across GPUs is not implemented",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
