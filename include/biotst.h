@@ -83,7 +83,8 @@ typedef struct {
                          * one instance's slab must hold < 2^31 unknowns             */
   double length[3];     /* box edge lengths                                          */
   int32_t r;            /* dG(r) order, 0..3; all instances of a batch share it      */
-  double tau;           /* slab length > 0                                           */
+  double tau;           /* slab length > 0; all instances of a batch share it (the   *
+                         * batch is marched on one clock), else BIOT_ERR_ARG         */
   double lambda, mu;    /* Lame parameters: mu > 0, lambda + 2 mu / dim > 0          */
   double b;             /* Biot coefficient in (0, 1)                                */
   double M;             /* Biot modulus > 0                                          */

@@ -429,7 +429,9 @@ def interpolate(mesh: Mesh, u, q, p, t):
 def pressure_point_matrix(mesh: Mesh, pts):
     """Sparse (npts, N) matrix evaluating the DG-Q1 pressure at points.
 
-    A point on a cell face belongs to the lower-index cell (floor, clipped).
+    The containing cell is floor(x / h) per axis, clipped to the mesh: a point
+    on an interior face belongs to the cell above it along that axis (the cell
+    whose lower face it lies on), a point on the upper boundary to the last cell.
     """
     d = mesh.d
     h = np.array(mesh.h)

@@ -35,6 +35,8 @@ class SlabProblem:
     theta: np.ndarray
     # load(t) -> F(t) of one spatial level; default: top traction sigma(t)
     load: Optional[Callable] = None
+    # fill-reducing ordering of the sparse LU: "nd" or "colamd" (see factor)
+    ordering: str = "nd"
 
     def __post_init__(self):
         self.s, self.w, self.D, self.T, self.g = temporal.dg_matrices(self.r)
@@ -45,6 +47,7 @@ class SlabProblem:
         self.N = self.mesh.N
         self._A = None
         self._lu = None
+        self._perm = None
 
     # -- the slab operator ------------------------------------------------------
     def slab_matrix(self):
@@ -62,22 +65,68 @@ class SlabProblem:
         A = self.slab_matrix()
         return (A.T @ x) if transpose else (A @ x)
 
+    def slab_ordering(self):
+        """Fill-reducing symmetric permutation of the slab unknowns: geometric
+        nested dissection of the spatial coupling graph (K_s and M_t), every
+        spatial DoF keeping its r+1 levels together."""
+        G = (abs(self.Ks) + abs(self.Mt)).tocsr()
+        G = (G + G.T).tocsr()
+        ps = nested_dissection(G, fe.dof_coordinates(self.mesh))
+        return (np.arange(self.L)[None, :] * self.N + ps[:, None]).reshape(-1)
+
     def factor(self):
+        """Sparse LU of the slab matrix (SuperLU).  ordering "nd": nested
+        dissection (slab_ordering) as a symmetric permutation, diagonal pivots
+        preferred; "colamd": SuperLU's column ordering with partial pivoting.
+        Both factor the same matrix: their spread is the oracle's own floor."""
         if self._lu is None:
-            A = self.slab_matrix().tocsc()
-            self._lu = spla.splu(A, permc_spec="COLAMD",
-                                 options=dict(Equil=True, IterRefine="DOUBLE"))
+            A = self.slab_matrix()
+            if self.ordering == "nd":
+                perm = self.slab_ordering()
+                Ap = A[perm][:, perm].tocsc()
+                lu = spla.splu(Ap, permc_spec="NATURAL", diag_pivot_thresh=0.0,
+                               options=dict(Equil=True, IterRefine="DOUBLE", SymmetricMode=True))
+            elif self.ordering == "colamd":
+                perm = None
+                lu = spla.splu(A.tocsc(), permc_spec="COLAMD",
+                               options=dict(Equil=True, IterRefine="DOUBLE"))
+            else:
+                raise ValueError(f"unknown ordering {self.ordering!r}")
+            self._lu, self._perm = lu, perm
         return self._lu
 
-    def solve(self, rhs, transpose=False, refine=2):
+    def _lu_solve(self, b, trans):
         lu = self.factor()
+        if self._perm is None:
+            return lu.solve(b, trans=trans)
+        # A = P^T A_p P with A_p = A[perm][:, perm]; the same holds for A^T
+        y = lu.solve(b[self._perm], trans=trans)
+        x = np.empty_like(y)
+        x[self._perm] = y
+        return x
+
+    def solve(self, rhs, transpose=False, refine=2):
         A = self.slab_matrix()
         trans = "T" if transpose else "N"
-        x = lu.solve(rhs, trans=trans)
+        x = self._lu_solve(rhs, trans)
         for _ in range(refine):
             res = rhs - (A.T @ x if transpose else A @ x)
-            x = x + lu.solve(res, trans=trans)
+            x = x + self._lu_solve(res, trans)
+        res = rhs - (A.T @ x if transpose else A @ x)
+        nb = np.linalg.norm(rhs)
+        if nb > 0 and not np.linalg.norm(res) <= 1e-10 * nb:
+            raise RuntimeError(f"oracle LU residual {np.linalg.norm(res) / nb:.2e} above 1e-10")
         return x
+
+    def condition_estimate(self):
+        """1-norm condition estimate ||A||_1 ||A^-1||_1 (Hager-Higham block
+        estimator on the LU factors)."""
+        A = self.slab_matrix()
+        n = A.shape[0]
+        inv = spla.LinearOperator((n, n), matvec=lambda v: self._lu_solve(np.asarray(v, float).ravel(), "N"),
+                                  rmatvec=lambda v: self._lu_solve(np.asarray(v, float).ravel(), "T"),
+                                  dtype=float)
+        return spla.onenormest(A) * spla.onenormest(inv)
 
     # -- right-hand side ----------------------------------------------------------
     def rhs(self, t_start, x_prev_end):
@@ -104,6 +153,39 @@ class SlabProblem:
 
     def level(self, X, i):
         return X[i * self.N:(i + 1) * self.N]
+
+
+def nested_dissection(G, X, leaf=64):
+    """Geometric nested dissection of a graph with vertex coordinates.
+
+    G: symmetric sparse adjacency (csr); X: (n, d) coordinates.  A vertex set
+    larger than `leaf` is split at the median of its widest coordinate; the
+    vertices of the lower half with a neighbour in the upper half form the
+    separator.  The order is: lower half (recursively), upper half
+    (recursively), separator; so no vertex of one half is coupled to the
+    other half before the separator is eliminated.  Returns a permutation.
+    """
+    G = sp.csr_matrix(G)
+    n = G.shape[0]
+
+    def split(idx):
+        if len(idx) <= leaf:
+            return [idx]
+        pts = X[idx]
+        axis = int(np.argmax(pts.max(0) - pts.min(0)))
+        cut = np.median(pts[:, axis])
+        low = pts[:, axis] < cut
+        if low.all() or not low.any():
+            return [idx]
+        upper = np.zeros(n)
+        upper[idx[~low]] = 1.0
+        lo = idx[low]
+        touches = (G[lo] @ upper) > 0
+        return split(lo[~touches]) + split(idx[~low]) + [lo[touches]]
+
+    perm = np.concatenate(split(np.arange(n)))
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    return perm
 
 
 def traction_load(mesh: fe.Mesh, mat: fe.Material, theta, sigma_of_t):

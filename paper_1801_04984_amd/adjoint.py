@@ -45,6 +45,9 @@ class PressureMisfit(torch.autograd.Function):
         obs = torch.as_tensor(p_obs, dtype=torch.float64, device=dev).reshape(-1)
         J = slab.misfit(nslabs, ends, sensors, obs)
         ctx.slab, ctx.nslabs, ctx.sensors, ctx.opts = slab, nslabs, sensors, opts
+        # the handle is shared: another forward (a line search, a finite-difference
+        # probe) may set a different field before this backward runs
+        ctx.log_k_parts = [p.copy() for p in parts]
         ctx.save_for_backward(chk, obs)
         return torch.tensor(J, dtype=torch.float64, device=log_k.device)
 
@@ -52,6 +55,7 @@ class PressureMisfit(torch.autograd.Function):
     def backward(ctx, gJ):
         chk, obs = ctx.saved_tensors
         slab = ctx.slab
+        slab.set_log_k(ctx.log_k_parts)
         J, grad, st = slab.adjoint(ctx.nslabs, 0.0, chk, ctx.sensors, obs, **ctx.opts)
         if st != 0:
             raise RuntimeError("adjoint sweep failed")

@@ -172,6 +172,8 @@ static void check_batch(const biot_problem_desc* descs, int count) {
   for (int k = 1; k < count; ++k) {
     if (descs[k].dim != descs[0].dim) arg_fail("all instances of a batch must share dim");
     if (descs[k].r != descs[0].r) arg_fail("all instances of a batch must share r");
+    // step() and adjoint_sweep() advance the whole batch on one clock
+    if (descs[k].tau != descs[0].tau) arg_fail("all instances of a batch must share tau");
   }
 }
 

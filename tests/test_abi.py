@@ -69,6 +69,10 @@ def test_batch_rules_and_sizes():
     c.r = 2
     st, _, err = _ws([a, c])
     assert st == 1 and "share r" in err
+    e = native.make_desc(W.c2_hetero2d())
+    e.tau = 0.5 * a.tau
+    st, _, err = _ws([a, e])
+    assert st == 1 and "share tau" in err
     st, n1, _ = _ws([a])
     st2, n2, _ = _ws([a, a])
     assert st == 0 and st2 == 0 and n2 > n1 > 0

@@ -69,3 +69,25 @@ def test_autograd_finite_differences_20_directions():
         fd = (jp - jm) / (2 * eps)
         assert abs(fd - g @ dvec) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g).max()), (fd, g @ dvec)
     h.close()
+
+
+def test_backward_uses_its_own_forward_field():
+    """A second forward at another field on the same handle (a line search, a
+    finite-difference probe) must not change the first forward's gradient."""
+    torch = torch_cuda()
+    from paper_1801_04984_amd.adjoint import PressureMisfit
+    wl = small_workload(2, (8, 7), 1, seed=12, load_kind=W.LOAD_RAMP)
+    ns = 2
+    h, thetas, sens, obs, refs = _setup([wl], ns, 5, 31)
+    opts = {"rtol": 1e-13}
+    theta = torch.tensor(thetas[0], device="cuda", requires_grad=True)
+    J1 = PressureMisfit.apply(theta, h, ns, sens, obs[0].reshape(-1), opts)
+    other = torch.tensor(thetas[0] + 0.7 * W.unit_directions(1, thetas[0].size, 3)[0] * np.sqrt(thetas[0].size),
+                         device="cuda", requires_grad=True)
+    J2 = PressureMisfit.apply(other, h, ns, sens, obs[0].reshape(-1), opts)
+    assert abs(J2.item() - J1.item()) > 1e-6 * abs(J1.item())
+    J1.sum().backward()
+    g = theta.grad.cpu().numpy()
+    gref = refs[0][1]
+    assert np.linalg.norm(g - gref) <= 1e-8 * np.linalg.norm(gref)
+    h.close()
