@@ -74,6 +74,23 @@ typedef enum {
 typedef enum { BIOT_FP64 = 0, BIOT_MIXED = 1, BIOT_FP32_PREC = 2 } biot_precision;
 typedef enum { BIOT_LOAD_STEP = 0, BIOT_LOAD_RAMP = 1 } biot_load_kind;
 
+/* Complex-pair level blocks of the preconditioner (section "Monolithic
+ * Approach": a complex eigenvalue alpha +- i beta of the temporal matrix gives
+ * a 2x2 level block [[L, beta M_t], [-beta M_t, L]], L = alpha M_t + tau K_s,
+ * whose off-diagonal blocks are the paper's C^+-).
+ * BIOT_PAIR_DROP (default): couplings dropped, each level solved with the
+ *   shift alpha ("diagonal blockwise").
+ * BIOT_PAIR_PRESB: couplings kept; the block is solved by the preconditioned
+ *   square-block factorisation, two level solves with the shift alpha + beta
+ *   (one after the other; the preconditioner then takes two passes over all
+ *   levels) and one M_t product.
+ * BIOT_PAIR_SHIFT: couplings dropped, each level solved with the shift
+ *   alpha + beta.
+ * Real eigenvalues always give one level solve with their own shift.  The
+ * mode changes iteration counts, never the solution.  Transposed solves use
+ * the transposed blocks in the eigenbasis of T^T. */
+typedef enum { BIOT_PAIR_DROP = 0, BIOT_PAIR_PRESB = 1, BIOT_PAIR_SHIFT = 2 } biot_pair_mode;
+
 /* One problem instance.  Section "Poroelasticity": isotropic C (lambda, mu),
  * Biot coefficient 0 < b < 1, Biot modulus M > 0, viscosity eta; cellwise
  * permeability K = exp(log_k). */
@@ -93,6 +110,7 @@ typedef struct {
   int32_t load_kind;    /* biot_load_kind                                            */
   double load_s0;       /* top compressive traction magnitude                        */
   double load_t_ramp;   /* ramp time (> 0 for BIOT_LOAD_RAMP)                        */
+  int32_t pair_mode;    /* biot_pair_mode; all instances of a batch share it         */
 } biot_problem_desc;
 
 /* Solver controls (nullable: defaults in brackets). */
@@ -152,6 +170,14 @@ biot_status biot_totals(biot_problem h, int64_t* slab_len, int64_t* state_len);
 biot_status apply_operator(biot_problem h, const void* x, void* y, int32_t transpose,
                            int32_t dtype, void* stream);
 
+/* The elasticity block of the slab operator, y_u = tau A x_u (section
+ * "Monolithic Approach": the tau-scaled displacement block of every L_j), on
+ * the u-blocks of every time level and instance of device slab vectors;
+ * essential u rows copy x; the q and p entries of y are not written.  This is
+ * the fine-level operator of the preconditioner's elasticity multigrid.
+ * dtype 0: double, 1: float.  x and y must not alias.  Asynchronous. */
+biot_status biot_elasticity_apply(biot_problem h, const void* x, void* y, int32_t dtype, void* stream);
+
 /* Tile shapes of the operator apply.  Every variant computes bitwise the same
  * y; they differ only in the work decomposition (2D: 0 = 16x16-thread tiles,
  * 1 = 8x8, 2 = 8x8 with one thread layer per time level, the levels in
@@ -200,7 +226,10 @@ biot_status solve_slab_transposed(biot_problem h, const double* rhs, double* x,
 /* March nslabs slabs from t_start (section "Discretisation in Time"):
  * state (device, in/out) = X^- per instance; slabs_out (device, nullable)
  * receives nslabs slab vectors; checkpoints (device, nullable) receives the
- * state entering each slab.  infos: host, nslabs * count entries. */
+ * state entering each slab.  infos: host, nslabs * count entries.
+ * Initial guess of each slab solve: the previous slab extrapolated in time;
+ * with checkpoints, the entering state broadcast to all levels instead, so
+ * that adjoint_sweep (same opts) recomputes bitwise the same slabs. */
 biot_status step(biot_problem h, int32_t nslabs, double t_start, double* state,
                  double* slabs_out, double* checkpoints, const biot_solve_opts* opts,
                  biot_solve_info* infos, void* stream);

@@ -15,21 +15,14 @@
 namespace bt {
 
 // threads per block of the element-wise and gather kernels over segments
-#ifndef BT_BLK
-#define BT_BLK 256
-#endif
-constexpr int kBlk = BT_BLK;
+constexpr int kBlk = 256;
 
 // The 8 XCDs of the chip each have their own L2, and consecutive workgroup ids
 // go to consecutive XCDs.  xcd_order(n)[b] = the tile that workgroup b should
 // take so that every XCD gets one contiguous run of tiles (neighbouring tiles
 // share halo data through that XCD's L2): XCD x = b % 8 takes its k-th
 // (k = b / 8) tile from the x-th run.
-#ifndef BT_NO_XCD_ORDER
 constexpr int kXcds = 8;
-#else
-constexpr int kXcds = 1;
-#endif
 inline long long xcd_tile(long long b, long long n) {
   const long long x = b % kXcds, k = b / kXcds;
   const long long base = n / kXcds, rem = n % kXcds;   // run x holds base + (x < rem) tiles

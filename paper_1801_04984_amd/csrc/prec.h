@@ -24,6 +24,33 @@ struct ChebCoef {      // one launch: init scale or step coefficients
   double bsign;        // init: r = bsign * b (- S x)
 };
 
+// complex-pair level blocks (levels j, j+1 of the real block eigenbasis,
+// Q^-1 T Q = [[alpha, beta], [-beta, alpha]] there, beta > 0)
+struct PairSet {
+  int n;               // number of pairs (0..2)
+  int j[2];            // first level of each pair
+  double beta[2];
+};
+template <typename T>
+void launch_pair_split(const InstDev* insts, int count, long long maxN, const PairSet& ps, T* r, T* save,
+                       hipStream_t s);
+template <typename T>
+void launch_pair_couple(int dim, const InstDev* insts, int count, long long maxN, const PairSet& ps, const T* z,
+                        T* save, T* r, hipStream_t s);
+template <typename T>
+void launch_pair_join(const InstDev* insts, int count, long long maxN, const PairSet& ps, const T* save, T* z,
+                      hipStream_t s);
+// the same for the transposed pair block [[L^T, -beta M_t^T], [beta M_t^T, L^T]]
+template <typename T>
+void launch_pair_split_t(const InstDev* insts, int count, long long maxN, const PairSet& ps, T* r, T* save,
+                         hipStream_t s);
+template <typename T>
+void launch_pair_couple_t(int dim, const InstDev* insts, int count, long long maxN, const PairSet& ps, const T* z,
+                          T* save, T* r, hipStream_t s);
+template <typename T>
+void launch_pair_join_t(const InstDev* insts, int count, long long maxN, const PairSet& ps, const T* save, T* z,
+                        hipStream_t s);
+
 // pressure Schur, fine DG level: one segment per instance (all time levels)
 struct PDgSeg {
   int inst;            // index into InstDev table
@@ -79,9 +106,12 @@ void launch_p_prolong_cell(const PCellSeg* fine, const PCellSeg* coarse, int nse
 void launch_dq(const InstDev* insts, int count, long long maxN, const double* kinv, double* dqinv, hipStream_t s);
 
 // flux block: coupling right-hand sides from p, and tau Mq Chebyshev
+// per time level coefficient of the displacement right-hand side f_u = r_u + c_j b E p
+// (c_j = tau for L_j, c_j = the level shift for L_j^T)
+struct LevelCoef { double c[4]; };
 template <typename T>
-void launch_coupling(int dim, const InstDev* insts, int count, int nj, long long maxN, const T* rt, const T* zp,
-                     T* fu, T* fq, hipStream_t s);
+void launch_coupling(int dim, const InstDev* insts, int count, int nj, long long maxN, const LevelCoef& cu,
+                     const T* rt, const T* zp, T* fu, T* fq, hipStream_t s);
 template <typename T>
 void launch_mq(int dim, const InstDev* insts, int count, int nj, long long maxN, int mode, ChebCoef cc,
                const T* kinv, const T* dinvq, const T* b, T* x, T* r, const T* din, T* dout, hipStream_t s);

@@ -21,11 +21,12 @@ static dim3 grid3(long long maxlen, int nseg, int nj) {
 }
 
 template <typename T, int DIM>
-__global__ __launch_bounds__(256) void coupling_kernel(const InstDev* __restrict__ insts, const T* __restrict__ rt,
-                                                       const T* __restrict__ zp, T* __restrict__ fu,
-                                                       T* __restrict__ fq) {
+__global__ __launch_bounds__(256) void coupling_kernel(const InstDev* __restrict__ insts, LevelCoef cu,
+                                                       const T* __restrict__ rt, const T* __restrict__ zp,
+                                                       T* __restrict__ fu, T* __restrict__ fq) {
   const InstDev& I = insts[blockIdx.y];
   const int j = blockIdx.z;
+  const T cuj = T(cu.c[j] * I.b);
   const long long lo = I.x_off + j * I.N;
   const T* P = zp + lo + I.off_p;
   const int nuq = (int)I.off_p;
@@ -37,7 +38,7 @@ __global__ __launch_bounds__(256) void coupling_kernel(const InstDev* __restrict
     // that no load waits behind a per-lane branch
     if (blk == 0) {
       const T ep = ep_node<T, DIM>(I, P, comp, co);
-      fu[lo + t] = u_fixed(I, comp, co[0], co[1], co[2]) ? T(0) : r + T(I.b * I.tau) * ep;
+      fu[lo + t] = u_fixed(I, comp, co[0], co[1], co[2]) ? T(0) : r + cuj * ep;
     } else {
       T mq, dg, bp;
       flux_row<T, false>(I, nullptr, zp + lo, comp, co, t - (int)I.off_q[comp], mq, dg, bp);
@@ -46,17 +47,17 @@ __global__ __launch_bounds__(256) void coupling_kernel(const InstDev* __restrict
   }
 }
 template <typename T>
-void launch_coupling(int dim, const InstDev* insts, int count, int nj, long long maxN, const T* rt, const T* zp, T* fu,
-                     T* fq, hipStream_t s) {
+void launch_coupling(int dim, const InstDev* insts, int count, int nj, long long maxN, const LevelCoef& cu,
+                     const T* rt, const T* zp, T* fu, T* fq, hipStream_t s) {
   if (dim == 2)
-    hipLaunchKernelGGL((coupling_kernel<T, 2>), grid3(maxN, count, nj), dim3(kBlk), 0, s, insts, rt, zp, fu, fq);
+    hipLaunchKernelGGL((coupling_kernel<T, 2>), grid3(maxN, count, nj), dim3(kBlk), 0, s, insts, cu, rt, zp, fu, fq);
   else
-    hipLaunchKernelGGL((coupling_kernel<T, 3>), grid3(maxN, count, nj), dim3(kBlk), 0, s, insts, rt, zp, fu, fq);
+    hipLaunchKernelGGL((coupling_kernel<T, 3>), grid3(maxN, count, nj), dim3(kBlk), 0, s, insts, cu, rt, zp, fu, fq);
 }
-template void launch_coupling<double>(int, const InstDev*, int, int, long long, const double*, const double*,
-                                      double*, double*, hipStream_t);
-template void launch_coupling<float>(int, const InstDev*, int, int, long long, const float*, const float*, float*,
-                                     float*, hipStream_t);
+template void launch_coupling<double>(int, const InstDev*, int, int, long long, const LevelCoef&, const double*,
+                                      const double*, double*, double*, hipStream_t);
+template void launch_coupling<float>(int, const InstDev*, int, int, long long, const LevelCoef&, const float*,
+                                     const float*, float*, float*, hipStream_t);
 
 // ---- tau Mq and its Chebyshev solve ---------------------------------------------------------
 template <typename T>

@@ -6,9 +6,11 @@
 // Sections "Monolithic Approach" and "Preconditioning technology": the slab
 // matrix A = T kron M_t + tau I kron K_s is preconditioned in the real block
 // eigenbasis of T, where it is block diagonal up to the +-beta M_t couplings of
-// complex eigenvalue pairs; those couplings are dropped ("diagonal blockwise")
-// and every remaining dG(0)-type block L_j = alpha_j M_t + tau K_s is
-// approximated by one truncated fixed-stress sweep.
+// complex eigenvalue pairs.  A pair's coupled 2x2 block is solved by the
+// preconditioned square-block factorisation (two level solves with the shift
+// alpha + beta, pairs.hip), or its couplings are dropped ("diagonal
+// blockwise"), per biot_pair_mode; every dG(0)-type level solve
+// (alpha M_t + tau K_s)^-1 is approximated by one truncated fixed-stress sweep.
 #include "solver.h"
 
 #include <algorithm>
@@ -32,18 +34,12 @@ constexpr int kMaxRestart = 64;
 // coarse-correction over-relaxation of the aggregation multigrid (2^d cells per
 // aggregate; measured best on the 2D 128^2 / 3D 48^3 workloads: 2.1 / 1.9)
 inline double omega_p(int dim) { return dim == 2 ? 2.1 : 1.9; }
-#ifndef BT_PDEG3
-#define BT_PDEG3 5
-#endif
-#ifndef BT_UDEG
-#define BT_UDEG 2
-#endif
 // Chebyshev smoothing degree on the pressure levels: 3 in 2D; in 3D degree 5
 // costs fewer slab iterations than it adds per iteration (measured on 32^3)
-inline int pdeg(int dim) { return dim == 2 ? 3 : BT_PDEG3; }
+inline int pdeg(int dim) { return dim == 2 ? 3 : 5; }
 constexpr double kPLo = 1.0 / 8.0, kPHi = 1.1;
 // Chebyshev degree of the elasticity smoother
-inline int udeg(int) { return BT_UDEG; }
+inline int udeg(int) { return 2; }
 constexpr double kULo = 1.0 / 15.0, kUHi = 1.1;
 constexpr double kQLo = 0.25, kQHi = 1.75;  // Gershgorin interval of Dq^-1 Mq
 constexpr long long kLineSolveMinLines = 16384;   // automatic flux-block choice
@@ -54,11 +50,8 @@ constexpr int kQDegDefault = 8;                     // Chebyshev degree when lin
 // (the inverses stay resident in the last-level cache).
 constexpr long long kPCoarseCells = 256;
 constexpr long long kUCoarseDofs = 1100;
-#ifndef BT_UTILE16_MIN
-#define BT_UTILE16_MIN 1024
-#endif
 // 2D elasticity levels with fewer 16x16 tiles (times levels j) than this use 8x8 tiles
-constexpr long long kUTile16MinTiles = BT_UTILE16_MIN;
+constexpr long long kUTile16MinTiles = 1024;
 constexpr long long kPCoarseBytes = 24LL << 20;   // sum over instances and levels j
 constexpr long long kUCoarseBytes = 48LL << 20;   // sum over instances (shared by the levels)
 
@@ -67,6 +60,7 @@ struct PrecBufs {
   T* V = nullptr;
   T *w = nullptr, *t = nullptr, *r = nullptr;
   T *Wr = nullptr, *Wz = nullptr, *Wf = nullptr, *T1 = nullptr, *T2 = nullptr, *T3 = nullptr, *T4 = nullptr;
+  T* Ws = nullptr;   // complex-pair blocks solved with their couplings: w and g (levels j, j+1)
   T* dqinv = nullptr;
   T* pdg_dinv = nullptr;
   std::vector<T*> pc_x, pc_b, pc_r, pc_d0, pc_d1, pc_coef, pc_dinv;
@@ -78,6 +72,9 @@ struct PrecBufs {
 
 struct PrecData {
   int nl = 1, dim = 2, count = 1;
+  // complex-pair level blocks (biot_pair_mode) and the pairs of the real block form
+  int pair_mode = BIOT_PAIR_DROP;
+  PairSet pairs{};
   // pressure hierarchy
   int npl = 0;
   std::vector<PDgSeg> pdg;
@@ -140,11 +137,12 @@ struct PrecData {
   int max_sens = 256;
   PrecBufs<double> b64;
   PrecBufs<float> b32;
-  Mat4 Q, Qi;
+  Mat4 Q, Qi;     // real block eigenbasis of T and its inverse
+  Mat4 Qt, Qit;   // their transposes (the eigenbasis of T^T is Q^-T)
   // captured preconditioner graphs (per precision and flux Chebyshev degree)
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
-  int gdeg[2] = {0, 0};
+  hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};   // [precision + 2 * transpose]
+  int gdeg[4] = {0, 0, 0, 0};
   // captured Arnoldi steps (preconditioner, operator, CGS2, normalisation), one
   // per Krylov index and variant; their dot products land in pinned host memory
   std::map<long long, hipGraphExec_t> arnoldi;
@@ -232,7 +230,11 @@ static void build_hierarchy(biot_problem_s* h, PrecData* P) {
     off += nl * np;
     const double kdr = D.lambda + 2.0 * D.mu / d;
     const double L = D.L_fs > 0 ? D.L_fs : D.b * D.b / kdr;
-    for (int j = 0; j < 4; ++j) s.cm[j] = (j < nl) ? h->tc.alpha[j] * (1.0 / D.M + L) : 0.0;
+    // level shift: alpha_j, or alpha_j + |beta_j| on complex-pair levels unless their couplings are dropped
+    for (int j = 0; j < 4; ++j) {
+      const double sh = h->tc.alpha[j] + (P->pair_mode == BIOT_PAIR_DROP ? 0.0 : std::fabs(h->tc.beta[j]));
+      s.cm[j] = (j < nl) ? sh * (1.0 / D.M + L) : 0.0;
+    }
     P->pdg.push_back(s);
     P->pdg_max = std::max(P->pdg_max, np);
   }
@@ -479,6 +481,7 @@ static void carve_bufs(biot_problem_s* h, PrecData* P, PrecBufs<T>& B, Layout& L
   B.xin = L.take<T>(S); B.bin = L.take<T>(S); B.pin = L.take<T>(S);
   B.Wr = L.take<T>(S); B.Wz = L.take<T>(S); B.Wf = L.take<T>(S);
   B.T1 = L.take<T>(S); B.T2 = L.take<T>(S); B.T3 = L.take<T>(S); B.T4 = L.take<T>(S);
+  if (P->pair_mode == BIOT_PAIR_PRESB && P->pairs.n > 0) B.Ws = L.take<T>(S);
   B.dqinv = L.take<T>(h->state_len);
   B.pdg_dinv = L.take<T>(P->pdg_total);
   const int nl = h->nl;
@@ -515,6 +518,14 @@ void plan_solver_layout(biot_problem_s* h, Layout& L, bool carve) {
     P = new PrecData();
     h->prec = P;
   }
+  P->pair_mode = h->descs[0].pair_mode;
+  P->pairs = PairSet{};
+  for (int j = 0; j + 1 < h->nl; ++j)
+    if (h->tc.beta[j] > 0 && P->pairs.n < 2) {   // columns j, j+1: alpha_j +- i beta_j
+      P->pairs.j[P->pairs.n] = j;
+      P->pairs.beta[P->pairs.n] = h->tc.beta[j];
+      ++P->pairs.n;
+    }
   build_hierarchy(h, P);
   carve_bufs<double>(h, P, P->b64, L, false);
   carve_bufs<float>(h, P, P->b32, L, true);
@@ -902,6 +913,8 @@ void setup_solver(biot_problem_s* h, hipStream_t s) {
   upload(P->gjp, P->d_gjp, s);
   upload(P->gseg, P->d_gseg, s);
   for (int j = 0; j < 16; ++j) { P->Q.m[j] = h->tc.Q[j]; P->Qi.m[j] = h->tc.Qi[j]; }
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) { P->Qt.m[i * 4 + j] = h->tc.Q[j * 4 + i]; P->Qit.m[i * 4 + j] = h->tc.Qi[j * 4 + i]; }
   // initial guess of the next slab: the previous slab's solution extrapolated
   // linearly in time through its last two Radau levels (r >= 1), or its end
   // value (r = 0), evaluated at the next slab's levels 1 + s_i (units of tau)
@@ -932,7 +945,7 @@ void refresh_solver(biot_problem_s* h, hipStream_t s) {
 void destroy_solver(biot_problem_s* h) {
   PrecData* P = h->prec;
   if (P) {
-    for (int q = 0; q < 2; ++q)
+    for (int q = 0; q < 4; ++q)
       if (P->gexec[q]) (void)hipGraphExecDestroy(P->gexec[q]);
     for (auto& kv : P->arnoldi) (void)hipGraphExecDestroy(kv.second);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
@@ -1044,17 +1057,25 @@ static void u_vcycle(biot_problem_s* h, int l, T* x, const T* b, T* r, T* d0, T*
   }
 }
 
+// the fixed-stress level solves, every level j at once: B.Wr -> B.Wz (B.Wr is read only).
+// transpose: the blocks L_j^T.  Their pressure Schur complement (with the
+// fixed-stress term) is that of L_j, and the sweep differs only in the
+// displacement right-hand side, r_u + c_j b E p with c_j = the level shift
+// instead of tau (the u-p couplings of L_j^T carry the coefficients of L_j's
+// p-u couplings).
 template <typename T>
-static void apply_prec(biot_problem_s* h, const T* rin, T* z, int qdeg, hipStream_t s) {
+static void level_solves(biot_problem_s* h, int qdeg, int transpose, hipStream_t s) {
   PrecData* P = h->prec;
   auto& B = bufs<T>(P);
   const int nl = h->nl, cnt = h->count, d = h->dim;
-  // into the real block eigenbasis of T
-  time_transform<T>(h->d_inst, cnt, P->maxN, nl, P->Qi, rin, B.Wr, s);
   // 1) pressure: S_j p = -r_p
   p_solve<T>(h, B.Wr, B.Wz, s);
   // 2) coupling right-hand sides
-  launch_coupling<T>(d, h->d_inst, cnt, nl, P->maxN, B.Wr, B.Wz, B.Wf, B.Wf, s);
+  LevelCoef cu{};
+  for (int j = 0; j < 4; ++j)
+    cu.c[j] = transpose ? h->tc.alpha[j] + (P->pair_mode == BIOT_PAIR_DROP ? 0.0 : std::fabs(h->tc.beta[j]))
+                        : h->descs[0].tau;
+  launch_coupling<T>(d, h->d_inst, cnt, nl, P->maxN, cu, B.Wr, B.Wz, B.Wf, B.Wf, s);
   // 3) flux: tau Mq q = f_q  (exact line solves, or Chebyshev-Jacobi of degree qdeg on the Gershgorin interval)
   if (qdeg == 0) {
     launch_mq_lines<T>(d, h->d_inst, cnt, nl, P->maxlines, P->maxcells_line, B.kinv, B.Wf, B.Wz, B.T1, s);
@@ -1068,22 +1089,52 @@ static void apply_prec(biot_problem_s* h, const T* rin, T* z, int qdeg, hipStrea
   }
   // 4) mechanics: tau A u = f_u  (one V-cycle)
   u_vcycle<T>(h, 0, B.Wz, B.Wf, B.T1, B.T2, B.T4, s);
+}
+
+// z = P^-1 r for the slab operator (transpose = 0) or its transpose (1).
+// Forward: P^-1 = (Q kron I) blockdiag(L_j^-1) (Q^-1 kron I), T = Q Lambda_R Q^-1.
+// Transposed: T^T = Q^-T Lambda_R^T Q^T, so P^-1 = (Q^-T kron I) blockdiag(L_j^-T) (Q^T kron I),
+// and a pair block carries -beta where the forward one carries beta.
+template <typename T>
+static void apply_prec(biot_problem_s* h, const T* rin, T* z, int qdeg, int transpose, hipStream_t s) {
+  PrecData* P = h->prec;
+  auto& B = bufs<T>(P);
+  const int nl = h->nl, cnt = h->count, d = h->dim;
+  // into the real block eigenbasis of T (of T^T)
+  time_transform<T>(h->d_inst, cnt, P->maxN, nl, transpose ? P->Qt : P->Qi, rin, B.Wr, s);
+  if (P->pair_mode == BIOT_PAIR_PRESB && P->pairs.n > 0) {
+    // pair blocks with their couplings (square-block factorisation), forward:
+    // w = H^-1 (f - g), y = H^-1 (g + beta M_t w), x = w + y; transposed:
+    // w = H^-T (f + g), y = H^-T (g - beta M_t^T w), x = w - y.  The second pass
+    // repeats the real levels' solves on unchanged right-hand sides.
+    if (transpose) launch_pair_split_t<T>(h->d_inst, cnt, P->maxN, P->pairs, B.Wr, B.Ws, s);
+    else launch_pair_split<T>(h->d_inst, cnt, P->maxN, P->pairs, B.Wr, B.Ws, s);
+    level_solves<T>(h, qdeg, transpose, s);
+    if (transpose) launch_pair_couple_t<T>(d, h->d_inst, cnt, P->maxN, P->pairs, B.Wz, B.Ws, B.Wr, s);
+    else launch_pair_couple<T>(d, h->d_inst, cnt, P->maxN, P->pairs, B.Wz, B.Ws, B.Wr, s);
+    level_solves<T>(h, qdeg, transpose, s);
+    if (transpose) launch_pair_join_t<T>(h->d_inst, cnt, P->maxN, P->pairs, B.Ws, B.Wz, s);
+    else launch_pair_join<T>(h->d_inst, cnt, P->maxN, P->pairs, B.Ws, B.Wz, s);
+  } else {
+    level_solves<T>(h, qdeg, transpose, s);
+  }
   // back to the nodal time basis; essential rows pass through
-  launch_prec_finalize<T>(h->d_inst, cnt, P->maxN, nl, P->Q, B.Wz, rin, z, s);
+  launch_prec_finalize<T>(h->d_inst, cnt, P->maxN, nl, transpose ? P->Qit : P->Q, B.Wz, rin, z, s);
 }
 
 // z = P^-1 r through a captured graph: r is staged in a fixed buffer, the
 // graph (captured once on a private stream, replayed on the caller's stream)
 // runs the whole preconditioner and writes B.t.
 template <typename T>
-static void apply_prec_graph(biot_problem_s* h, const T* rin, T* z, int qdeg, bool use_graph, hipStream_t s) {
+static void apply_prec_graph(biot_problem_s* h, const T* rin, T* z, int qdeg, int transpose, bool use_graph,
+                             hipStream_t s) {
   PrecData* P = h->prec;
   auto& B = bufs<T>(P);
   if (!use_graph || z != B.t) {
-    apply_prec<T>(h, rin, z, qdeg, s);
+    apply_prec<T>(h, rin, z, qdeg, transpose, s);
     return;
   }
-  const int q = std::is_same<T, float>::value ? 1 : 0;
+  const int q = (std::is_same<T, float>::value ? 1 : 0) + (transpose ? 2 : 0);
   if (P->gexec[q] && P->gdeg[q] != qdeg) {
     hip_check(hipGraphExecDestroy(P->gexec[q]), "graph destroy");
     P->gexec[q] = nullptr;
@@ -1093,7 +1144,7 @@ static void apply_prec_graph(biot_problem_s* h, const T* rin, T* z, int qdeg, bo
     hip_check(hipStreamSynchronize(s), "pre-capture sync");
     hipGraph_t g;
     hip_check(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeRelaxed), "begin capture");
-    apply_prec<T>(h, B.pin, B.t, qdeg, P->cap_stream);
+    apply_prec<T>(h, B.pin, B.t, qdeg, transpose, P->cap_stream);
     hip_check(hipStreamEndCapture(P->cap_stream, &g), "end capture");
     hip_check(hipGraphInstantiate(&P->gexec[q], g, nullptr, nullptr, 0), "graph instantiate");
     hip_check(hipGraphDestroy(g), "graph destroy");
@@ -1154,13 +1205,13 @@ static void arnoldi_step(biot_problem_s* h, int jj, int transpose, const SolveCt
       auto& F = P->b32;
       float* zj = F.V + (long long)jj * S;
       vcast(vj, F.w, S, s);
-      apply_prec<float>(h, F.w, F.t, ctl.qdeg, s);
+      apply_prec<float>(h, F.w, F.t, ctl.qdeg, transpose, s);
       vcopy<float>(F.t, zj, S, s);
       vcast(zj, B.t, S, s);
       done_prec = true;
     }
   }
-  if (!done_prec) apply_prec<T>(h, vj, B.t, ctl.qdeg, s);
+  if (!done_prec) apply_prec<T>(h, vj, B.t, ctl.qdeg, transpose, s);
   launch_apply(h, B.t, vn, transpose, std::is_same<T, float>::value ? 1 : 0, s);
   const int nch = dot_chunks(P->gmax);
   double* hd = P->hdots;
@@ -1333,7 +1384,7 @@ static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const Solv
       if (!done_update) {
         hip_check(hipMemsetAsync(B.w, 0, sizeof(T) * S, s), "zero");
         seg_maxpy<T, T>(B.V, S, kmax, P->coef, 1.0, B.w, P->d_gseg, cnt, P->gmax, s);
-        apply_prec_graph<T>(h, B.w, B.t, ctl.qdeg, ctl.graph, s);
+        apply_prec_graph<T>(h, B.w, B.t, ctl.qdeg, transpose, ctl.graph, s);
         vaxpby<T>(1.0, B.t, 1.0, x, S, s);
       }
     }
@@ -1577,6 +1628,32 @@ biot_status biot_autotune(biot_problem h, int32_t reps, biot_tuning* out, void* 
   BIOT_CATCH
 }
 
+biot_status biot_elasticity_apply(biot_problem h, const void* x, void* y, int32_t dtype, void* stream) {
+  try {
+    need(h, "handle is null");
+    need(x && y, "x and y must be device pointers");
+    need(x != y, "x and y must not alias");
+    need(dtype == 0 || dtype == 1, "dtype must be 0 (double) or 1 (float)");
+    PrecData* P = h->prec;
+    hipStream_t s = (hipStream_t)stream;
+    const int nwork = (int)P->uwork[0].size();
+    if (dtype == 0)
+      launch_uapply<double>(h->dim, P->d_ug[0], P->d_uwork[0], nwork, h->nl, 0, (const double*)x, nullptr, (double*)y,
+                            uemat<double>(P), s, P->utile[0]);
+    else
+      launch_uapply<float>(h->dim, P->d_ug[0], P->d_uwork[0], nwork, h->nl, 0, (const float*)x, nullptr, (float*)y,
+                           uemat<float>(P), s, P->utile[0]);
+    hip_check(hipGetLastError(), "elasticity apply launch");
+    return BIOT_OK;
+  } catch (const BiotError& e) {
+    set_error(e.msg);
+    return e.st;
+  } catch (const std::exception& e) {
+    set_error(std::string("internal error: ") + e.what());
+    return BIOT_ERR_ARG;
+  }
+}
+
 biot_status slab_rhs(biot_problem h, const double* state, double t_start, double* rhs, void* stream) {
   BIOT_TRY
   need(h, "handle is null");
@@ -1630,8 +1707,11 @@ biot_status step(biot_problem h, int32_t nslabs, double t_start, double* state, 
     double* x = P->xfwd;
     biot_status worst_st = BIOT_OK;
     const double tau = h->descs[0].tau;
-    // continue from the slab solved last (still in x) when this call picks up where it ended
-    bool prev = P->have_prev && std::fabs(t_start - P->prev_tend) <= 1e-9 * tau;
+    // continue from the slab solved last (still in x) when this call picks up where it ended.
+    // With checkpoints every slab starts from its entering state broadcast to all levels, the
+    // start adjoint_sweep takes when it recomputes the slab, so the recomputed forward slabs
+    // are bitwise the ones marched here.
+    bool prev = !checkpoints && P->have_prev && std::fabs(t_start - P->prev_tend) <= 1e-9 * tau;
     P->have_prev = false;
     for (int n = 0; n < nslabs; ++n) {
       if (checkpoints)
@@ -1645,7 +1725,7 @@ biot_status step(biot_problem h, int32_t nslabs, double t_start, double* state, 
       } else {
         launch_bcast(h->d_inst, h->count, P->maxN, h->nl, state, x, s);
       }
-      prev = true;
+      prev = !checkpoints;
       solve_impl(h, rhs, x, 0, opts, infos + (long long)n * h->count, s);
       biot_status st = worst(infos + (long long)n * h->count, h->count);
       if (st != BIOT_OK) worst_st = st;

@@ -25,7 +25,7 @@ EXPORTS = [
     "biot_workspace_bytes", "create_slab_problem", "destroy_slab_problem", "biot_set_log_k",
     "biot_sizes", "biot_totals", "apply_operator", "slab_rhs", "solve_slab",
     "solve_slab_transposed", "step", "adjoint_sweep", "biot_misfit", "biot_autotune",
-    "biot_get_tuning", "biot_set_tuning", "biot_last_error",
+    "biot_get_tuning", "biot_set_tuning", "biot_elasticity_apply", "biot_last_error",
 ]
 
 
@@ -35,7 +35,7 @@ class Desc(ctypes.Structure):
         ("r", ctypes.c_int32), ("tau", ctypes.c_double), ("lam", ctypes.c_double),
         ("mu", ctypes.c_double), ("b", ctypes.c_double), ("M", ctypes.c_double),
         ("eta", ctypes.c_double), ("L_fs", ctypes.c_double), ("load_kind", ctypes.c_int32),
-        ("load_s0", ctypes.c_double), ("load_t_ramp", ctypes.c_double),
+        ("load_s0", ctypes.c_double), ("load_t_ramp", ctypes.c_double), ("pair_mode", ctypes.c_int32),
     ]
 
 
@@ -97,6 +97,7 @@ def load_library(path: str = LIB_PATH):
     lib.biot_sizes.argtypes = [P, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.biot_totals.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.apply_operator.argtypes = [P, P, P, i32, i32, P]
+    lib.biot_elasticity_apply.argtypes = [P, P, P, i32, P]
     lib.slab_rhs.argtypes = [P, P, dbl, P, P]
     lib.solve_slab.argtypes = [P, P, P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), P]
     lib.solve_slab_transposed.argtypes = [P, P, P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), P]
@@ -120,7 +121,10 @@ def _check(status):
         raise BiotError(status, msg)
 
 
-def make_desc(wl) -> Desc:
+PAIR_DROP, PAIR_PRESB, PAIR_SHIFT = 0, 1, 2
+
+
+def make_desc(wl, pair_mode=PAIR_DROP) -> Desc:
     """Descriptor from a workloads.Workload."""
     d = Desc()
     d.dim = wl.dim
@@ -134,6 +138,7 @@ def make_desc(wl) -> Desc:
     d.load_kind = wl.load_kind
     d.load_s0 = wl.load_s0
     d.load_t_ramp = wl.load_t_ramp
+    d.pair_mode = int(pair_mode)
     return d
 
 
@@ -156,14 +161,14 @@ def _stream(torch, device):
 class BiotSlab:
     """A handle over one or several (batched) slab problems on one GPU."""
 
-    def __init__(self, workloads: Sequence, log_k: Sequence[np.ndarray], device="cuda:0"):
+    def __init__(self, workloads: Sequence, log_k: Sequence[np.ndarray], device="cuda:0", pair_mode=PAIR_DROP):
         import torch
         self.torch = torch
         self.lib = load_library()
         self.device = torch.device(device)
         self.wls = list(workloads)
         self.count = len(self.wls)
-        self.descs = (Desc * self.count)(*[make_desc(w) for w in self.wls])
+        self.descs = (Desc * self.count)(*[make_desc(w, pair_mode) for w in self.wls])
         self._logk = [np.ascontiguousarray(np.asarray(k, dtype=np.float64)) for k in log_k]
         arr = (ctypes.POINTER(ctypes.c_double) * self.count)(
             *[k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for k in self._logk])
@@ -222,6 +227,17 @@ class BiotSlab:
         assert x.numel() == self.slab_len and y.numel() == self.slab_len and y.dtype == x.dtype
         assert x.is_contiguous() and y.is_contiguous()
         _check(self.lib.apply_operator(self.h, _ptr(x), _ptr(y), int(transpose), dtype, self._stream()))
+        return y
+
+    def elasticity_apply(self, x, y=None):
+        """y_u = tau A x_u on the u-blocks of every level (q, p entries of y untouched)."""
+        torch = self.torch
+        dtype = 1 if x.dtype == torch.float32 else 0
+        if y is None:
+            y = torch.zeros_like(x)
+        assert x.numel() == self.slab_len and y.numel() == self.slab_len and y.dtype == x.dtype
+        assert x.is_contiguous() and y.is_contiguous()
+        _check(self.lib.biot_elasticity_apply(self.h, _ptr(x), _ptr(y), dtype, self._stream()))
         return y
 
     def rhs(self, state, t_start, out=None):

@@ -15,6 +15,7 @@ int main(void) {
   F(biot_problem_desc, tau); F(biot_problem_desc, lambda); F(biot_problem_desc, mu); F(biot_problem_desc, b);
   F(biot_problem_desc, M); F(biot_problem_desc, eta); F(biot_problem_desc, L_fs);
   F(biot_problem_desc, load_kind); F(biot_problem_desc, load_s0); F(biot_problem_desc, load_t_ramp);
+  F(biot_problem_desc, pair_mode);
   printf("}}\n");
   first = 1;
   printf("{\"name\": \"biot_solve_opts\", \"size\": %zu, \"fields\": {", sizeof(biot_solve_opts));
