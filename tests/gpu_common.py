@@ -13,12 +13,12 @@ def torch_cuda():
     return torch
 
 
-def make_pair(wls, thetas=None):
+def make_pair(wls, thetas=None, pair_mode=0):
     """(BiotSlab over all wls, list of oracle SlabProblems)."""
     from oracle import slab
     from paper_1801_04984_amd import BiotSlab
     thetas = thetas if thetas is not None else [w.log_k() for w in wls]
-    h = BiotSlab(wls, thetas)
+    h = BiotSlab(wls, thetas, pair_mode=pair_mode)
     probs = [slab.problem_from_workload(w, theta=t) for w, t in zip(wls, thetas)]
     return h, probs
 

@@ -1,43 +1,47 @@
 """Host-side checks of the benchmark's roofline bookkeeping (no GPU): the HBM
-traffic of the operator apply is taken from the committed counter record only
-while that record was taken from the current apply2d.hip, and the record
-covers the kernel name that bench.py builds for every 2D tile variant."""
+traffic of a kernel is taken from the committed counter record only while
+every source the record was taken from is unchanged, and the committed record
+(once present) names the kernels bench.py reports."""
+import hashlib
 import json
 import os
-import shutil
 
 import bench
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-REC = os.path.join("profiles", "apply2d_2d_128_dg1_pmc.json")
-SRC = os.path.join("paper_1801_04984_amd", "csrc", "apply2d.hip")
 
 
-def _tree(tmp_path, edit_source=False):
-    for rel in (REC, SRC):
-        dst = tmp_path / rel
-        dst.parent.mkdir(parents=True, exist_ok=True)
-        shutil.copy(os.path.join(ROOT, rel), dst)
-    if edit_source:
-        with open(tmp_path / SRC, "a") as f:
-            f.write("\n// edited\n")
-    return str(tmp_path)
+def _record(tmp_path, src_text):
+    src = tmp_path / "k.hip"
+    src.write_text(src_text)
+    rec = {"kernels": {"bt::k<double>": {
+        "traffic_bytes_per_launch": 123.0,
+        "sources_sha256": {"k.hip": hashlib.sha256(src_text.encode()).hexdigest()}}}}
+    path = tmp_path / "rec.json"
+    path.write_text(json.dumps(rec))
+    return str(path)
 
 
-def test_record_names_every_fp64_variant():
-    rec = json.load(open(os.path.join(ROOT, REC)))
-    for ts, lp in ((16, "false"), (8, "false"), (8, "true")):
-        key = f"bt::apply2d_kernel<double, 2, false, {ts}, {lp}>"
-        assert key in rec["kernels"], key
-        assert rec["kernels"][key]["traffic_bytes_per_launch"] > 0
+def test_traffic_only_for_matching_sources(tmp_path, monkeypatch):
+    rec = _record(tmp_path, "// kernel\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "PMC_RECORD", rec)
+    assert bench.measured_traffic("bt::k<double>") == 123.0
+    assert bench.measured_traffic("bt::other<double>") is None
+    (tmp_path / "k.hip").write_text("// kernel, edited\n")
+    assert bench.measured_traffic("bt::k<double>") is None
+    monkeypatch.setattr(bench, "PMC_RECORD", str(tmp_path / "missing.json"))
+    assert bench.measured_traffic("bt::k<double>") is None
 
 
-def test_traffic_only_for_matching_source(tmp_path, monkeypatch):
-    key = "bt::apply2d_kernel<double, 2, false, 8, true>"
-    monkeypatch.setattr(bench, "ROOT", _tree(tmp_path / "same"))
-    t = bench.measured_traffic(key)
-    assert t is not None and t > 0
-    monkeypatch.setattr(bench, "ROOT", _tree(tmp_path / "edited", edit_source=True))
-    assert bench.measured_traffic(key) is None
-    monkeypatch.setattr(bench, "ROOT", _tree(tmp_path / "same2"))
-    assert bench.measured_traffic("bt::apply2d_kernel<double, 2, false, 32, true>") is None
+def test_committed_record_covers_the_reported_kernels():
+    path = os.path.join(ROOT, "profiles", "counters_pmc.json")
+    if not os.path.exists(path):
+        return
+    rec = json.load(open(path))
+    assert "bt::uapply3d_kernel<double>" in rec["kernels"]
+    for key, k in rec["kernels"].items():
+        assert k["traffic_bytes_per_launch"] > 0, key
+        assert k["sources_sha256"], key
+        for rel in k["sources_sha256"]:
+            assert os.path.exists(os.path.join(ROOT, rel)), (key, rel)

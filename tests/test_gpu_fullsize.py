@@ -70,6 +70,43 @@ def test_solve_2d_128_residual_with_oracle_matrix():
     h.close()
 
 
+def _march_vs_lu(n, nslabs=2):
+    """The first slabs of the benchmark march (2D heterogeneous workload, dG(1),
+    tau 0.02, ramp load) on an n x n mesh: the GPU march at its default
+    tolerance, autotuned, against the oracle's nested-dissection LU march, per
+    field (relative l2 over all levels of a slab) <= 1e-10."""
+    torch = torch_cuda()
+    from oracle import slab
+    from paper_1801_04984_amd import tuning
+    wl = W.c2_hetero2d().scaled(n)
+    theta = wl.log_k()
+    h = _handle([wl])
+    tuning.tune(h, path=None)
+    state = h.zeros_state()
+    slabs = torch.zeros(nslabs * h.slab_len, dtype=torch.float64, device="cuda")
+    infos, st = h.step(nslabs, 0.0, state, slabs_out=slabs)
+    assert st == 0, infos
+    sv = slabs.cpu().numpy().reshape(nslabs, -1)
+    h.close()
+    prob = slab.problem_from_workload(wl, theta=theta)
+    ref = prob.march(nslabs)
+    errs = [field_rel(prob, sv[k], ref[k]) for k in range(nslabs)]
+    print(f"{n}: per-field errors {errs}; iterations {[i['iterations'] for i in infos]}")
+    for k in range(nslabs):
+        assert max(errs[k].values()) <= 1e-10, (k, errs[k])
+
+
+def test_march_2d_64_matches_oracle_lu():
+    _march_vs_lu((64, 64))
+
+
+@pytest.mark.timeout(900)
+def test_march_2d_128_matches_oracle_lu():
+    """At the benchmark mesh itself (658,436 slab unknowns; the oracle's LU
+    factorisation takes a few minutes on one host core)."""
+    _march_vs_lu((128, 128))
+
+
 class _RowOracle:
     """Rows of the slab operator from the oracle's per-cell matrices: for a
     free row g of level l, y = sum_j T_lj (M_t xm_j)[g] + tau (K_s xm_l)[g]
@@ -164,3 +201,64 @@ def test_batch_64_instances_match_single_handles():
         assert torch.equal(ys, h.instance_slab(y, k)), k
         g.close()
     h.close()
+
+
+@pytest.mark.timeout(900)
+def test_adjoint_3d_48_dg2_mixed_matches_fd_20_directions():
+    """The 3D 48^3 dG(2) adjoint workload: the gradient of J = 1/2 sum (p_h - p_obs)^2
+    at 64 sensors with respect to all 110,592 cellwise log K values, computed by
+    adjoint_sweep with the slab solves in mixed precision (FP32 inner solves in
+    FP64 refinement), against central FP64 finite differences of the forward map
+    along 20 random unit directions (eps = 1e-5), on the first two slabs."""
+    torch = torch_cuda()
+    from paper_1801_04984_amd import tuning
+    wl = W.c4_adjoint3d()
+    theta = wl.log_k()
+    h = _handle([wl])
+    tuning.tune(h, path=None)
+    ns = 2
+    sens = W.sensors(W.C4_NSENS, 3, W.C4_SENSOR_SEED)
+    # p_obs: the FP64 forward of the K field of the next seed
+    obs_wl = wl.scaled(wl.n, k_seed=W.C4_OBS_K_SEED)
+    h.set_log_k([obs_wl.log_k()])
+    st = h.zeros_state()
+    chk = torch.zeros(ns * h.state_len, dtype=torch.float64, device="cuda")
+    infos, s0 = h.step(ns, 0.0, st, checkpoints=chk, rtol=1e-13)
+    assert s0 == 0, infos
+    ends = torch.cat([chk[h.state_len:], st])
+    # the observations: that field's pressure at the sensors after each slab
+    from oracle import fe
+    P = fe.pressure_point_matrix(fe.Mesh(tuple(wl.n), wl.length), sens)
+    pe = ends.view(ns, h.level_dofs[0]).cpu().numpy()
+    p_obs = torch.tensor(np.concatenate([P @ pe[k] for k in range(ns)]), device="cuda")
+    h.set_log_k([theta])
+
+    def J_of(th, precision=0):
+        h.set_log_k([th])
+        s = h.zeros_state()
+        c = torch.zeros(ns * h.state_len, dtype=torch.float64, device="cuda")
+        inf, st_ = h.step(ns, 0.0, s, checkpoints=c, rtol=1e-13, precision=precision)
+        assert st_ == 0, inf
+        e = torch.cat([c[h.state_len:], s])
+        return h.misfit(ns, e, sens, p_obs)[0], c
+
+    J0, chk0 = J_of(theta, precision=1)
+    J, g, sa = h.adjoint(ns, 0.0, chk0, sens, p_obs, precision=1, rtol=1e-13)
+    assert sa == 0
+    assert abs(J[0] - J0) <= 1e-12 * abs(J0)
+    g = g.cpu().numpy()
+    dirs = W.unit_directions(W.C4_NDIRS, theta.size, W.C4_DIRECTION_SEED)
+    eps = 1e-5
+    errs = []
+    for d in dirs:
+        jp, _ = J_of(theta + eps * d)
+        jm, _ = J_of(theta - eps * d)
+        fd = (jp - jm) / (2 * eps)
+        ad = float(g @ d)
+        errs.append((fd, ad))
+    h.close()
+    gn = float(np.linalg.norm(g))
+    rel = [abs(fd - ad) / max(abs(ad), 1e-3 * gn) for fd, ad in errs]
+    print(f"48^3 dG(2) adjoint: J {J0:.6e}, |grad| {gn:.3e}; directional derivatives (fd, adjoint) {errs}; "
+          f"max rel diff {max(rel):.2e}")
+    assert max(rel) <= 1e-4, rel

@@ -44,11 +44,6 @@ def test_solve_mixed_refined(r):
     assert st == 0 and info[0]["ir_sweeps"] >= 1, info
     err = field_rel(prob, x.cpu().numpy(), ref)
     assert max(err.values()) < TOL, err
-    # one refinement sweep only: the FP32 inner solve alone is good to the
-    # single-precision level (the mixed path before refinement)
-    x1, info1, st1 = h.solve(torch.tensor(b, device="cuda"), precision=1, max_refine=1, inner_rtol=1e-6)
-    err1 = field_rel(prob, x1.cpu().numpy(), ref)
-    assert max(err1.values()) < 1e-4, err1
     h.close()
 
 
@@ -138,11 +133,22 @@ def test_step_matches_oracle_march_and_resumes(r):
     assert np.all(cv[0] == 0.0)
     for n in range(1, ns):
         np.testing.assert_array_equal(cv[n], sv[n - 1][r * prob.N:(r + 1) * prob.N])
-    # resume: 2 + 2 slabs from the saved state equals 4 straight (bitwise)
+    # resume: 2 + 2 slabs from the saved state equals 4 straight (bitwise), with
+    # checkpoints (every slab starts from its entering state) and without (the
+    # march predictor carries over from the first call to the second)
     s2 = h.zeros_state()
-    h.step(2, 0.0, s2)
-    h.step(2, 2 * wl.tau, s2)
+    c2 = torch.zeros(2 * h.state_len, dtype=torch.float64, device="cuda")
+    h.step(2, 0.0, s2, checkpoints=c2)
+    h.step(2, 2 * wl.tau, s2, checkpoints=c2)
     np.testing.assert_array_equal(s2.cpu().numpy(), state.cpu().numpy())
+    s4 = h.zeros_state()
+    h.step(4, 0.0, s4)
+    s3 = h.zeros_state()
+    h.step(2, 0.0, s3)
+    h.step(2, 2 * wl.tau, s3)
+    np.testing.assert_array_equal(s3.cpu().numpy(), s4.cpu().numpy())
+    err = field_rel(prob, np.tile(s4.cpu().numpy(), prob.L), np.tile(ref[-1][r * prob.N:(r + 1) * prob.N], prob.L))
+    assert max(err.values()) < TOL, err
     h.close()
 
 
@@ -182,8 +188,32 @@ def test_error_paths():
     h.close()
 
 
-@pytest.mark.parametrize("r", [0, 1])
-def test_adjoint_gradient_matches_oracle(r):
+@pytest.mark.parametrize("d,n", [(2, (12, 10)), (2, (21, 13)), (3, (4, 4, 3))])
+def test_solve_dg3(d, n):
+    """dG(3): four Radau levels whose real block eigenbasis holds two
+    complex-pair blocks; forward and transposed FP64 solves, and the mixed
+    refined solve, against the oracle's LU."""
+    torch = torch_cuda()
+    wl = small_workload(d, n, 3, seed=13 + d)
+    h, (prob,) = make_pair([wl])
+    b = _rhs(prob, seed=6)
+    for transpose in (False, True):
+        ref = prob.solve(b, transpose=transpose)
+        x, info, st = h.solve(torch.tensor(b, device="cuda"), rtol=RT, transpose=transpose)
+        assert st == 0 and info[0]["iterations"] < 200, info
+        err = field_rel(prob, x.cpu().numpy(), ref)
+        assert max(err.values()) < TOL, (transpose, err)
+    x, info, st = h.solve(torch.tensor(b, device="cuda"), precision=1)
+    assert st == 0, info
+    err = field_rel(prob, x.cpu().numpy(), prob.solve(b))
+    assert max(err.values()) < TOL, err
+    h.close()
+
+
+@pytest.mark.parametrize("r,precision", [(0, 0), (1, 0), (2, 0), (3, 0), (1, 1), (2, 1), (2, 2)])
+def test_adjoint_gradient_matches_oracle(r, precision):
+    """adjoint_sweep against the oracle's discrete adjoint, for dG(0..3) and
+    with the forward and adjoint slab solves in both mixed modes."""
     torch = torch_cuda()
     from oracle import adjoint, fe
     wl = small_workload(2, (8, 7), r, seed=51, load_kind=W.LOAD_RAMP)
@@ -196,13 +226,19 @@ def test_adjoint_gradient_matches_oracle(r):
     Jref, gref, _ = adjoint.gradient(prob, ns, P, p_obs)
     state = h.zeros_state()
     chk = torch.zeros(ns * h.state_len, dtype=torch.float64, device="cuda")
-    infos, st = h.step(ns, 0.0, state, checkpoints=chk)
+    infos, st = h.step(ns, 0.0, state, checkpoints=chk, precision=precision)
     assert st == 0
-    J, g, st = h.adjoint(ns, 0.0, chk, sens, torch.tensor(p_obs.reshape(-1), device="cuda"))
+    p_obs_d = torch.tensor(p_obs.reshape(-1), device="cuda")
+    J, g, st = h.adjoint(ns, 0.0, chk, sens, p_obs_d, precision=precision)
     assert st == 0
     assert abs(J[0] - Jref) <= 1e-9 * abs(Jref)
     gv = g.cpu().numpy()
     assert np.linalg.norm(gv - gref) <= 1e-8 * np.linalg.norm(gref), (np.abs(gv - gref).max(), np.abs(gref).max())
+    # the adjoint's recomputed slabs are the marched ones: its J equals the
+    # misfit of the marched end states up to the order of the sum over slabs
+    ends = torch.cat([chk[h.state_len:], state])
+    Jf = h.misfit(ns, ends, sens, p_obs_d)
+    assert abs(J[0] - Jf[0]) <= 8 * np.finfo(float).eps * abs(Jf[0]), (J[0], Jf[0])
     h.close()
 
 
@@ -249,10 +285,11 @@ def test_flux_block_variants(d, n, length):
     h.close()
 
 
-def test_step3d_and_adjoint():
+@pytest.mark.parametrize("r", [1, 2])
+def test_step3d_and_adjoint(r):
     torch = torch_cuda()
     from oracle import adjoint, fe
-    wl = small_workload(3, (4, 3, 4), 1, seed=81, load_kind=W.LOAD_RAMP)
+    wl = small_workload(3, (4, 3, 4), r, seed=81, load_kind=W.LOAD_RAMP)
     theta = wl.log_k()
     h, (prob,) = make_pair([wl], [theta])
     ns = 2
@@ -327,3 +364,66 @@ def test_flux_line_solve_full_wavefront():
     cell-end equations, eight per lane, every slot of the reduction in use
     (the cross lines of 2 cells run in the same launch)."""
     test_flux_block_variants(2, (511, 2), (5.11, 0.02))
+
+
+@pytest.mark.parametrize("n,length", [((511, 1, 1), (5.11, 0.01, 0.01)), ((520, 1, 1), (5.2, 0.01, 0.01))])
+def test_flux_line_solve_3d_long_lines(n, length):
+    """3D flux lines along x of 511 cells (the wavefront line solve, every slot
+    in use) and 520 cells (one thread per line), in the same launch as the
+    cross lines of one cell."""
+    test_flux_block_variants(3, n, length)
+
+
+def test_mixed_before_refinement_per_field_error():
+    """The mixed path before refinement: one FP32 inner GMRES solve (FP32
+    operator and preconditioner, FP64 dot accumulation) run to its FP32
+    floor, per-field relative error against the oracle's LU.  The floor of a
+    single-precision solve is bounded by cond(A) eps32; on this mesh the
+    measured floor is above 1e-6 for u (it is stated, with the condition
+    estimate, rather than the bound loosened); refinement then reaches 1e-10."""
+    torch = torch_cuda()
+    wl = small_workload(2, (24, 17), 1, seed=9)
+    h, (prob,) = make_pair([wl])
+    b = _rhs(prob, seed=2)
+    ref = prob.solve(b)
+    cond = prob.condition_estimate()
+    x1, info1, st1 = h.solve(torch.tensor(b, device="cuda"), precision=1, max_refine=1, inner_rtol=1e-7)
+    err1 = field_rel(prob, x1.cpu().numpy(), ref)
+    eps32 = float(np.finfo(np.float32).eps)
+    print(f"cond_1 estimate {cond:.3e}; one FP32 sweep per-field error {err1}; "
+          f"iterations {info1[0]['iterations']}")
+    # measured on this mesh (cond_1 ~ 2.3e6): u 1.1e-5, q 3.3e-7, p 2.4e-6 -- the
+    # single-precision floor; 1e-6 is not reachable for u in FP32 arithmetic
+    assert max(err1.values()) <= min(5e-5, cond * eps32), (err1, cond)
+    assert err1["q"] <= 1e-6 and err1["p"] <= 1e-5, err1
+    # refinement from there reaches the FP64 tolerance
+    x, info, st = h.solve(torch.tensor(b, device="cuda"), precision=1, inner_rtol=1e-7)
+    assert st == 0, info
+    err = field_rel(prob, x.cpu().numpy(), ref)
+    assert max(err.values()) < TOL, err
+    h.close()
+
+
+@pytest.mark.parametrize("d,n,r", [(2, (20, 13), 1), (2, (33, 20), 2), (2, (16, 12), 3), (3, (5, 4, 6), 2)])
+def test_pair_modes_reach_the_oracle(d, n, r):
+    """The three treatments of the complex-pair level blocks (couplings kept
+    by the square-block factorisation, dropped, dropped with the shifted
+    level solve) are preconditioners of one system: all reach the oracle's
+    solution, forward and transposed, FP64 and FP32-preconditioned."""
+    torch = torch_cuda()
+    wl = small_workload(d, n, r, seed=110 + d + r)
+    its = {}
+    for mode in (0, 1, 2):
+        h, (prob,) = make_pair([wl], pair_mode=mode)
+        b = _rhs(prob, seed=12)
+        for transpose in (False, True):
+            ref = prob.solve(b, transpose=transpose)
+            for precision in (0, 2):
+                x, info, st = h.solve(torch.tensor(b, device="cuda"), rtol=RT, transpose=transpose,
+                                      precision=precision)
+                assert st == 0, (mode, transpose, precision, info)
+                err = field_rel(prob, x.cpu().numpy(), ref)
+                assert max(err.values()) < TOL, (mode, transpose, precision, err)
+                its[(mode, transpose, precision)] = info[0]["iterations"]
+        h.close()
+    print(f"d={d} n={n} r={r} iterations (mode, transposed, precision): {its}")
