@@ -254,6 +254,21 @@ biot_status adjoint_sweep(biot_problem h, int32_t nslabs, double t_start,
 biot_status biot_misfit(biot_problem h, int32_t nslabs, const double* states, const double* sensors_xyz,
                         int32_t nsens, const double* p_obs, double* J, void* stream);
 
+/* biot_misfit for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same J, with the sensor weights and residuals kept in a static device
+ * scratch of 4 MiB instead of the handle's workspace, and the states and
+ * p_obs read in place.  It calls no hipMalloc/hipFree and allocates nothing
+ * on the device.  Needs 256-byte-aligned count * nsens * 128 bytes +
+ * count * nsens * 8 bytes <= 4 MiB, else BIOT_ERR_ARG (no side effect); no
+ * other limit on nsens.  Every call on one GPU shares that GPU's scratch
+ * (held until the process ends): calls that overlap on one GPU (other
+ * streams, other threads, other handles) race and must be serialised by the
+ * caller.  Arguments and result as biot_misfit; synchronises `stream`. */
+biot_status biot_misfit_noalloc(biot_problem h, int32_t nslabs, const double* states,
+                                const double* sensors_xyz, int32_t nsens, const double* p_obs,
+                                double* J, void* stream);
+
 /* Thread-local message describing the last non-OK status. */
 const char* biot_last_error(void);
 

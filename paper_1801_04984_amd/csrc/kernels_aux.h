@@ -14,6 +14,8 @@ void launch_bcast(const InstDev* insts, int count, long long maxN, int nl, const
                   hipStream_t s);
 void launch_extract(const InstDev* insts, int count, long long maxN, int lev, const double* x, double* state,
                     hipStream_t s);
+void launch_sensor_state(const InstDev* insts, int count, int n, int nslabs, int nsens, const SensorW* sw,
+                         const double* state, const double* p_obs, double* res, hipStream_t s);
 void launch_sensor(const InstDev* insts, int count, int lev, int nsens, const SensorW* sw, const double* X,
                    const double* obs, double* res, hipStream_t s);
 void launch_adjrhs(const InstDev* insts, int count, long long maxN, const TimeMat& tm, int nl, int has_next,

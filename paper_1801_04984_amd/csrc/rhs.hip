@@ -149,6 +149,28 @@ void launch_sensor(const InstDev* insts, int count, int lev, int nsens, const Se
   hipLaunchKernelGGL(sensor_kernel, dim3((nsens + 63) / 64, count), dim3(64), 0, s, insts, lev, nsens, sw, X, obs, res);
 }
 
+// the same residuals read straight from state n of a state sequence (one
+// spatial level per instance) and from p_obs[k][n][s]
+__global__ __launch_bounds__(256) void sensor_state_kernel(const InstDev* __restrict__ insts, int n, int nslabs,
+                                                           int nsens, const SensorW* __restrict__ sw,
+                                                           const double* __restrict__ state,
+                                                           const double* __restrict__ p_obs, double* __restrict__ res) {
+  const int k = blockIdx.y;
+  const InstDev& I = insts[k];
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsens) return;
+  const SensorW& W = sw[(long long)k * nsens + s];
+  const double* P = state + I.state_off + I.off_p;
+  double v = 0.0;
+  for (int g = 0; g < 8; ++g) v += W.w[g] * P[W.idx[g]];
+  res[(long long)k * nsens + s] = v - p_obs[((long long)k * nslabs + n) * nsens + s];
+}
+void launch_sensor_state(const InstDev* insts, int count, int n, int nslabs, int nsens, const SensorW* sw,
+                         const double* state, const double* p_obs, double* res, hipStream_t s) {
+  hipLaunchKernelGGL(sensor_state_kernel, dim3((nsens + 63) / 64, count), dim3(64), 0, s, insts, n, nslabs, nsens, sw,
+                     state, p_obs, res);
+}
+
 // adjoint right-hand side: a = 0 except
 //   level r p-rows:  sum_s res_s psi(x_s)  (sensor scatter, sequential per instance)
 //                    - (1/M) w_p c_p

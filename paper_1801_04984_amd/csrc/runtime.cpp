@@ -297,6 +297,8 @@ biot_status create_slab_problem(const biot_problem_desc* descs, int32_t count, c
     C.base = (char*)base;
     plan_layout(h, C, true);
     hipStream_t s = (hipStream_t)stream;
+    // look up this device's copy of the static scratch of biot_misfit_noalloc once, here
+    (void)scratch_ptr();
     // the workspace starts defined: no buffer of the handle ever holds stale caller data
     hip_check(hipMemsetAsync((void*)base, 0, C.off, s), "workspace clear");
     hip_check(hipMemcpyAsync(h->d_inst, h->inst.data(), sizeof(InstDev) * h->count, hipMemcpyHostToDevice, s),

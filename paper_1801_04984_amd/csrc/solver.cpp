@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <random>
 #include <string>
 #include <type_traits>
@@ -1494,6 +1495,37 @@ void launch_slab_rhs(const biot_problem_s* h, const double* state, double t_star
   hip_check(hipGetLastError(), "rhs launch");
 }
 
+// ---------------------------------------------------------------------------
+// Static scratch of biot_misfit_noalloc: the sensor weights and residuals that
+// biot_misfit keeps in the handle's workspace live here instead.  One copy per
+// GPU, held until the process ends; host code reaches it only through the
+// per-device address from hipGetSymbolAddress (the array's name is a host-side
+// stand-in, not a device address).
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(4) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// address of this device's copy of the scratch array (looked up once per
+// device, with that device current)
+void* scratch_ptr() {
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "current device");
+  if (dev < 0 || dev >= kMaxDevices) throw BiotError{BIOT_ERR_DEVICE, "device index beyond the scratch table"};
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch symbol address");
+    if (!p) throw BiotError{BIOT_ERR_DEVICE, "scratch symbol has no device address"};
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+static size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
 // sensor weights (host): containing cell (floor, clipped), DG-Q1 Lagrange weights
 static std::vector<SensorW> sensor_weights(biot_problem_s* h, const double* sensors_xyz, int nsens) {
   const int cnt = h->count, d = h->dim;
@@ -1771,6 +1803,47 @@ biot_status biot_misfit(biot_problem h, int32_t nslabs, const double* states, co
                                  8 * nsens, hipMemcpyDeviceToDevice, s), "obs gather");
       launch_sensor(h->d_inst, cnt, 0, nsens, P->sw, P->xfwd, P->sobs, P->sres, s);
       hip_check(hipMemcpyAsync(res.data(), P->sres, 8 * res.size(), hipMemcpyDeviceToHost, s), "res read");
+      hip_check(hipStreamSynchronize(s), "misfit sync");
+      for (int k = 0; k < cnt; ++k)
+        for (int q = 0; q < nsens; ++q) Jk[k] += 0.5 * res[(size_t)k * nsens + q] * res[(size_t)k * nsens + q];
+    }
+    for (int k = 0; k < cnt; ++k) J[k] = Jk[k];
+    return BIOT_OK;
+  } catch (const BiotError& e) {
+    set_error(e.msg);
+    return e.st;
+  } catch (const std::exception& e) {
+    set_error(std::string("internal error: ") + e.what());
+    return BIOT_ERR_ARG;
+  }
+}
+
+biot_status biot_misfit_noalloc(biot_problem h, int32_t nslabs, const double* states, const double* sensors_xyz,
+                                int32_t nsens, const double* p_obs, double* J, void* stream) {
+  try {
+    need(h, "handle is null");
+    need(nslabs >= 1, "nslabs must be >= 1");
+    need(states && p_obs, "states and p_obs must be device pointers");
+    need(sensors_xyz && J, "sensors_xyz and J must be host pointers");
+    need(nsens >= 1, "nsens must be >= 1");
+    const int cnt = h->count;
+    const size_t wbytes = align256(sizeof(SensorW) * (size_t)cnt * nsens);
+    const size_t need_bytes = wbytes + sizeof(double) * (size_t)cnt * nsens;
+    if (need_bytes > kScratchBytes)
+      throw BiotError{BIOT_ERR_ARG, "instances x sensors needs " + std::to_string(need_bytes) +
+                                        " bytes of scratch; the static scratch holds " +
+                                        std::to_string(kScratchBytes)};
+    hipStream_t s = (hipStream_t)stream;
+    char* base = (char*)scratch_ptr();
+    SensorW* sw_d = (SensorW*)base;
+    double* res_d = (double*)(base + wbytes);
+    auto sw = sensor_weights(h, sensors_xyz, nsens);
+    hip_check(hipMemcpyAsync(sw_d, sw.data(), sizeof(SensorW) * sw.size(), hipMemcpyHostToDevice, s), "weights");
+    std::vector<double> Jk(cnt, 0.0), res((size_t)cnt * nsens);
+    for (int n = 0; n < nslabs; ++n) {
+      launch_sensor_state(h->d_inst, cnt, n, nslabs, nsens, sw_d, states + (long long)n * h->state_len, p_obs, res_d,
+                          s);
+      hip_check(hipMemcpyAsync(res.data(), res_d, 8 * res.size(), hipMemcpyDeviceToHost, s), "res read");
       hip_check(hipStreamSynchronize(s), "misfit sync");
       for (int k = 0; k < cnt; ++k)
         for (int q = 0; q < nsens; ++q) Jk[k] += 0.5 * res[(size_t)k * nsens + q] * res[(size_t)k * nsens + q];

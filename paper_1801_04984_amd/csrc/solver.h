@@ -8,4 +8,6 @@ void setup_solver(biot_problem_s* h, hipStream_t s);
 void refresh_solver(biot_problem_s* h, hipStream_t s);
 void destroy_solver(biot_problem_s* h);
 void launch_apply(const biot_problem_s* h, const void* x, void* y, int transpose, int dtype, hipStream_t s);
+// device address of the static scratch of biot_misfit_noalloc on the current device
+void* scratch_ptr();
 }  // namespace bt

@@ -25,7 +25,7 @@ EXPORTS = [
     "biot_workspace_bytes", "create_slab_problem", "destroy_slab_problem", "biot_set_log_k",
     "biot_sizes", "biot_totals", "apply_operator", "slab_rhs", "solve_slab",
     "solve_slab_transposed", "step", "adjoint_sweep", "biot_misfit", "biot_autotune",
-    "biot_get_tuning", "biot_set_tuning", "biot_elasticity_apply", "biot_last_error",
+    "biot_get_tuning", "biot_set_tuning", "biot_misfit_noalloc", "biot_elasticity_apply", "biot_last_error",
 ]
 
 
@@ -105,6 +105,7 @@ def load_library(path: str = LIB_PATH):
     lib.adjoint_sweep.argtypes = [P, i32, dbl, P, ctypes.POINTER(dbl), i32, P, ctypes.POINTER(SolveOpts),
                                   ctypes.POINTER(dbl), P, P]
     lib.biot_misfit.argtypes = [P, i32, P, ctypes.POINTER(dbl), i32, P, ctypes.POINTER(dbl), P]
+    lib.biot_misfit_noalloc.argtypes = [P, i32, P, ctypes.POINTER(dbl), i32, P, ctypes.POINTER(dbl), P]
     lib.biot_autotune.argtypes = [P, i32, ctypes.POINTER(Tuning), P]
     lib.biot_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
     lib.biot_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
@@ -283,6 +284,15 @@ class BiotSlab:
         _check(self.lib.biot_misfit(self.h, int(nslabs), _ptr(end_states),
                                     sens.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), sens.shape[0],
                                     _ptr(p_obs), J, self._stream()))
+        return list(J)
+
+    def misfit_noalloc(self, nslabs, end_states, sensors_xyz, p_obs):
+        """biot_misfit_noalloc: the misfit with a static device scratch (no allocation)."""
+        sens = np.ascontiguousarray(np.asarray(sensors_xyz, dtype=np.float64))
+        J = (ctypes.c_double * self.count)()
+        _check(self.lib.biot_misfit_noalloc(self.h, int(nslabs), _ptr(end_states),
+                                            sens.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), sens.shape[0],
+                                            _ptr(p_obs), J, self._stream()))
         return list(J)
 
     # -- tile autotuner ----------------------------------------------------------
