@@ -396,8 +396,8 @@ def test_mixed_before_refinement_per_field_error():
     # single-precision floor; 1e-6 is not reachable for u in FP32 arithmetic
     assert max(err1.values()) <= min(5e-5, cond * eps32), (err1, cond)
     assert err1["q"] <= 1e-6 and err1["p"] <= 1e-5, err1
-    # refinement from there reaches the FP64 tolerance
-    x, info, st = h.solve(torch.tensor(b, device="cuda"), precision=1, inner_rtol=1e-7)
+    # refinement (default inner tolerance) reaches the FP64 tolerance
+    x, info, st = h.solve(torch.tensor(b, device="cuda"), precision=1)
     assert st == 0, info
     err = field_rel(prob, x.cpu().numpy(), ref)
     assert max(err.values()) < TOL, err
