@@ -6,9 +6,11 @@
 // matrices tau A_e (81x81) and E_e (81x8).  The element products of a layer
 // of cells are therefore one dense contraction
 //     [tau A_e | E_e] (81 x 89)  x  [u_e ; -c_p p_e] (89 x cells),
-// done on the matrix cores (16x16x4 MFMA, FP64 or FP32): six waves each keep
-// one 16-row tile of the element matrix in registers for the whole launch
-// and multiply the gathered element vectors staged in LDS.
+// done on the matrix cores (16x16x4 MFMA, FP64 or FP32): twelve waves, three
+// per SIMD, each keep one 16-row tile of the element matrix in registers for
+// the whole launch and multiply it with one half of the layer's gathered
+// element vectors staged in LDS.  The node loads of the next layer are issued
+// before the matrix-core phase of the current one (software pipeline).
 //
 // Work decomposition: one block = an xy tile of 8x8 cells (7x7 owned plus a
 // one-cell halo on the low sides) marching through a z-chunk of cell layers.
@@ -27,7 +29,8 @@ namespace bt {
 constexpr int kT3 = 8;        // xy tile edge in cells (64 cells per layer)
 constexpr int kO3 = kT3 - 1;  // owned cells per tile edge
 constexpr int kZC = 8;        // cell layers per z-chunk
-constexpr int kW3 = 6;        // waves per block: one 16-row tile of the 96 padded element rows each
+constexpr int kRT3 = 6;       // 16-row tiles of the 96 padded element rows
+constexpr int kW3 = 12;       // waves per block: (row tile, half of the 64 cells) each, three per SIMD
 constexpr int kLD3 = 80;      // LDS row stride (elements): 16-lane groups of one half-wave hit disjoint banks
 
 int apply3d_tile_cells_xy() { return kO3; }
@@ -89,10 +92,12 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
   const int mye = (j0 + kO3 >= ny) ? 2 * ny + 1 : 2 * j0 + 2 * kO3;
   const int nmx = mxe - 2 * i0, nmy = mye - 2 * j0;
   const int nplane = nmx * nmy;
-  // this wave's 16-row tile of the element matrix, resident for the whole launch
+  // this wave's 16-row tile of the element matrix, resident for the whole launch,
+  // and its half of the layer's 64 cells (column tiles 2 ch, 2 ch + 1)
+  const int rt = wv % kRT3, ch = wv / kRT3;
   T af[KS];
 #pragma unroll
-  for (int s = 0; s < KS; ++s) af[s] = J.A[(wv * KS + s) * 64 + lane];
+  for (int s = 0; s < KS; ++s) af[s] = J.A[(rt * KS + s) * 64 + lane];
   for (int idx = tid; idx < 27 * NC; idx += NT) Cc[idx] = T(0);
   // node-plane gather: 3 planes x 3 components of 17 x 17 nodes per layer.  All
   // of a thread's loads are issued before the LDS scatter; their offsets (less
@@ -121,20 +126,23 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
     }
   }
 
+  // the node loads of layer k are issued one layer ahead (software pipeline):
+  // they are in flight while the matrix cores and the node sums of layer k-1 run
+  T gv[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) gv[it] = J.X[(int)(gcode[it] & 0x3fffffffu) + sz * (2 * kbeg)];
   for (int k = kbeg; k < kend; ++k) {
     // ---- gather element vectors: the three node planes 2k..2k+2 of the tile
     // (17 x 17 nodes per plane and component) are read once, coalesced along x,
     // and every node is written to the element-vector slot of each cell that
     // shares it (essential u masked).  Cells outside the mesh get partial
     // vectors; their rows are never summed into an owned node.
-    T gv[NIT];
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
       // bottom face (plane mz = 0) is essential for every component
       const unsigned g = gcode[it];
       const bool in = !(g >> 31) && !(k == 0 && ((g >> 30) & 1u));
-      const T raw = J.X[(int)(g & 0x3fffffffu) + sz * (2 * k)];
-      gv[it] = in ? raw : T(0);
+      gv[it] = in ? gv[it] : T(0);
     }
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
@@ -160,6 +168,12 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
         }
       }
     }
+    // next layer's node loads (the last layer re-reads its own planes: in range, unused)
+    {
+      const int kn = k + 1 < kend ? k + 1 : k;
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) gv[it] = J.X[(int)(gcode[it] & 0x3fffffffu) + sz * (2 * kn)];
+    }
     // coupling columns (scaled mixed pressure at the cell's Gauss points) and padding
     for (int idx = tid; idx < (KR - 81) * NC; idx += NT) {
       const int kr = 81 + (idx >> 6), cell = idx & 63;
@@ -176,25 +190,25 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
       Ul[kr * kLD3 + cell] = v;
     }
     __syncthreads();
-    // ---- element rows of the layer: rows of tile wv x 64 cells
-    typename M::V acc[4];
+    // ---- element rows of the layer: rows of tile rt x cells 32 ch .. 32 ch + 31
+    typename M::V acc[2];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = typename M::V{0, 0, 0, 0};
+    for (int t = 0; t < 2; ++t) acc[t] = typename M::V{0, 0, 0, 0};
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      const T* Bs = Ul + (4 * s + (lane >> 4)) * kLD3 + (lane & 15);
+      const T* Bs = Ul + (4 * s + (lane >> 4)) * kLD3 + 32 * ch + (lane & 15);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc[t] = M::mma(af[s], Bs[16 * t], acc[t]);
+      for (int t = 0; t < 2; ++t) acc[t] = M::mma(af[s], Bs[16 * t], acc[t]);
     }
     __syncthreads();
     {
-      const int c = wv >> 1, h = wv & 1;
+      const int c = rt >> 1, h = rt & 1;
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+      for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int pr = 16 * h + M::row(lane, v);
-          if (pr < 27) Ul[(c * 27 + pr) * kLD3 + 16 * t + (lane & 15)] = acc[t][v];
+          if (pr < 27) Ul[(c * 27 + pr) * kLD3 + 32 * ch + 16 * t + (lane & 15)] = acc[t][v];
         }
     }
     __syncthreads();
@@ -475,7 +489,7 @@ template void launch_apply3d<float>(const ApplyArgs&, const void*, void*, int);
 // elasticity multigrid level: y = tau A x (mode 0) or y = b - tau A x (mode 1)
 template <typename T>
 __global__ __launch_bounds__(64 * kW3) void uapply3d_kernel(const UGridSeg* __restrict__ segs,
-                                                            const int4* __restrict__ work, int mode,
+                                                            const int4* __restrict__ work, int zc, int mode,
                                                             const T* __restrict__ emat, const T* __restrict__ X,
                                                             const T* __restrict__ Bv, T* __restrict__ Y) {
   const int4 w = work[blockIdx.x];
@@ -494,16 +508,17 @@ __global__ __launch_bounds__(64 * kW3) void uapply3d_kernel(const UGridSeg* __re
   J.npl = 0;
   J.sp[0] = 1; J.sp[1] = 1;
   for (int l = 0; l < 4; ++l) J.pw[l] = T(0);
-  u3_run<T, 21>(J, w.y * kO3, w.z * kO3, w.w * kZC, kZC);
+  u3_run<T, 21>(J, w.y * kO3, w.z * kO3, w.w * zc, zc);
 }
 template <typename T>
-void launch_uapply3d(const UGridSeg* segs, const int4* work, int nwork, int nj, int mode, const T* x, const T* b, T* y,
-                     const T* emat, hipStream_t s) {
-  hipLaunchKernelGGL((uapply3d_kernel<T>), dim3(nwork, nj), dim3(64 * kW3), 0, s, segs, work, mode, emat, x, b, y);
+void launch_uapply3d(const UGridSeg* segs, const int4* work, int nwork, int nj, int zc, int mode, const T* x,
+                     const T* b, T* y, const T* emat, hipStream_t s) {
+  hipLaunchKernelGGL((uapply3d_kernel<T>), dim3(nwork, nj), dim3(64 * kW3), 0, s, segs, work, zc, mode, emat, x, b,
+                     y);
 }
-template void launch_uapply3d<double>(const UGridSeg*, const int4*, int, int, int, const double*, const double*,
+template void launch_uapply3d<double>(const UGridSeg*, const int4*, int, int, int, int, const double*, const double*,
                                       double*, const double*, hipStream_t);
-template void launch_uapply3d<float>(const UGridSeg*, const int4*, int, int, int, const float*, const float*, float*,
-                                     const float*, hipStream_t);
+template void launch_uapply3d<float>(const UGridSeg*, const int4*, int, int, int, int, const float*, const float*,
+                                     float*, const float*, hipStream_t);
 
 }  // namespace bt

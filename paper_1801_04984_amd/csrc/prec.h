@@ -144,7 +144,7 @@ struct UProl {
   long long tab[3];            // per axis: per fine node (coarse cell, w0, w1, w2)
 };
 // 2D: variant 0 = 16x16-thread tiles, 1 = 8x8 (owned cells per tile edge:
-// uapply_tile(2, variant)); 3D ignores the variant
+// uapply_tile(2, variant)); 3D: the variant is the z-chunk (cell layers per block)
 template <typename T>
 void launch_uapply(int dim, const UGridSeg* segs, const int4* work, int nwork, int nj, int mode, const T* x,
                    const T* b, T* y, const T* emat, hipStream_t s, int variant);
@@ -158,8 +158,8 @@ template <typename T>
 void launch_mq_lines(int dim, const InstDev* insts, int count, int nj, long long maxlines, int maxcells_line,
                      const T* kinv, const T* b, T* x, T* w, hipStream_t s);
 template <typename T>
-void launch_uapply3d(const UGridSeg* segs, const int4* work, int nwork, int nj, int mode, const T* x, const T* b,
-                     T* y, const T* emat, hipStream_t s);
+void launch_uapply3d(const UGridSeg* segs, const int4* work, int nwork, int nj, int zc, int mode, const T* x,
+                     const T* b, T* y, const T* emat, hipStream_t s);
 template <typename T>
 void launch_rpass(const RPass* segs, int nseg, int nj, long long maxout, const double* tab, const T* in, T* out,
                   hipStream_t s);

@@ -128,7 +128,7 @@ void launch_uapply(int dim, const UGridSeg* segs, const int4* work, int nwork, i
       hipLaunchKernelGGL((uapply2d_kernel<T, 16>), dim3(nwork, nj), dim3(16, 16), 0, s, segs, work, mode, x, b, y,
                          emat);
   } else {
-    launch_uapply3d<T>(segs, work, nwork, nj, mode, x, b, y, emat, s);
+    launch_uapply3d<T>(segs, work, nwork, nj, variant, mode, x, b, y, emat, s);
   }
 }
 template void launch_uapply<double>(int, const UGridSeg*, const int4*, int, int, int, const double*, const double*,

@@ -333,7 +333,21 @@ static void build_hierarchy(biot_problem_s* h, PrecData* P) {
   P->uwork.assign(P->nul, {});
   P->utile.assign(P->nul, 0);
   for (int l = 0; l < P->nul; ++l) {
-    if (d != 2) continue;
+    if (d == 3) {
+      // z-chunk of the z-marching 3D kernel: 8 cell layers, halved (down to 2) while the
+      // level would give fewer blocks than CUs -- the small levels are bound by the
+      // latency of the serial layer march, which shorter chunks cut
+      long long txy = 0, nzmax = 1;
+      const int t = apply3d_tile_cells_xy();
+      for (const auto& g : P->ug[l]) {
+        txy += (long long)((g.n[0] + t - 1) / t) * ((g.n[1] + t - 1) / t);
+        nzmax = std::max<long long>(nzmax, g.n[2]);
+      }
+      int zc = 8;
+      while (zc > 2 && txy * ((nzmax + zc - 1) / zc) * nl < 256) zc /= 2;
+      P->utile[l] = zc;
+      continue;
+    }
     long long t16 = 0;
     for (const auto& g : P->ug[l]) t16 += (long long)((g.n[0] + 14) / 15) * ((g.n[1] + 14) / 15);
     P->utile[l] = t16 * nl < kUTile16MinTiles ? 1 : 0;
@@ -346,7 +360,7 @@ static void build_hierarchy(biot_problem_s* h, PrecData* P) {
         for (int ty = 0; ty < (g.n[1] + t - 1) / t; ++ty)
           for (int tx = 0; tx < (g.n[0] + t - 1) / t; ++tx) P->uwork[l].push_back(make_int4(k, tx, ty, 0));
       } else {
-        const int txy = apply3d_tile_cells_xy(), tz = apply3d_tile_cells_z(0);
+        const int txy = apply3d_tile_cells_xy(), tz = P->utile[l];
         for (int z = 0; z < (g.n[2] + tz - 1) / tz; ++z)
           for (int ty = 0; ty < (g.n[1] + txy - 1) / txy; ++ty)
             for (int tx = 0; tx < (g.n[0] + txy - 1) / txy; ++tx) P->uwork[l].push_back(make_int4(k, tx, ty, z));
@@ -1217,8 +1231,14 @@ static void arnoldi_step(biot_problem_s* h, int jj, int transpose, const SolveCt
   const int nch = dot_chunks(P->gmax);
   double* hd = P->hdots;
   seg_mdot<T, T>(B.V, S, jj + 1, vn, P->d_gseg, cnt, nch, P->partial, P->dot1, s, hd);
-  seg_maxpy<T, T>(B.V, S, jj + 1, P->dot1, -1.0, vn, P->d_gseg, cnt, P->gmax, s);
-  if (pythagorean_norm(jj)) {
+  if (jj + 1 <= kFuseK) {
+    // the same two passes with three sweeps over the basis: the update of pass 1
+    // fused with the dot products of pass 2 (which also give |w|^2), then the update
+    // of pass 2 fused with the normalisation (norm by Pythagoras, as below)
+    gs_update_dot<T, T>(B.V, S, jj + 1, P->dot1, vn, P->d_gseg, cnt, nch, P->partial, P->dot2, s, hd + 64 * cnt);
+    gs_update_scale<T, T>(B.V, S, jj + 1, P->dot2, vn, P->d_gseg, cnt, P->gmax, s);
+  } else if (pythagorean_norm(jj)) {
+    seg_maxpy<T, T>(B.V, S, jj + 1, P->dot1, -1.0, vn, P->d_gseg, cnt, P->gmax, s);
     // second pass; w itself is basis slot jj+1, so the same pass gives |w|^2, and
     // the norm after the update follows by Pythagoras (the second-pass components
     // are at rounding level, so no cancellation)
@@ -1226,6 +1246,7 @@ static void arnoldi_step(biot_problem_s* h, int jj, int transpose, const SolveCt
     seg_maxpy<T, T>(B.V, S, jj + 1, P->dot2, -1.0, vn, P->d_gseg, cnt, P->gmax, s);
     seg_scale<T, T>(vn, vn, P->dot2, jj + 1, 3, P->d_gseg, cnt, P->gmax, s);   // 0 for a zero norm
   } else {
+    seg_maxpy<T, T>(B.V, S, jj + 1, P->dot1, -1.0, vn, P->d_gseg, cnt, P->gmax, s);
     seg_mdot<T, T>(B.V, S, jj + 1, vn, P->d_gseg, cnt, nch, P->partial, P->dot2, s, hd + 64 * cnt);
     seg_maxpy<T, T>(B.V, S, jj + 1, P->dot2, -1.0, vn, P->d_gseg, cnt, P->gmax, s);
     seg_mdot<T, T>(vn, 0, 1, vn, P->d_gseg, cnt, nch, P->partial, P->dot3, s, hd + 128 * cnt);

@@ -38,6 +38,16 @@ template <typename TV, typename TW>
 void seg_mdot(const TV* V, long long ldv, int nk, const TW* w, const VSeg* segs, int nseg, int nchunk,
               double* partial, double* out, hipStream_t s, double* hout = nullptr);
 template <typename T> void vcopy(const T* x, T* y, long long n, hipStream_t s);
+// fused classical Gram-Schmidt passes for nk <= kFuseK basis vectors (see vec.hip):
+// w -= V c1 with out[seg*64 + k] = <V_k, w> (k < nk), out[seg*64 + nk] = <w, w>;
+// then w = (w - V c2) / sqrt(c2[nk] - |c2[0..nk)|^2)
+constexpr int kFuseK = 32;
+template <typename TV, typename TW>
+void gs_update_dot(const TV* V, long long ldv, int nk, const double* c1, TW* w, const VSeg* segs, int nseg, int nchunk,
+                   double* partial, double* out, hipStream_t s, double* hout = nullptr);
+template <typename TV, typename TW>
+void gs_update_scale(const TV* V, long long ldv, int nk, const double* c2, TW* w, const VSeg* segs, int nseg,
+                     long long maxlen, hipStream_t s);
 template <typename TV, typename TW>
 void seg_maxpy(const TV* V, long long ldv, int nk, const double* c, double csign, TW* w, const VSeg* segs, int nseg,
                long long maxlen, hipStream_t s);

@@ -58,7 +58,7 @@ void vacc(const float* x, double* y, long long n, hipStream_t s) {
 // ---- segmented multi-dot: out[seg][k] = <V_k, w> over segment seg ------------
 // stage 1: block b of segment s reduces a fixed chunk for KB vectors
 constexpr int kDotThreads = 256;
-constexpr int kKB = 8;
+constexpr int kKB = 32;   // vectors per stage-1 launch: w is read once per 32
 template <typename TV, typename TW>
 __global__ __launch_bounds__(kDotThreads) void mdot_stage1(const TV* __restrict__ V, long long ldv, int k0, int nk,
                                                            const TW* __restrict__ w, const VSeg* __restrict__ segs,
@@ -129,6 +129,112 @@ template void seg_mdot<double, double>(const double*, long long, int, const doub
                                        double*, hipStream_t, double*);
 template void seg_mdot<float, float>(const float*, long long, int, const float*, const VSeg*, int, int, double*,
                                      double*, hipStream_t, double*);
+
+// ---- fused Gram-Schmidt passes (K = nk <= kFuseK basis vectors) -----------------
+// pass 2 of classical Gram-Schmidt twice, fused with the update of pass 1:
+//   w <- w - sum_k c1[k] V_k,   partial dots <V_k, w> (k < K) and <w, w> (slot K)
+// over the same fixed chunks as mdot_stage1 (the V_k values of an element are
+// read once for both), reduced by mdot_stage2.
+template <typename TV, typename TW>
+__global__ __launch_bounds__(kDotThreads) void gs_update_dot_kernel(const TV* __restrict__ V, long long ldv, int nk,
+                                                                    const double* __restrict__ c1,
+                                                                    TW* __restrict__ w, const VSeg* __restrict__ segs,
+                                                                    int nchunk, double* __restrict__ partial) {
+  const VSeg sg = segs[blockIdx.y];
+  const int chunk = blockIdx.x;
+  const long long len = sg.len;
+  const long long per = (len + nchunk - 1) / nchunk;
+  const long long beg = chunk * per, end = beg + per < len ? beg + per : len;
+  __shared__ double cs[kFuseK];
+  if (threadIdx.x < kFuseK) cs[threadIdx.x] = threadIdx.x < nk ? c1[blockIdx.y * 64 + threadIdx.x] : 0.0;
+  __syncthreads();
+  double acc[kFuseK + 1];
+#pragma unroll
+  for (int k = 0; k <= kFuseK; ++k) acc[k] = 0.0;
+  for (long long i = beg + threadIdx.x; i < end; i += kDotThreads) {
+    double v[kFuseK];
+#pragma unroll
+    for (int k = 0; k < kFuseK; ++k) v[k] = k < nk ? (double)V[(long long)k * ldv + sg.off + i] : 0.0;
+    double wi = (double)w[sg.off + i];
+#pragma unroll
+    for (int k = 0; k < kFuseK; ++k) wi -= cs[k] * v[k];
+    const TW wt = (TW)wi;
+    w[sg.off + i] = wt;
+    const double wn = (double)wt;
+#pragma unroll
+    for (int k = 0; k < kFuseK; ++k) acc[k] += v[k] * wn;
+    acc[kFuseK] += wn * wn;
+  }
+  __shared__ double red[kFuseK + 1][kDotThreads / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k <= kFuseK; ++k) {
+    double v = acc[k];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if (lane == 0) red[k][wv] = v;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k <= nk; k += kDotThreads) {
+    const int src = k < nk ? k : kFuseK;
+    double v = 0.0;
+    for (int q = 0; q < kDotThreads / 64; ++q) v += red[src][q];
+    partial[((long long)blockIdx.y * 64 + k) * nchunk + chunk] = v;
+  }
+}
+// update of pass 2 and normalisation in one sweep:
+//   w <- f (w - sum_k c2[k] V_k),  f = 1 / sqrt(c2[K] - sum_k c2[k]^2)  (0 for a zero norm)
+// (c2[K] = |w|^2 before the update; the removed components are orthogonal, so the
+// norm after it follows by Pythagoras)
+template <typename TV, typename TW>
+__global__ __launch_bounds__(256) void gs_update_scale_kernel(const TV* __restrict__ V, long long ldv, int nk,
+                                                              const double* __restrict__ c2, TW* __restrict__ w,
+                                                              const VSeg* __restrict__ segs) {
+  const VSeg sg = segs[blockIdx.y];
+  __shared__ double cs[kFuseK];
+  __shared__ double fs;
+  const double* c = c2 + blockIdx.y * 64;
+  if (threadIdx.x < kFuseK) cs[threadIdx.x] = threadIdx.x < nk ? c[threadIdx.x] : 0.0;
+  if (threadIdx.x == 0) {
+    double n2 = c[nk];
+    for (int k = 0; k < nk; ++k) n2 -= c[k] * c[k];
+    fs = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+  }
+  __syncthreads();
+  const double f = fs;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < sg.len;
+       i += (long long)gridDim.x * blockDim.x) {
+    double v[kFuseK];
+#pragma unroll
+    for (int k = 0; k < kFuseK; ++k) v[k] = k < nk ? (double)V[(long long)k * ldv + sg.off + i] : 0.0;
+    double wi = (double)w[sg.off + i];
+#pragma unroll
+    for (int k = 0; k < kFuseK; ++k) wi -= cs[k] * v[k];
+    const TW wt = (TW)wi;   // rounded to the storage type before the scaling, as a separate pass would
+    w[sg.off + i] = (TW)(f * (double)wt);
+  }
+}
+template <typename TV, typename TW>
+void gs_update_dot(const TV* V, long long ldv, int nk, const double* c1, TW* w, const VSeg* segs, int nseg, int nchunk,
+                   double* partial, double* out, hipStream_t s, double* hout) {
+  hipLaunchKernelGGL((gs_update_dot_kernel<TV, TW>), dim3(nchunk, nseg), dim3(kDotThreads), 0, s, V, ldv, nk, c1, w,
+                     segs, nchunk, partial);
+  hipLaunchKernelGGL(mdot_stage2, dim3(nk + 1, nseg), dim3(256), 0, s, partial, nchunk, out, hout);
+}
+template <typename TV, typename TW>
+void gs_update_scale(const TV* V, long long ldv, int nk, const double* c2, TW* w, const VSeg* segs, int nseg,
+                     long long maxlen, hipStream_t s) {
+  long long b = (maxlen + 255) / 256;
+  unsigned gx = (unsigned)(b > 2048 ? 2048 : (b < 1 ? 1 : b));
+  hipLaunchKernelGGL((gs_update_scale_kernel<TV, TW>), dim3(gx, nseg), dim3(256), 0, s, V, ldv, nk, c2, w, segs);
+}
+template void gs_update_dot<double, double>(const double*, long long, int, const double*, double*, const VSeg*, int,
+                                            int, double*, double*, hipStream_t, double*);
+template void gs_update_dot<float, float>(const float*, long long, int, const double*, float*, const VSeg*, int, int,
+                                          double*, double*, hipStream_t, double*);
+template void gs_update_scale<double, double>(const double*, long long, int, const double*, double*, const VSeg*, int,
+                                              long long, hipStream_t);
+template void gs_update_scale<float, float>(const float*, long long, int, const double*, float*, const VSeg*, int,
+                                            long long, hipStream_t);
 
 // ---- plain copy (a kernel, so that it can sit in a captured graph) ----------------
 template <typename T>
