@@ -223,6 +223,33 @@ biot_status solve_slab_transposed(biot_problem h, const double* rhs, double* x,
                                   const biot_solve_opts* opts, biot_solve_info* info,
                                   void* stream);
 
+/* The paper's alternative to the monolithic solve (section "Iterative Coupling
+ * Approach"): the fixed-stress iterative coupling of flow and mechanics, here on
+ * the whole slab system.  Each outer iteration solves the flow sub-system for the
+ * (q, p) correction of the current residual, with the displacement's response to
+ * the pressure replaced by the fixed-stress term L Mp in the mass rows (L = the
+ * descriptor's L_fs, default b^2 / K_dr), then the mechanics sub-system
+ * tau A u = (b - A x)_u per time level with the new pressure.  The sub-systems
+ * are solved by GMRES preconditioned with the flow and mechanics parts of the
+ * level solves.  The fixed point is the slab solution of solve_slab; the
+ * iteration converges linearly, at a rate set by L.  x: initial guess in,
+ * solution out (device); info: host, one per instance; FP64 only. */
+typedef struct {
+  double rtol;          /* outer: ||b - A x|| <= rtol ||b||               [1e-12] */
+  int32_t max_outer;    /* outer fixed-stress iterations                   [1000] */
+  double inner_rtol;    /* relative tolerance of each sub-system solve     [1e-4] */
+  int32_t inner_maxit;  /* GMRES iterations per sub-system solve            [500] */
+} biot_fs_opts;
+typedef struct {
+  int32_t outer;            /* outer iterations                                    */
+  int32_t flow_iterations;  /* GMRES iterations of all flow solves                 */
+  int32_t mech_iterations;  /* GMRES iterations of all mechanics solves            */
+  int32_t status;           /* BIOT_OK, or BIOT_ERR_NOCONV after max_outer           */
+  double rel_residual;      /* final ||b - A x|| / ||b||                           */
+} biot_fs_info;
+biot_status solve_slab_fixed_stress(biot_problem h, const double* rhs, double* x, const biot_fs_opts* opts,
+                                    biot_fs_info* info, void* stream);
+
 /* March nslabs slabs from t_start (section "Discretisation in Time"):
  * state (device, in/out) = X^- per instance; slabs_out (device, nullable)
  * receives nslabs slab vectors; checkpoints (device, nullable) receives the

@@ -91,6 +91,7 @@ struct InstDev {
   long long state_off;   // offset into state (one level) vectors
   long long ncells;
   long long emat_off;    // element matrices of the instance (2D: tau*A_e, E_e; 3D: matrix-core fragments)
+  double Lfs;            // fixed-stress parameter L
 };
 
 // temporal matrices shared by a batch (same r)

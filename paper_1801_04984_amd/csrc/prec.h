@@ -51,6 +51,15 @@ template <typename T>
 void launch_pair_join_t(const InstDev* insts, int count, long long maxN, const PairSet& ps, const T* save, T* z,
                         hipStream_t s);
 
+// fixed-stress sub-systems (fixed_stress.hip): y += -L Mp (T p) on the p-rows with the
+// u-rows cleared; zero_rows clears the u-rows (which = 0) or the q- and p-rows (1)
+template <typename T>
+void launch_fs_flow_fix(const InstDev* insts, int count, long long maxN, int nl, const TimeMat& tm, const T* x, T* y,
+                        hipStream_t s);
+template <typename T>
+void launch_zero_rows(const InstDev* insts, int count, long long maxN, int nl, int which, T* y, hipStream_t s);
+
+
 // pressure Schur, fine DG level: one segment per instance (all time levels)
 struct PDgSeg {
   int inst;            // index into InstDev table

@@ -92,6 +92,7 @@ static InstDev make_inst(const biot_problem_desc& d) {
   o += (long long)I.sp[0] * I.sp[1] * I.sp[2];
   I.N = o;
   I.tau = d.tau; I.lam = d.lambda; I.mu = d.mu; I.b = d.b; I.Minv = 1.0 / d.M; I.eta = d.eta;
+  I.Lfs = d.L_fs > 0 ? d.L_fs : d.b * d.b / (d.lambda + 2.0 * d.mu / d.dim);
   I.s0 = d.load_s0; I.t_ramp = d.load_t_ramp; I.load_kind = d.load_kind;
   I.ncells = (long long)I.n[0] * I.n[1] * I.n[2];
   return I;

@@ -142,8 +142,8 @@ struct PrecData {
   Mat4 Qt, Qit;   // their transposes (the eigenbasis of T^T is Q^-T)
   // captured preconditioner graphs (per precision and flux Chebyshev degree)
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};   // [precision + 2 * transpose]
-  int gdeg[4] = {0, 0, 0, 0};
+  hipGraphExec_t gexec[12] = {};   // [precision + 2 * transpose + 4 * sub-system]
+  int gdeg[12] = {};
   // captured Arnoldi steps (preconditioner, operator, CGS2, normalisation), one
   // per Krylov index and variant; their dot products land in pinned host memory
   std::map<long long, hipGraphExec_t> arnoldi;
@@ -960,7 +960,7 @@ void refresh_solver(biot_problem_s* h, hipStream_t s) {
 void destroy_solver(biot_problem_s* h) {
   PrecData* P = h->prec;
   if (P) {
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 12; ++q)
       if (P->gexec[q]) (void)hipGraphExecDestroy(P->gexec[q]);
     for (auto& kv : P->arnoldi) (void)hipGraphExecDestroy(kv.second);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
@@ -1079,7 +1079,7 @@ static void u_vcycle(biot_problem_s* h, int l, T* x, const T* b, T* r, T* d0, T*
 // instead of tau (the u-p couplings of L_j^T carry the coefficients of L_j's
 // p-u couplings).
 template <typename T>
-static void level_solves(biot_problem_s* h, int qdeg, int transpose, hipStream_t s) {
+static void level_solves(biot_problem_s* h, int qdeg, int transpose, hipStream_t s, bool flow_only = false) {
   PrecData* P = h->prec;
   auto& B = bufs<T>(P);
   const int nl = h->nl, cnt = h->count, d = h->dim;
@@ -1103,20 +1103,45 @@ static void level_solves(biot_problem_s* h, int qdeg, int transpose, hipStream_t
                    B.kinv, nullptr, B.Wf, B.Wz, B.T1, (k & 1) ? B.T3 : B.T2, (k & 1) ? B.T2 : B.T3, s);
   }
   // 4) mechanics: tau A u = f_u  (one V-cycle)
-  u_vcycle<T>(h, 0, B.Wz, B.Wf, B.T1, B.T2, B.T4, s);
+  if (!flow_only) u_vcycle<T>(h, 0, B.Wz, B.Wf, B.T1, B.T2, B.T4, s);
 }
+
+// Sub-systems of the fixed-stress iterative coupling (fixed_stress.hip): 0 = the slab
+// system, 1 = the flow sub-system on (q, p), 2 = the mechanics sub-system tau A on u.
+enum SubSystem { kSysSlab = 0, kSysFlow = 1, kSysMech = 2 };
 
 // z = P^-1 r for the slab operator (transpose = 0) or its transpose (1).
 // Forward: P^-1 = (Q kron I) blockdiag(L_j^-1) (Q^-1 kron I), T = Q Lambda_R Q^-1.
 // Transposed: T^T = Q^-T Lambda_R^T Q^T, so P^-1 = (Q^-T kron I) blockdiag(L_j^-T) (Q^T kron I),
 // and a pair block carries -beta where the forward one carries beta.
 template <typename T>
-static void apply_prec(biot_problem_s* h, const T* rin, T* z, int qdeg, int transpose, hipStream_t s) {
+static void apply_prec(biot_problem_s* h, const T* rin, T* z, int qdeg, int transpose, hipStream_t s,
+                       int sys = kSysSlab) {
   PrecData* P = h->prec;
   auto& B = bufs<T>(P);
   const int nl = h->nl, cnt = h->count, d = h->dim;
+  if (sys == kSysMech) {
+    // one V-cycle per level on the u-rows (essential rows pass through, q and p rows zero)
+    vfill<T>(B.Wz, T(0), h->slab_len, s);
+    LevelCoef cu{};
+    launch_coupling<T>(d, h->d_inst, cnt, nl, P->maxN, cu, rin, B.Wz, B.Wf, B.Wf, s);   // f_u: essential rows 0
+    u_vcycle<T>(h, 0, B.Wz, B.Wf, B.T1, B.T2, B.T4, s);
+    Mat4 id{};
+    for (int i = 0; i < 4; ++i) id.m[i * 5] = 1.0;
+    launch_prec_finalize<T>(h->d_inst, cnt, P->maxN, nl, id, B.Wz, rin, z, s);
+    launch_zero_rows<T>(h->d_inst, cnt, P->maxN, nl, 1, z, s);
+    return;
+  }
   // into the real block eigenbasis of T (of T^T)
   time_transform<T>(h->d_inst, cnt, P->maxN, nl, transpose ? P->Qt : P->Qi, rin, B.Wr, s);
+  if (sys == kSysFlow) {
+    // the flow part of every level solve (pressure Schur cycle, then the flux lines); the
+    // pair couplings are dropped
+    level_solves<T>(h, qdeg, transpose, s, true);
+    launch_prec_finalize<T>(h->d_inst, cnt, P->maxN, nl, P->Q, B.Wz, rin, z, s);
+    launch_zero_rows<T>(h->d_inst, cnt, P->maxN, nl, 0, z, s);
+    return;
+  }
   if (P->pair_mode == BIOT_PAIR_PRESB && P->pairs.n > 0) {
     // pair blocks with their couplings (square-block factorisation), forward:
     // w = H^-1 (f - g), y = H^-1 (g + beta M_t w), x = w + y; transposed:
@@ -1142,14 +1167,14 @@ static void apply_prec(biot_problem_s* h, const T* rin, T* z, int qdeg, int tran
 // runs the whole preconditioner and writes B.t.
 template <typename T>
 static void apply_prec_graph(biot_problem_s* h, const T* rin, T* z, int qdeg, int transpose, bool use_graph,
-                             hipStream_t s) {
+                             hipStream_t s, int sys = kSysSlab) {
   PrecData* P = h->prec;
   auto& B = bufs<T>(P);
   if (!use_graph || z != B.t) {
-    apply_prec<T>(h, rin, z, qdeg, transpose, s);
+    apply_prec<T>(h, rin, z, qdeg, transpose, s, sys);
     return;
   }
-  const int q = (std::is_same<T, float>::value ? 1 : 0) + (transpose ? 2 : 0);
+  const int q = (std::is_same<T, float>::value ? 1 : 0) + (transpose ? 2 : 0) + 4 * sys;
   if (P->gexec[q] && P->gdeg[q] != qdeg) {
     hip_check(hipGraphExecDestroy(P->gexec[q]), "graph destroy");
     P->gexec[q] = nullptr;
@@ -1159,7 +1184,7 @@ static void apply_prec_graph(biot_problem_s* h, const T* rin, T* z, int qdeg, in
     hip_check(hipStreamSynchronize(s), "pre-capture sync");
     hipGraph_t g;
     hip_check(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeRelaxed), "begin capture");
-    apply_prec<T>(h, B.pin, B.t, qdeg, transpose, P->cap_stream);
+    apply_prec<T>(h, B.pin, B.t, qdeg, transpose, P->cap_stream, sys);
     hip_check(hipStreamEndCapture(P->cap_stream, &g), "end capture");
     hip_check(hipGraphInstantiate(&P->gexec[q], g, nullptr, nullptr, 0), "graph instantiate");
     hip_check(hipGraphDestroy(g), "graph destroy");
@@ -1177,12 +1202,30 @@ struct SolveCtl {
   int maxit, restart, qdeg;
   bool graph;
   bool flex32 = false;   // FP64 flexible GMRES with the preconditioner applied in FP32
+  int sys = kSysSlab;    // the system solved (SubSystem)
 };
+
+// y = A x for the slab system or a fixed-stress sub-system (x zero outside the
+// sub-system's rows; y zero there)
+template <typename T>
+static void sys_apply(biot_problem_s* h, const T* x, T* y, int transpose, int sys, hipStream_t s) {
+  const int dt = std::is_same<T, float>::value ? 1 : 0;
+  PrecData* P = h->prec;
+  if (sys == kSysMech) {
+    launch_uapply<T>(h->dim, P->d_ug[0], P->d_uwork[0], (int)P->uwork[0].size(), h->nl, 0, x, nullptr, y,
+                     uemat<T>(P), s, P->utile[0]);
+    launch_zero_rows<T>(h->d_inst, h->count, P->maxN, h->nl, 1, y, s);
+    return;
+  }
+  launch_apply(h, x, y, transpose, dt, s);
+  if (sys == kSysFlow) launch_fs_flow_fix<T>(h->d_inst, h->count, P->maxN, h->nl, h->tm, x, y, s);
+}
 
 // y = b - A x into r (type T)
 template <typename T>
-static void residual(biot_problem_s* h, const T* b, const T* x, T* r, int transpose, hipStream_t s) {
-  launch_apply(h, x, r, transpose, std::is_same<T, float>::value ? 1 : 0, s);
+static void residual(biot_problem_s* h, const T* b, const T* x, T* r, int transpose, hipStream_t s,
+                     int sys = kSysSlab) {
+  sys_apply<T>(h, x, r, transpose, sys, s);
   vaxpby<T>(1.0, b, -1.0, r, h->slab_len, s);
 }
 
@@ -1226,8 +1269,8 @@ static void arnoldi_step(biot_problem_s* h, int jj, int transpose, const SolveCt
       done_prec = true;
     }
   }
-  if (!done_prec) apply_prec<T>(h, vj, B.t, ctl.qdeg, transpose, s);
-  launch_apply(h, B.t, vn, transpose, std::is_same<T, float>::value ? 1 : 0, s);
+  if (!done_prec) apply_prec<T>(h, vj, B.t, ctl.qdeg, transpose, s, ctl.sys);
+  sys_apply<T>(h, B.t, vn, transpose, ctl.sys, s);
   const int nch = dot_chunks(P->gmax);
   double* hd = P->hdots;
   seg_mdot<T, T>(B.V, S, jj + 1, vn, P->d_gseg, cnt, nch, P->partial, P->dot1, s, hd);
@@ -1263,8 +1306,8 @@ static void arnoldi_step_graph(biot_problem_s* h, int jj, int transpose, const S
     return;
   }
   const long long key =
-      ((((long long)jj * 2 + (transpose ? 1 : 0)) * 2 + (ctl.flex32 ? 1 : 0)) * 2 +
-       (std::is_same<T, float>::value ? 1 : 0)) * 128 + ctl.qdeg;
+      (((((long long)jj * 2 + (transpose ? 1 : 0)) * 2 + (ctl.flex32 ? 1 : 0)) * 2 +
+        (std::is_same<T, float>::value ? 1 : 0)) * 128 + ctl.qdeg) * 3 + ctl.sys;
   auto it = P->arnoldi.find(key);
   if (it == P->arnoldi.end()) {
     if (!P->cap_stream) hip_check(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking), "capture stream");
@@ -1303,7 +1346,7 @@ static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const Solv
   seg_norms<T>(P, b, cnt, s, bn);
   for (int k = 0; k < cnt; ++k)
     if (!std::isfinite(bn[k])) throw BiotError{BIOT_ERR_NONFINITE, "right-hand side is not finite"};
-  residual<T>(h, b, x, B.r, transpose, s);
+  residual<T>(h, b, x, B.r, transpose, s, ctl.sys);
   seg_norms<T>(P, B.r, cnt, s, beta);
   std::vector<char> done(cnt, 0);
   for (int k = 0; k < cnt; ++k) {
@@ -1406,12 +1449,12 @@ static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const Solv
       if (!done_update) {
         hip_check(hipMemsetAsync(B.w, 0, sizeof(T) * S, s), "zero");
         seg_maxpy<T, T>(B.V, S, kmax, P->coef, 1.0, B.w, P->d_gseg, cnt, P->gmax, s);
-        apply_prec_graph<T>(h, B.w, B.t, ctl.qdeg, transpose, ctl.graph, s);
+        apply_prec_graph<T>(h, B.w, B.t, ctl.qdeg, transpose, ctl.graph, s, ctl.sys);
         vaxpby<T>(1.0, B.t, 1.0, x, S, s);
       }
     }
     std::vector<double> prev = beta;
-    residual<T>(h, b, x, B.r, transpose, s);
+    residual<T>(h, b, x, B.r, transpose, s, ctl.sys);
     seg_norms<T>(P, B.r, cnt, s, beta);
     for (int k = 0; k < cnt; ++k) {
       if (!std::isfinite(beta[k])) throw BiotError{BIOT_ERR_NONFINITE, "non-finite residual"};
@@ -1501,6 +1544,66 @@ static void solve_impl(biot_problem_s* h, const double* b, double* x, int transp
       info[k].status = done[k] ? BIOT_OK : BIOT_ERR_NOCONV;
       info[k].rel_residual = bn[k] > 0 ? rn[k] / bn[k] : 0.0;
     }
+  }
+}
+
+// Fixed-stress iterative coupling of one slab system (section "Iterative Coupling
+// Approach"), as a stationary iteration on the slab residual:
+//   flow:      solve the flow sub-system (fixed-stress term L Mp in the mass rows) for
+//              the (q, p) correction of the current residual,
+//   mechanics: solve tau A u_i = (b - A x)_u per level with the new pressure,
+// until ||b - A x|| <= rtol ||b||.  Each sub-system is solved by restarted GMRES
+// preconditioned with its part of the level solves (flow: pressure Schur cycle and
+// flux lines in the eigenbasis of T; mechanics: one V-cycle per level).
+static void fixed_stress_impl(biot_problem_s* h, const double* b, double* x, const biot_fs_opts* o,
+                              biot_fs_info* info, hipStream_t s) {
+  biot_fs_opts opts;
+  opts.rtol = 1e-12; opts.max_outer = 1000; opts.inner_rtol = 1e-4; opts.inner_maxit = 500;
+  if (o) opts = *o;
+  if (!(opts.rtol > 0) || !std::isfinite(opts.rtol)) throw BiotError{BIOT_ERR_ARG, "rtol must be > 0"};
+  if (!(opts.inner_rtol > 0) || !(opts.inner_rtol < 1)) throw BiotError{BIOT_ERR_ARG, "inner_rtol must be in (0, 1)"};
+  if (opts.max_outer < 1 || opts.inner_maxit < 1) throw BiotError{BIOT_ERR_ARG, "iteration limits must be >= 1"};
+  PrecData* P = h->prec;
+  auto& B = P->b64;
+  const int cnt = h->count, nl = h->nl;
+  const long long S = h->slab_len;
+  double* R = B.bin;   // outer residual / sub-system right-hand side
+  double* D = B.xin;   // sub-system correction
+  const long long lines = (long long)cnt * nl * P->maxlines;
+  const int qdeg = (P->maxcells_line <= kPcrMaxCells || lines >= kLineSolveMinLines) ? 0 : kQDegDefault;
+  std::vector<double> bn, rn;
+  seg_norms<double>(P, b, cnt, s, bn);
+  for (int k = 0; k < cnt; ++k)
+    if (!std::isfinite(bn[k])) throw BiotError{BIOT_ERR_NONFINITE, "right-hand side is not finite"};
+  std::vector<int> its, rst, st, fl(cnt, 0), me(cnt, 0), outer(cnt, 0);
+  std::vector<double> rr;
+  std::vector<char> done(cnt, 0);
+  for (int it = 0;; ++it) {
+    residual<double>(h, b, x, R, 0, s);
+    seg_norms<double>(P, R, cnt, s, rn);
+    bool all = true;
+    for (int k = 0; k < cnt; ++k) {
+      if (!std::isfinite(rn[k])) throw BiotError{BIOT_ERR_NONFINITE, "non-finite residual"};
+      if (bn[k] == 0.0 || rn[k] <= opts.rtol * bn[k]) done[k] = 1;
+      all = all && done[k];
+    }
+    if (all || it == opts.max_outer) break;
+    for (int k = 0; k < cnt; ++k) if (!done[k]) ++outer[k];
+    for (int sys : {kSysFlow, kSysMech}) {
+      if (sys == kSysMech) residual<double>(h, b, x, R, 0, s);
+      launch_zero_rows<double>(h->d_inst, cnt, P->maxN, nl, sys == kSysFlow ? 0 : 1, R, s);
+      vfill<double>(D, 0.0, S, s);
+      SolveCtl ctl{opts.inner_rtol, opts.inner_maxit, 30, qdeg, true};
+      ctl.sys = sys;
+      gmres<double>(h, R, D, 0, ctl, its, rst, rr, st, s);
+      for (int k = 0; k < cnt; ++k) (sys == kSysFlow ? fl : me)[k] += its[k];
+      vaxpby<double>(1.0, D, 1.0, x, S, s);
+    }
+  }
+  for (int k = 0; k < cnt; ++k) {
+    info[k].outer = outer[k]; info[k].flow_iterations = fl[k]; info[k].mech_iterations = me[k];
+    info[k].rel_residual = bn[k] > 0 ? rn[k] / bn[k] : 0.0;
+    info[k].status = done[k] ? BIOT_OK : BIOT_ERR_NOCONV;
   }
 }
 
@@ -1739,6 +1842,29 @@ static biot_status solve_common(biot_problem h, const double* rhs, double* x, in
 biot_status solve_slab(biot_problem h, const double* rhs, double* x, const biot_solve_opts* opts,
                        biot_solve_info* info, void* stream) {
   return solve_common(h, rhs, x, 0, opts, info, stream);
+}
+
+biot_status solve_slab_fixed_stress(biot_problem h, const double* rhs, double* x, const biot_fs_opts* opts,
+                                    biot_fs_info* info, void* stream) {
+  try {
+    need(h, "handle is null");
+    need(rhs && x, "rhs and x must be device pointers");
+    need(info, "info is null");
+    h->prec->have_prev = false;
+    fixed_stress_impl(h, rhs, x, opts, info, (hipStream_t)stream);
+    hip_check(hipStreamSynchronize((hipStream_t)stream), "fixed-stress sync");
+    biot_status w = BIOT_OK;
+    for (int k = 0; k < h->count; ++k)
+      if (info[k].status != BIOT_OK) w = (biot_status)info[k].status;
+    if (w != BIOT_OK) set_error("the fixed-stress iteration did not reach the tolerance");
+    return w;
+  } catch (const BiotError& e) {
+    set_error(e.msg);
+    return e.st;
+  } catch (const std::exception& e) {
+    set_error(std::string("internal error: ") + e.what());
+    return BIOT_ERR_ARG;
+  }
 }
 
 biot_status solve_slab_transposed(biot_problem h, const double* rhs, double* x, const biot_solve_opts* opts,

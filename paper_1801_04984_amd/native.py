@@ -25,7 +25,7 @@ EXPORTS = [
     "biot_workspace_bytes", "create_slab_problem", "destroy_slab_problem", "biot_set_log_k",
     "biot_sizes", "biot_totals", "apply_operator", "slab_rhs", "solve_slab",
     "solve_slab_transposed", "step", "adjoint_sweep", "biot_misfit", "biot_autotune",
-    "biot_get_tuning", "biot_set_tuning", "biot_misfit_noalloc", "biot_elasticity_apply", "biot_last_error",
+    "biot_get_tuning", "biot_set_tuning", "biot_misfit_noalloc", "biot_elasticity_apply", "solve_slab_fixed_stress", "biot_last_error",
 ]
 
 
@@ -55,6 +55,20 @@ class SolveInfo(ctypes.Structure):
 
     def as_dict(self):
         return dict(iterations=self.iterations, restarts=self.restarts, ir_sweeps=self.ir_sweeps,
+                    status=self.status, rel_residual=self.rel_residual)
+
+
+class FsOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
+                ("inner_maxit", ctypes.c_int32)]
+
+
+class FsInfo(ctypes.Structure):
+    _fields_ = [("outer", ctypes.c_int32), ("flow_iterations", ctypes.c_int32), ("mech_iterations", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("rel_residual", ctypes.c_double)]
+
+    def as_dict(self):
+        return dict(outer=self.outer, flow_iterations=self.flow_iterations, mech_iterations=self.mech_iterations,
                     status=self.status, rel_residual=self.rel_residual)
 
 
@@ -98,6 +112,7 @@ def load_library(path: str = LIB_PATH):
     lib.biot_totals.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.apply_operator.argtypes = [P, P, P, i32, i32, P]
     lib.biot_elasticity_apply.argtypes = [P, P, P, i32, P]
+    lib.solve_slab_fixed_stress.argtypes = [P, P, P, ctypes.POINTER(FsOpts), ctypes.POINTER(FsInfo), P]
     lib.slab_rhs.argtypes = [P, P, dbl, P, P]
     lib.solve_slab.argtypes = [P, P, P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), P]
     lib.solve_slab_transposed.argtypes = [P, P, P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), P]
@@ -125,7 +140,7 @@ def _check(status):
 PAIR_DROP, PAIR_PRESB, PAIR_SHIFT = 0, 1, 2
 
 
-def make_desc(wl, pair_mode=PAIR_DROP) -> Desc:
+def make_desc(wl, pair_mode=PAIR_DROP, L_fs=0.0) -> Desc:
     """Descriptor from a workloads.Workload."""
     d = Desc()
     d.dim = wl.dim
@@ -135,7 +150,7 @@ def make_desc(wl, pair_mode=PAIR_DROP) -> Desc:
     d.r = wl.r
     d.tau = wl.tau
     d.lam, d.mu, d.b, d.M, d.eta = wl.lam, wl.mu, wl.b, wl.M, wl.eta
-    d.L_fs = 0.0
+    d.L_fs = float(L_fs)
     d.load_kind = wl.load_kind
     d.load_s0 = wl.load_s0
     d.load_t_ramp = wl.load_t_ramp
@@ -162,14 +177,15 @@ def _stream(torch, device):
 class BiotSlab:
     """A handle over one or several (batched) slab problems on one GPU."""
 
-    def __init__(self, workloads: Sequence, log_k: Sequence[np.ndarray], device="cuda:0", pair_mode=PAIR_DROP):
+    def __init__(self, workloads: Sequence, log_k: Sequence[np.ndarray], device="cuda:0", pair_mode=PAIR_DROP,
+                 L_fs=0.0):
         import torch
         self.torch = torch
         self.lib = load_library()
         self.device = torch.device(device)
         self.wls = list(workloads)
         self.count = len(self.wls)
-        self.descs = (Desc * self.count)(*[make_desc(w, pair_mode) for w in self.wls])
+        self.descs = (Desc * self.count)(*[make_desc(w, pair_mode, L_fs) for w in self.wls])
         self._logk = [np.ascontiguousarray(np.asarray(k, dtype=np.float64)) for k in log_k]
         arr = (ctypes.POINTER(ctypes.c_double) * self.count)(
             *[k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for k in self._logk])
@@ -254,6 +270,16 @@ class BiotSlab:
         infos = (SolveInfo * self.count)()
         fn = self.lib.solve_slab_transposed if transpose else self.lib.solve_slab
         st = fn(self.h, _ptr(rhs), _ptr(x), ctypes.byref(opts), infos, self._stream())
+        return x, [i.as_dict() for i in infos], st
+
+    def solve_fixed_stress(self, rhs, x=None, rtol=1e-12, max_outer=1000, inner_rtol=1e-4, inner_maxit=500):
+        """Fixed-stress iterative coupling of the slab system (solve_slab_fixed_stress)."""
+        if x is None:
+            x = self.zeros_slab()
+        o = FsOpts()
+        o.rtol, o.max_outer, o.inner_rtol, o.inner_maxit = rtol, max_outer, inner_rtol, inner_maxit
+        infos = (FsInfo * self.count)()
+        st = self.lib.solve_slab_fixed_stress(self.h, _ptr(rhs), _ptr(x), ctypes.byref(o), infos, self._stream())
         return x, [i.as_dict() for i in infos], st
 
     def step(self, nslabs, t_start, state, slabs_out=None, checkpoints=None, **opt):

@@ -32,5 +32,14 @@ int main(void) {
   printf("{\"name\": \"biot_tuning\", \"size\": %zu, \"fields\": {", sizeof(biot_tuning));
   F(biot_tuning, apply_variant); F(biot_tuning, n_variants); F(biot_tuning, apply_us);
   printf("}}\n");
+  first = 1;
+  printf("{\"name\": \"biot_fs_opts\", \"size\": %zu, \"fields\": {", sizeof(biot_fs_opts));
+  F(biot_fs_opts, rtol); F(biot_fs_opts, max_outer); F(biot_fs_opts, inner_rtol); F(biot_fs_opts, inner_maxit);
+  printf("}}\n");
+  first = 1;
+  printf("{\"name\": \"biot_fs_info\", \"size\": %zu, \"fields\": {", sizeof(biot_fs_info));
+  F(biot_fs_info, outer); F(biot_fs_info, flow_iterations); F(biot_fs_info, mech_iterations);
+  F(biot_fs_info, status); F(biot_fs_info, rel_residual);
+  printf("}}\n");
   return 0;
 }

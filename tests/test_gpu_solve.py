@@ -427,3 +427,49 @@ def test_pair_modes_reach_the_oracle(d, n, r):
                 its[(mode, transpose, precision)] = info[0]["iterations"]
         h.close()
     print(f"d={d} n={n} r={r} iterations (mode, transposed, precision): {its}")
+
+
+@pytest.mark.parametrize("d,n,r", [(2, (12, 10), 0), (2, (16, 11), 1), (2, (12, 9), 2), (3, (4, 3, 4), 1)])
+def test_fixed_stress_coupling_reaches_the_oracle(d, n, r):
+    """The standalone fixed-stress iterative coupling (flow with the fixed-stress
+    term, then mechanics, in turn) converges to the slab solution: the oracle's
+    LU solution per field <= 1e-10, and the monolithic GMRES solution."""
+    torch = torch_cuda()
+    wl = small_workload(d, n, r, seed=130 + d + r)
+    h, (prob,) = make_pair([wl])
+    b = _rhs(prob, seed=14)
+    ref = prob.solve(b)
+    x, info, st = h.solve_fixed_stress(torch.tensor(b, device="cuda"), rtol=1e-13)
+    assert st == 0 and info[0]["rel_residual"] <= 1e-13, info
+    err = field_rel(prob, x.cpu().numpy(), ref)
+    assert max(err.values()) < TOL, (err, info)
+    xm, infm, stm = h.solve(torch.tensor(b, device="cuda"), rtol=RT)
+    assert stm == 0
+    err = field_rel(prob, x.cpu().numpy(), xm.cpu().numpy())
+    assert max(err.values()) < TOL, err
+    print(f"d={d} n={n} r={r}: fixed-stress {info[0]}, monolithic GMRES {infm[0]['iterations']} iterations")
+    h.close()
+
+
+def test_fixed_stress_parameter_scan():
+    """Outer iterations of the fixed-stress coupling against L: every L >= b^2 / (2 K_dr)
+    converges to the oracle's solution; the counts are printed for the record."""
+    torch = torch_cuda()
+    from paper_1801_04984_amd import BiotSlab
+    from oracle import slab
+    wl = small_workload(2, (16, 12), 1, seed=141)
+    theta = wl.log_k()
+    prob = slab.problem_from_workload(wl, theta=theta)
+    b = _rhs(prob, seed=15)
+    ref = prob.solve(b)
+    L0 = wl.b ** 2 / (wl.lam + wl.mu)
+    counts = {}
+    for f in (0.5, 0.75, 1.0, 1.5, 2.0):
+        h = BiotSlab([wl], [theta], L_fs=f * L0)
+        x, info, st = h.solve_fixed_stress(torch.tensor(b, device="cuda"), rtol=1e-12)
+        assert st == 0, (f, info)
+        err = field_rel(prob, x.cpu().numpy(), ref)
+        assert max(err.values()) < 1e-9, (f, err)
+        counts[f] = info[0]["outer"]
+        h.close()
+    print(f"fixed-stress outer iterations against L / (b^2 / K_dr): {counts}")

@@ -122,7 +122,8 @@ def test_binding_structs_match_header_layout(tmp_path):
     rows = [json.loads(l) for l in subprocess.run([exe], capture_output=True, text=True,
                                                   timeout=60).stdout.splitlines()]
     mirrors = {"biot_problem_desc": native.Desc, "biot_solve_opts": native.SolveOpts,
-               "biot_solve_info": native.SolveInfo, "biot_tuning": native.Tuning}
+               "biot_solve_info": native.SolveInfo, "biot_tuning": native.Tuning,
+               "biot_fs_opts": native.FsOpts, "biot_fs_info": native.FsInfo}
     assert sorted(r["name"] for r in rows) == sorted(mirrors)
     for row in rows:
         S = mirrors[row["name"]]
