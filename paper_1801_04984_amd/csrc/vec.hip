@@ -58,8 +58,8 @@ void vacc(const float* x, double* y, long long n, hipStream_t s) {
 // ---- segmented multi-dot: out[seg][k] = <V_k, w> over segment seg ------------
 // stage 1: block b of segment s reduces a fixed chunk for KB vectors
 constexpr int kDotThreads = 256;
-constexpr int kKB = 32;   // vectors per stage-1 launch: w is read once per 32
-template <typename TV, typename TW>
+constexpr int kKBMax = 32;   // vectors per stage-1 launch: w is read once per 32
+template <typename TV, typename TW, int kKB>
 __global__ __launch_bounds__(kDotThreads) void mdot_stage1(const TV* __restrict__ V, long long ldv, int k0, int nk,
                                                            const TW* __restrict__ w, const VSeg* __restrict__ segs,
                                                            int nchunk, double* __restrict__ partial) {
@@ -118,10 +118,15 @@ int dot_chunks(long long maxlen) {
 template <typename TV, typename TW>
 void seg_mdot(const TV* V, long long ldv, int nk, const TW* w, const VSeg* segs, int nseg, int nchunk,
               double* partial, double* out, hipStream_t s, double* hout) {
-  for (int k0 = 0; k0 < nk; k0 += kKB) {
-    int kk = nk - k0 < kKB ? nk - k0 : kKB;
-    hipLaunchKernelGGL((mdot_stage1<TV, TW>), dim3(nchunk, nseg), dim3(kDotThreads), 0, s, V, ldv, k0, kk, w, segs,
-                       nchunk, partial);
+  // groups of up to 32 vectors; a group of at most 8 takes the 8-wide kernel
+  for (int k0 = 0; k0 < nk; k0 += kKBMax) {
+    int kk = nk - k0 < kKBMax ? nk - k0 : kKBMax;
+    if (kk <= 8)
+      hipLaunchKernelGGL((mdot_stage1<TV, TW, 8>), dim3(nchunk, nseg), dim3(kDotThreads), 0, s, V, ldv, k0, kk, w,
+                         segs, nchunk, partial);
+    else
+      hipLaunchKernelGGL((mdot_stage1<TV, TW, kKBMax>), dim3(nchunk, nseg), dim3(kDotThreads), 0, s, V, ldv, k0, kk,
+                         w, segs, nchunk, partial);
   }
   hipLaunchKernelGGL(mdot_stage2, dim3(nk, nseg), dim3(256), 0, s, partial, nchunk, out, hout);
 }
@@ -135,7 +140,7 @@ template void seg_mdot<float, float>(const float*, long long, int, const float*,
 //   w <- w - sum_k c1[k] V_k,   partial dots <V_k, w> (k < K) and <w, w> (slot K)
 // over the same fixed chunks as mdot_stage1 (the V_k values of an element are
 // read once for both), reduced by mdot_stage2.
-template <typename TV, typename TW>
+template <typename TV, typename TW, int kFuseK>
 __global__ __launch_bounds__(kDotThreads) void gs_update_dot_kernel(const TV* __restrict__ V, long long ldv, int nk,
                                                                     const double* __restrict__ c1,
                                                                     TW* __restrict__ w, const VSeg* __restrict__ segs,
@@ -185,7 +190,7 @@ __global__ __launch_bounds__(kDotThreads) void gs_update_dot_kernel(const TV* __
 //   w <- f (w - sum_k c2[k] V_k),  f = 1 / sqrt(c2[K] - sum_k c2[k]^2)  (0 for a zero norm)
 // (c2[K] = |w|^2 before the update; the removed components are orthogonal, so the
 // norm after it follows by Pythagoras)
-template <typename TV, typename TW>
+template <typename TV, typename TW, int kFuseK>
 __global__ __launch_bounds__(256) void gs_update_scale_kernel(const TV* __restrict__ V, long long ldv, int nk,
                                                               const double* __restrict__ c2, TW* __restrict__ w,
                                                               const VSeg* __restrict__ segs) {
@@ -216,8 +221,16 @@ __global__ __launch_bounds__(256) void gs_update_scale_kernel(const TV* __restri
 template <typename TV, typename TW>
 void gs_update_dot(const TV* V, long long ldv, int nk, const double* c1, TW* w, const VSeg* segs, int nseg, int nchunk,
                    double* partial, double* out, hipStream_t s, double* hout) {
-  hipLaunchKernelGGL((gs_update_dot_kernel<TV, TW>), dim3(nchunk, nseg), dim3(kDotThreads), 0, s, V, ldv, nk, c1, w,
-                     segs, nchunk, partial);
+  // the unrolled width is the smallest of 8, 16, 32 that holds nk
+  if (nk <= 8)
+    hipLaunchKernelGGL((gs_update_dot_kernel<TV, TW, 8>), dim3(nchunk, nseg), dim3(kDotThreads), 0, s, V, ldv, nk,
+                       c1, w, segs, nchunk, partial);
+  else if (nk <= 16)
+    hipLaunchKernelGGL((gs_update_dot_kernel<TV, TW, 16>), dim3(nchunk, nseg), dim3(kDotThreads), 0, s, V, ldv, nk,
+                       c1, w, segs, nchunk, partial);
+  else
+    hipLaunchKernelGGL((gs_update_dot_kernel<TV, TW, kFuseK>), dim3(nchunk, nseg), dim3(kDotThreads), 0, s, V, ldv,
+                       nk, c1, w, segs, nchunk, partial);
   hipLaunchKernelGGL(mdot_stage2, dim3(nk + 1, nseg), dim3(256), 0, s, partial, nchunk, out, hout);
 }
 template <typename TV, typename TW>
@@ -225,7 +238,14 @@ void gs_update_scale(const TV* V, long long ldv, int nk, const double* c2, TW* w
                      long long maxlen, hipStream_t s) {
   long long b = (maxlen + 255) / 256;
   unsigned gx = (unsigned)(b > 2048 ? 2048 : (b < 1 ? 1 : b));
-  hipLaunchKernelGGL((gs_update_scale_kernel<TV, TW>), dim3(gx, nseg), dim3(256), 0, s, V, ldv, nk, c2, w, segs);
+  if (nk <= 8)
+    hipLaunchKernelGGL((gs_update_scale_kernel<TV, TW, 8>), dim3(gx, nseg), dim3(256), 0, s, V, ldv, nk, c2, w, segs);
+  else if (nk <= 16)
+    hipLaunchKernelGGL((gs_update_scale_kernel<TV, TW, 16>), dim3(gx, nseg), dim3(256), 0, s, V, ldv, nk, c2, w,
+                       segs);
+  else
+    hipLaunchKernelGGL((gs_update_scale_kernel<TV, TW, kFuseK>), dim3(gx, nseg), dim3(256), 0, s, V, ldv, nk, c2, w,
+                       segs);
 }
 template void gs_update_dot<double, double>(const double*, long long, int, const double*, double*, const VSeg*, int,
                                             int, double*, double*, hipStream_t, double*);
