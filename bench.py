@@ -3,7 +3,7 @@
 Default workload: 3D 48^3 hexahedra, dG(2) on right Gauss-Radau points,
 Q2/RT1/DG-Q1 (18,913,833 slab unknowns), log-normal K (sigma 1.5, correlation
 length 0.15), ramp load, tau = 0.1.  One step = one time slab: slab right-hand
-side, preconditioned GMRES solve to relative residual 1e-12 in FP64, state
+side, preconditioned GMRES solve to relative residual 1e-13 in FP64, state
 update.  The timed region holds exactly --steps slabs of the march (after
 --warmup untimed slabs) with all inputs resident on the GPU.
 
@@ -43,6 +43,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_MATRIX_PEAK_TFS = 78.6
 METRIC = "space-time DoF-applies/s and slab solve time at 1e-10 rel. err, FP64 vs mixed"
+# Relative residual tolerance of every timed slab solve.  On the 48^3 march the
+# late slabs' flux and pressure are a few hundred times smaller than at their
+# peak, and 1e-12 leaves them at ~3e-9 relative error (measured against a refined
+# reference); 1e-13 brings every path to ~1e-10 (the FP64 residual floor is
+# ~1.5e-13).  The per-field errors are measured and reported with every run.
+RTOL = 1e-13
 PMC_RECORD = os.path.join(ROOT, "profiles", "counters_pmc.json")
 
 
@@ -102,11 +108,13 @@ def measured_traffic(kernel_key):
         return None
 
 
-def march(h, nsteps, t0, state, precision, slabs_last=None):
+def march(h, nsteps, t0, state, precision, slabs_last=None, state_before_last=None):
     infos_all = []
     for k in range(nsteps):
         out = slabs_last if (slabs_last is not None and k == nsteps - 1) else None
-        infos, st = h.step(1, t0 + k * h.wls[0].tau, state, slabs_out=out, precision=precision)
+        if state_before_last is not None and k == nsteps - 1:
+            state_before_last.copy_(state)
+        infos, st = h.step(1, t0 + k * h.wls[0].tau, state, slabs_out=out, precision=precision, rtol=RTOL)
         if st != 0:
             raise RuntimeError(f"slab solve failed: {infos}")
         infos_all.append(infos)
@@ -129,6 +137,23 @@ def field_rel(h, a, b):
         nb = float(bb.norm())
         out[name] = float((aa - bb).norm()) / (nb if nb > 0 else 1.0)
     return out
+
+
+def slab_error(h, state_in, t, slab, sweeps=3):
+    """Per-field relative l2 error of a solved slab against a reference for the
+    same slab (same entering state): FP64 GMRES to its rounding floor, then FP64
+    iterative refinement (residual b - A x by the operator apply, correction by
+    GMRES to 1e-6 of it), which takes the residual below the GMRES floor.
+    Returns (errors, relative residual of the reference)."""
+    torch = h.torch
+    rhs = h.rhs(state_in, t)
+    ref, info, st = h.solve(rhs, rtol=1e-14, maxit=4000)
+    for _ in range(sweeps):
+        r = rhs - h.apply(ref)
+        d, _, _ = h.solve(r, rtol=1e-6, maxit=2000)
+        ref += d
+    res = float(torch.linalg.norm(rhs - h.apply(ref)) / torch.linalg.norm(rhs))
+    return field_rel(h, slab, ref), res
 
 
 def host_info():
@@ -183,10 +208,10 @@ def adjoint_timing(torch, W, h, nslabs, precision):
     chk = torch.zeros(nslabs * h.state_len, dtype=torch.float64, device=h.device)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos, st = h.step(nslabs, 0.0, state, checkpoints=chk, precision=precision)
+    infos, st = h.step(nslabs, 0.0, state, checkpoints=chk, precision=precision, rtol=RTOL)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    J, g, st2 = h.adjoint(nslabs, 0.0, chk, sens, p_obs, precision=precision)
+    J, g, st2 = h.adjoint(nslabs, 0.0, chk, sens, p_obs, precision=precision, rtol=RTOL)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     if st != 0 or st2 != 0:
@@ -224,8 +249,8 @@ def batched(torch, W, BiotSlab, tuning, nsteps=4, sample_every=8):
     chk = torch.zeros(nsteps * h.state_len, dtype=torch.float64, device=h.device)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos, st1 = h.step(nsteps, 0.0, state, checkpoints=chk)
-    J, g, st2 = h.adjoint(nsteps, 0.0, chk, sens, p_obs)
+    infos, st1 = h.step(nsteps, 0.0, state, checkpoints=chk, rtol=RTOL)
+    J, g, st2 = h.adjoint(nsteps, 0.0, chk, sens, p_obs, rtol=RTOL)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     if st1 != 0 or st2 != 0:
@@ -328,19 +353,22 @@ def main():
 
     state = h.zeros_state()
     last64 = h.zeros_slab()
+    before64 = h.zeros_state()
     march(h, args.warmup, 0.0, state, 0)
     torch.cuda.synchronize()
     t_start = args.warmup * wl.tau
+    t_last = t_start + (args.steps - 1) * wl.tau
     t0 = time.perf_counter()
-    infos = march(h, args.steps, t_start, state, 0, slabs_last=last64)
+    infos = march(h, args.steps, t_start, state, 0, slabs_last=last64, state_before_last=before64)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = args.steps * slab_dofs / dt
     its = [i[0]["iterations"] for i in infos]
+    err64, ref_res = slab_error(h, before64, t_last, last64)
     shape = "x".join(str(m) for m in wl.n)
 
     out = {
-        "metric": METRIC, "value": value, "unit": "space-time DoF/s (slab solved to rel. residual 1e-12, FP64)",
+        "metric": METRIC, "value": value, "unit": "space-time DoF/s (slab solved to rel. residual 1e-13, FP64)",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded log-normal permeability)",
@@ -348,6 +376,9 @@ def main():
                                f"log-normal K sigma={wl.k_sigma} ell={wl.k_ell} seed={wl.k_seed}, ramp load",
                    "slab_dofs": slab_dofs, "parallelism": "single GPU"},
         "gmres_iterations_per_slab": {"mean": float(np.mean(its)), "min": int(min(its)), "max": int(max(its))},
+        "last_slab_rel_l2_error": err64,
+        "error_reference": f"the same slab solved in FP64 to the GMRES floor, then FP64 iterative refinement "
+                           f"(reference relative residual {ref_res:.1e})",
         "apply_tile_variant": tune["apply_variant"],
     }
 
@@ -355,14 +386,16 @@ def main():
         for key, prec in (("mixed", 1), ("fp32_preconditioned", 2)):
             st2 = h.zeros_state()
             last = h.zeros_slab()
+            before = h.zeros_state()
             march(h, args.warmup, 0.0, st2, prec)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            inf2 = march(h, args.steps, t_start, st2, prec, slabs_last=last)
+            inf2 = march(h, args.steps, t_start, st2, prec, slabs_last=last, state_before_last=before)
             torch.cuda.synchronize()
             dt2 = time.perf_counter() - t1
             out[key] = {"value": args.steps * slab_dofs / dt2, "ms_per_step": 1e3 * dt2 / args.steps,
                         "speedup_vs_fp64": dt / dt2,
+                        "last_slab_rel_l2_error": slab_error(h, before, t_last, last)[0],
                         "last_slab_rel_l2_vs_fp64": field_rel(h, last, last64),
                         "end_state_rel_l2_vs_fp64": field_rel(h, st2, state),
                         "iterations_per_slab": float(np.mean([i[0]["iterations"] for i in inf2])),
