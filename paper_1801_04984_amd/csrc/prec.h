@@ -24,32 +24,24 @@ struct ChebCoef {      // one launch: init scale or step coefficients
   double bsign;        // init: r = bsign * b (- S x)
 };
 
-// complex-pair level blocks (levels j, j+1 of the real block eigenbasis,
-// Q^-1 T Q = [[alpha, beta], [-beta, alpha]] there, beta > 0)
+// complex-pair level blocks: Q^-1 T Q = [[alpha, beta], [-beta, alpha]] on the
+// levels (j, j2) of a pair, beta > 0 (pairs.hip)
 struct PairSet {
   int n;               // number of pairs (0..2)
   int j[2];            // first level of each pair
+  int j2[2];           // its second level
   double beta[2];
 };
+// transpose selects the block of the slab transpose in the basis Q^-T
 template <typename T>
-void launch_pair_split(const InstDev* insts, int count, long long maxN, const PairSet& ps, T* r, T* save,
+void launch_pair_split(const InstDev* insts, int count, long long maxN, const PairSet& ps, int transpose, T* r,
                        hipStream_t s);
 template <typename T>
-void launch_pair_couple(int dim, const InstDev* insts, int count, long long maxN, const PairSet& ps, const T* z,
-                        T* save, T* r, hipStream_t s);
+void launch_pair_couple(int dim, const InstDev* insts, int count, long long maxN, const PairSet& ps, int transpose,
+                        const T* z, T* save, T* r, hipStream_t s);
 template <typename T>
-void launch_pair_join(const InstDev* insts, int count, long long maxN, const PairSet& ps, const T* save, T* z,
-                      hipStream_t s);
-// the same for the transposed pair block [[L^T, -beta M_t^T], [beta M_t^T, L^T]]
-template <typename T>
-void launch_pair_split_t(const InstDev* insts, int count, long long maxN, const PairSet& ps, T* r, T* save,
-                         hipStream_t s);
-template <typename T>
-void launch_pair_couple_t(int dim, const InstDev* insts, int count, long long maxN, const PairSet& ps, const T* z,
-                          T* save, T* r, hipStream_t s);
-template <typename T>
-void launch_pair_join_t(const InstDev* insts, int count, long long maxN, const PairSet& ps, const T* save, T* z,
-                        hipStream_t s);
+void launch_pair_join(const InstDev* insts, int count, long long maxN, const PairSet& ps, int transpose, const T* save,
+                      T* z, hipStream_t s);
 
 // fixed-stress sub-systems (fixed_stress.hip): y += -L Mp (T p) on the p-rows with the
 // u-rows cleared; zero_rows clears the u-rows (which = 0) or the q- and p-rows (1)

@@ -61,7 +61,7 @@ struct PrecBufs {
   T* V = nullptr;
   T *w = nullptr, *t = nullptr, *r = nullptr;
   T *Wr = nullptr, *Wz = nullptr, *Wf = nullptr, *T1 = nullptr, *T2 = nullptr, *T3 = nullptr, *T4 = nullptr;
-  T* Ws = nullptr;   // complex-pair blocks solved with their couplings: w and g (levels j, j+1)
+  T* Ws = nullptr;   // complex-pair blocks solved with their couplings: w (first level of each pair)
   T* dqinv = nullptr;
   T* pdg_dinv = nullptr;
   std::vector<T*> pc_x, pc_b, pc_r, pc_d0, pc_d1, pc_coef, pc_dinv;
@@ -76,6 +76,11 @@ struct PrecData {
   // complex-pair level blocks (biot_pair_mode) and the pairs of the real block form
   int pair_mode = BIOT_PAIR_DROP;
   PairSet pairs{};
+  // preconditioner level k is column lperm[k] of the real block eigenbasis, with its
+  // alpha and beta (square-block factorisation: pair firsts, real levels, pair seconds;
+  // otherwise the eigenbasis order)
+  int lperm[4] = {0, 1, 2, 3};
+  double lalpha[4] = {0, 0, 0, 0}, lbeta[4] = {0, 0, 0, 0};
   // pressure hierarchy
   int npl = 0;
   std::vector<PDgSeg> pdg;
@@ -233,7 +238,7 @@ static void build_hierarchy(biot_problem_s* h, PrecData* P) {
     const double L = D.L_fs > 0 ? D.L_fs : D.b * D.b / kdr;
     // level shift: alpha_j, or alpha_j + |beta_j| on complex-pair levels unless their couplings are dropped
     for (int j = 0; j < 4; ++j) {
-      const double sh = h->tc.alpha[j] + (P->pair_mode == BIOT_PAIR_DROP ? 0.0 : std::fabs(h->tc.beta[j]));
+      const double sh = P->lalpha[j] + (P->pair_mode == BIOT_PAIR_DROP ? 0.0 : std::fabs(P->lbeta[j]));
       s.cm[j] = (j < nl) ? sh * (1.0 / D.M + L) : 0.0;
     }
     P->pdg.push_back(s);
@@ -535,12 +540,31 @@ void plan_solver_layout(biot_problem_s* h, Layout& L, bool carve) {
   }
   P->pair_mode = h->descs[0].pair_mode;
   P->pairs = PairSet{};
+  int first[2] = {0, 0}, npair = 0;
   for (int j = 0; j + 1 < h->nl; ++j)
-    if (h->tc.beta[j] > 0 && P->pairs.n < 2) {   // columns j, j+1: alpha_j +- i beta_j
-      P->pairs.j[P->pairs.n] = j;
-      P->pairs.beta[P->pairs.n] = h->tc.beta[j];
-      ++P->pairs.n;
+    if (h->tc.beta[j] > 0 && npair < 2) first[npair++] = j;   // columns j, j+1: alpha_j +- i beta_j
+  for (int k = 0; k < 4; ++k) P->lperm[k] = k;
+  if (P->pair_mode == BIOT_PAIR_PRESB && npair > 0) {
+    int k = 0;
+    for (int i = 0; i < npair; ++i) P->lperm[k++] = first[i];
+    for (int j = 0; j < h->nl; ++j) {
+      bool in_pair = false;
+      for (int i = 0; i < npair; ++i) in_pair = in_pair || j == first[i] || j == first[i] + 1;
+      if (!in_pair) P->lperm[k++] = j;
     }
+    for (int i = 0; i < npair; ++i) P->lperm[k++] = first[i] + 1;
+  }
+  for (int k = 0; k < 4; ++k) {
+    P->lalpha[k] = h->tc.alpha[P->lperm[k]];
+    P->lbeta[k] = h->tc.beta[P->lperm[k]];
+  }
+  for (int i = 0; i < npair; ++i)
+    for (int k = 0; k < h->nl; ++k) {
+      if (P->lperm[k] == first[i]) P->pairs.j[i] = k;
+      if (P->lperm[k] == first[i] + 1) P->pairs.j2[i] = k;
+    }
+  for (int i = 0; i < npair; ++i) P->pairs.beta[i] = h->tc.beta[first[i]];
+  P->pairs.n = npair;
   build_hierarchy(h, P);
   carve_bufs<double>(h, P, P->b64, L, false);
   carve_bufs<float>(h, P, P->b32, L, true);
@@ -927,9 +951,14 @@ void setup_solver(biot_problem_s* h, hipStream_t s) {
   upload(P->gju, P->d_gju, s);
   upload(P->gjp, P->d_gjp, s);
   upload(P->gseg, P->d_gseg, s);
-  for (int j = 0; j < 16; ++j) { P->Q.m[j] = h->tc.Q[j]; P->Qi.m[j] = h->tc.Qi[j]; }
+  // level k = eigenbasis column lperm[k]: Q's columns and Q^-1's rows in level order
   for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) { P->Qt.m[i * 4 + j] = h->tc.Q[j * 4 + i]; P->Qit.m[i * 4 + j] = h->tc.Qi[j * 4 + i]; }
+    for (int k = 0; k < 4; ++k) {
+      P->Q.m[i * 4 + k] = h->tc.Q[i * 4 + P->lperm[k]];
+      P->Qi.m[k * 4 + i] = h->tc.Qi[P->lperm[k] * 4 + i];
+    }
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) { P->Qt.m[i * 4 + j] = P->Q.m[j * 4 + i]; P->Qit.m[i * 4 + j] = P->Qi.m[j * 4 + i]; }
   // initial guess of the next slab: the previous slab's solution extrapolated
   // linearly in time through its last two Radau levels (r >= 1), or its end
   // value (r = 0), evaluated at the next slab's levels 1 + s_i (units of tau)
@@ -974,10 +1003,10 @@ void destroy_solver(biot_problem_s* h) {
 // the preconditioner  z = P^-1 r  (vectors of type T)
 // ---------------------------------------------------------------------------
 template <typename T>
-static void p_vcycle(biot_problem_s* h, int l, hipStream_t s) {
+static void p_vcycle(biot_problem_s* h, int l, int nl, hipStream_t s) {
   PrecData* P = h->prec;
   auto& B = bufs<T>(P);
-  const int nl = h->nl, cnt = h->count;
+  const int cnt = h->count;
   const int pd = pdeg(h->dim);
   const ChebSeq cs = cheb_seq(kPLo, kPHi, pd);
   if (l == P->npl - 1) {
@@ -994,7 +1023,7 @@ static void p_vcycle(biot_problem_s* h, int l, hipStream_t s) {
                     B.pc_dinv[l], b, x, r, (k & 1) ? d1 : d0, (k & 1) ? d0 : d1, s);
   }
   launch_p_restrict_cell<T>(sg, P->d_pc[l + 1], cnt, nl, P->pc_max[l + 1], r, B.pc_b[l + 1], s);
-  p_vcycle<T>(h, l + 1, s);
+  p_vcycle<T>(h, l + 1, nl, s);
   launch_p_prolong_cell<T>(sg, P->d_pc[l + 1], cnt, nl, mx, omega_p(h->dim), B.pc_x[l + 1], x, s);
   launch_pcell<T>(sg, cnt, nl, mx, kResInit, ChebCoef{cs.s0, 0, 0, 1}, B.pc_coef[l], B.pc_dinv[l], b, x, r, nullptr,
                   d0, s);
@@ -1004,12 +1033,12 @@ static void p_vcycle(biot_problem_s* h, int l, hipStream_t s) {
   }
 }
 
-// S_j y = bsign * b on the DG level (x, b: slab layout p-blocks)
+// S_j y = bsign * b on the DG level (x, b: slab layout p-blocks), levels j < nl
 template <typename T>
-static void p_solve(biot_problem_s* h, const T* b, T* x, hipStream_t s) {
+static void p_solve(biot_problem_s* h, const T* b, T* x, int nl, hipStream_t s) {
   PrecData* P = h->prec;
   auto& B = bufs<T>(P);
-  const int nl = h->nl, cnt = h->count, d = h->dim;
+  const int cnt = h->count, d = h->dim;
   const int pd = pdeg(h->dim);
   const ChebSeq cs = cheb_seq(kPLo, kPHi, pd);
   T *r = B.T1, *d0 = B.T2, *d1 = B.T3;
@@ -1020,7 +1049,7 @@ static void p_solve(biot_problem_s* h, const T* b, T* x, hipStream_t s) {
                   ChebCoef{0, cs.steps[k].first, cs.steps[k].second, -1}, B.dqinv, B.pdg_dinv, b, x, r,
                   (k & 1) ? d1 : d0, (k & 1) ? d0 : d1, s);
   launch_p_restrict_dg<T>(h->d_inst, P->d_pdg, P->d_pc[0], cnt, nl, P->pc_max[0], r, B.pc_b[0], s);
-  p_vcycle<T>(h, 0, s);
+  p_vcycle<T>(h, 0, nl, s);
   launch_p_prolong_dg<T>(h->d_inst, P->d_pdg, P->d_pc[0], cnt, nl, P->pdg_max, omega_p(h->dim), B.pc_x[0], x, s);
   launch_pdg<T>(d, h->d_inst, P->d_pdg, cnt, nl, P->pdg_max, kResInit, ChebCoef{cs.s0, 0, 0, -1}, B.dqinv,
                 B.pdg_dinv, b, x, r, nullptr, d0, s);
@@ -1030,12 +1059,13 @@ static void p_solve(biot_problem_s* h, const T* b, T* x, hipStream_t s) {
                   (k & 1) ? d1 : d0, (k & 1) ? d0 : d1, s);
 }
 
-// one V-cycle for tau A_l x = b at u level l (level 0: slab layout buffers given)
+// one V-cycle for tau A_l x = b at u level l (level 0: slab layout buffers given),
+// time levels j < nl
 template <typename T>
-static void u_vcycle(biot_problem_s* h, int l, T* x, const T* b, T* r, T* d0, T* y, hipStream_t s) {
+static void u_vcycle(biot_problem_s* h, int l, int nl, T* x, const T* b, T* r, T* d0, T* y, hipStream_t s) {
   PrecData* P = h->prec;
   auto& B = bufs<T>(P);
-  const int nl = h->nl, cnt = h->count, d = h->dim;
+  const int cnt = h->count, d = h->dim;
   const int ud = udeg(d);
   const ChebSeq cs = cheb_seq(kULo, kUHi, ud);
   if (l == P->nul - 1) {
@@ -1061,7 +1091,7 @@ static void u_vcycle(biot_problem_s* h, int l, T* x, const T* b, T* r, T* d0, T*
     launch_rpass<T>(P->d_rp[l][pass], cnt, nl, P->rp_max[l][pass], P->d_utab, in, out, s);
     in = out;
   }
-  u_vcycle<T>(h, l + 1, B.u_x[l + 1], B.u_b[l + 1], B.u_r[l + 1], B.u_d0[l + 1], B.u_y[l + 1], s);
+  u_vcycle<T>(h, l + 1, nl, B.u_x[l + 1], B.u_b[l + 1], B.u_r[l + 1], B.u_d0[l + 1], B.u_y[l + 1], s);
   launch_uprolong<T>(P->d_up[l], cnt, nl, mx, P->d_utab, B.u_x[l + 1], x, s);
   // post-smoothing
   launch_uapply<T>(d, gs, work, nwork, nl, 1, x, b, r, uemat<T>(P), s, P->utile[l]);
@@ -1072,23 +1102,24 @@ static void u_vcycle(biot_problem_s* h, int l, T* x, const T* b, T* r, T* d0, T*
   }
 }
 
-// the fixed-stress level solves, every level j at once: B.Wr -> B.Wz (B.Wr is read only).
+// the fixed-stress level solves of the levels j < nl at once: B.Wr -> B.Wz (B.Wr is read only).
 // transpose: the blocks L_j^T.  Their pressure Schur complement (with the
 // fixed-stress term) is that of L_j, and the sweep differs only in the
 // displacement right-hand side, r_u + c_j b E p with c_j = the level shift
 // instead of tau (the u-p couplings of L_j^T carry the coefficients of L_j's
 // p-u couplings).
 template <typename T>
-static void level_solves(biot_problem_s* h, int qdeg, int transpose, hipStream_t s, bool flow_only = false) {
+static void level_solves(biot_problem_s* h, int nl, int qdeg, int transpose, hipStream_t s,
+                         bool flow_only = false) {
   PrecData* P = h->prec;
   auto& B = bufs<T>(P);
-  const int nl = h->nl, cnt = h->count, d = h->dim;
+  const int cnt = h->count, d = h->dim;
   // 1) pressure: S_j p = -r_p
-  p_solve<T>(h, B.Wr, B.Wz, s);
+  p_solve<T>(h, B.Wr, B.Wz, nl, s);
   // 2) coupling right-hand sides
   LevelCoef cu{};
   for (int j = 0; j < 4; ++j)
-    cu.c[j] = transpose ? h->tc.alpha[j] + (P->pair_mode == BIOT_PAIR_DROP ? 0.0 : std::fabs(h->tc.beta[j]))
+    cu.c[j] = transpose ? P->lalpha[j] + (P->pair_mode == BIOT_PAIR_DROP ? 0.0 : std::fabs(P->lbeta[j]))
                         : h->descs[0].tau;
   launch_coupling<T>(d, h->d_inst, cnt, nl, P->maxN, cu, B.Wr, B.Wz, B.Wf, B.Wf, s);
   // 3) flux: tau Mq q = f_q  (exact line solves, or Chebyshev-Jacobi of degree qdeg on the Gershgorin interval)
@@ -1103,7 +1134,7 @@ static void level_solves(biot_problem_s* h, int qdeg, int transpose, hipStream_t
                    B.kinv, nullptr, B.Wf, B.Wz, B.T1, (k & 1) ? B.T3 : B.T2, (k & 1) ? B.T2 : B.T3, s);
   }
   // 4) mechanics: tau A u = f_u  (one V-cycle)
-  if (!flow_only) u_vcycle<T>(h, 0, B.Wz, B.Wf, B.T1, B.T2, B.T4, s);
+  if (!flow_only) u_vcycle<T>(h, 0, nl, B.Wz, B.Wf, B.T1, B.T2, B.T4, s);
 }
 
 // Sub-systems of the fixed-stress iterative coupling (fixed_stress.hip): 0 = the slab
@@ -1125,7 +1156,7 @@ static void apply_prec(biot_problem_s* h, const T* rin, T* z, int qdeg, int tran
     vfill<T>(B.Wz, T(0), h->slab_len, s);
     LevelCoef cu{};
     launch_coupling<T>(d, h->d_inst, cnt, nl, P->maxN, cu, rin, B.Wz, B.Wf, B.Wf, s);   // f_u: essential rows 0
-    u_vcycle<T>(h, 0, B.Wz, B.Wf, B.T1, B.T2, B.T4, s);
+    u_vcycle<T>(h, 0, nl, B.Wz, B.Wf, B.T1, B.T2, B.T4, s);
     Mat4 id{};
     for (int i = 0; i < 4; ++i) id.m[i * 5] = 1.0;
     launch_prec_finalize<T>(h->d_inst, cnt, P->maxN, nl, id, B.Wz, rin, z, s);
@@ -1137,26 +1168,26 @@ static void apply_prec(biot_problem_s* h, const T* rin, T* z, int qdeg, int tran
   if (sys == kSysFlow) {
     // the flow part of every level solve (pressure Schur cycle, then the flux lines); the
     // pair couplings are dropped
-    level_solves<T>(h, qdeg, transpose, s, true);
+    level_solves<T>(h, nl, qdeg, transpose, s, true);
     launch_prec_finalize<T>(h->d_inst, cnt, P->maxN, nl, P->Q, B.Wz, rin, z, s);
     launch_zero_rows<T>(h->d_inst, cnt, P->maxN, nl, 0, z, s);
     return;
   }
   if (P->pair_mode == BIOT_PAIR_PRESB && P->pairs.n > 0) {
     // pair blocks with their couplings (square-block factorisation), forward:
-    // w = H^-1 (f - g), y = H^-1 (g + beta M_t w), x = w + y; transposed:
-    // w = H^-T (f + g), y = H^-T (g - beta M_t^T w), x = w - y.  The second pass
-    // repeats the real levels' solves on unchanged right-hand sides.
-    if (transpose) launch_pair_split_t<T>(h->d_inst, cnt, P->maxN, P->pairs, B.Wr, B.Ws, s);
-    else launch_pair_split<T>(h->d_inst, cnt, P->maxN, P->pairs, B.Wr, B.Ws, s);
-    level_solves<T>(h, qdeg, transpose, s);
-    if (transpose) launch_pair_couple_t<T>(d, h->d_inst, cnt, P->maxN, P->pairs, B.Wz, B.Ws, B.Wr, s);
-    else launch_pair_couple<T>(d, h->d_inst, cnt, P->maxN, P->pairs, B.Wz, B.Ws, B.Wr, s);
-    level_solves<T>(h, qdeg, transpose, s);
-    if (transpose) launch_pair_join_t<T>(h->d_inst, cnt, P->maxN, P->pairs, B.Ws, B.Wz, s);
-    else launch_pair_join<T>(h->d_inst, cnt, P->maxN, P->pairs, B.Ws, B.Wz, s);
+    // w = H^-1 (f - g), y = H^-1 (g + beta M_t w), x = (w + y, y); transposed:
+    // w = H^-T (f + g), y = H^-T (g - beta M_t^T w), x = (w - y, y).  The levels
+    // are ordered pair firsts, real levels, pair seconds: the first pass solves
+    // the w of every pair with the real levels, the second the y of every pair
+    // in the pair firsts' slots (same shift alpha + beta).
+    const int np = P->pairs.n;
+    launch_pair_split<T>(h->d_inst, cnt, P->maxN, P->pairs, transpose, B.Wr, s);
+    level_solves<T>(h, nl - np, qdeg, transpose, s);
+    launch_pair_couple<T>(d, h->d_inst, cnt, P->maxN, P->pairs, transpose, B.Wz, B.Ws, B.Wr, s);
+    level_solves<T>(h, np, qdeg, transpose, s);
+    launch_pair_join<T>(h->d_inst, cnt, P->maxN, P->pairs, transpose, B.Ws, B.Wz, s);
   } else {
-    level_solves<T>(h, qdeg, transpose, s);
+    level_solves<T>(h, nl, qdeg, transpose, s);
   }
   // back to the nodal time basis; essential rows pass through
   launch_prec_finalize<T>(h->d_inst, cnt, P->maxN, nl, transpose ? P->Qit : P->Q, B.Wz, rin, z, s);
