@@ -78,18 +78,29 @@ typedef enum { BIOT_LOAD_STEP = 0, BIOT_LOAD_RAMP = 1 } biot_load_kind;
  * Approach": a complex eigenvalue alpha +- i beta of the temporal matrix gives
  * a 2x2 level block [[L, beta M_t], [-beta M_t, L]], L = alpha M_t + tau K_s,
  * whose off-diagonal blocks are the paper's C^+-).
- * BIOT_PAIR_DROP (default): couplings dropped, each level solved with the
- *   shift alpha ("diagonal blockwise").
+ * BIOT_PAIR_AUTO (default): BIOT_PAIR_PRESB for dim == 3 and r >= 2, else
+ *   BIOT_PAIR_DROP (the faster of the two in every measured case: in 3D at
+ *   dG(2) and dG(3) the kept couplings save 15-30% of the iterations for a
+ *   second, serial pass of level solves; in 2D and at dG(1) that pass costs
+ *   more than the iterations it saves).
+ * BIOT_PAIR_DROP: couplings dropped, each level solved with the shift alpha
+ *   ("diagonal blockwise").
  * BIOT_PAIR_PRESB: couplings kept; the block is solved by the preconditioned
  *   square-block factorisation, two level solves with the shift alpha + beta
- *   (one after the other; the preconditioner then takes two passes over all
- *   levels) and one M_t product.
+ *   one after the other, and one M_t product.  The preconditioner still costs
+ *   one level solve per level, in two passes: the first solves of the pairs
+ *   with the real levels, then the second solves of the pairs.
  * BIOT_PAIR_SHIFT: couplings dropped, each level solved with the shift
  *   alpha + beta.
  * Real eigenvalues always give one level solve with their own shift.  The
  * mode changes iteration counts, never the solution.  Transposed solves use
  * the transposed blocks in the eigenbasis of T^T. */
-typedef enum { BIOT_PAIR_DROP = 0, BIOT_PAIR_PRESB = 1, BIOT_PAIR_SHIFT = 2 } biot_pair_mode;
+typedef enum {
+  BIOT_PAIR_AUTO = 0,
+  BIOT_PAIR_DROP = 1,
+  BIOT_PAIR_PRESB = 2,
+  BIOT_PAIR_SHIFT = 3
+} biot_pair_mode;
 
 /* One problem instance.  Section "Poroelasticity": isotropic C (lambda, mu),
  * Biot coefficient 0 < b < 1, Biot modulus M > 0, viscosity eta; cellwise

@@ -58,7 +58,7 @@ static void validate_desc(const biot_problem_desc& d, int idx) {
   if (!fin(d.M) || d.M <= 0) arg_fail(os.str() + "Biot modulus M must be > 0");
   if (!fin(d.eta) || d.eta <= 0) arg_fail(os.str() + "viscosity eta must be > 0");
   if (!fin(d.L_fs)) arg_fail(os.str() + "L_fs must be finite");
-  if (d.pair_mode != BIOT_PAIR_DROP && d.pair_mode != BIOT_PAIR_PRESB && d.pair_mode != BIOT_PAIR_SHIFT)
+  if (d.pair_mode < BIOT_PAIR_AUTO || d.pair_mode > BIOT_PAIR_SHIFT)
     arg_fail(os.str() + "unknown pair_mode");
   if (d.load_kind != BIOT_LOAD_STEP && d.load_kind != BIOT_LOAD_RAMP) arg_fail(os.str() + "unknown load_kind");
   if (!fin(d.load_s0)) arg_fail(os.str() + "load_s0 must be finite");

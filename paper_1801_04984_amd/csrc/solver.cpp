@@ -74,7 +74,7 @@ struct PrecBufs {
 struct PrecData {
   int nl = 1, dim = 2, count = 1;
   // complex-pair level blocks (biot_pair_mode) and the pairs of the real block form
-  int pair_mode = BIOT_PAIR_DROP;
+  int pair_mode = BIOT_PAIR_DROP;   // resolved (never BIOT_PAIR_AUTO)
   PairSet pairs{};
   // preconditioner level k is column lperm[k] of the real block eigenbasis, with its
   // alpha and beta (square-block factorisation: pair firsts, real levels, pair seconds;
@@ -538,33 +538,23 @@ void plan_solver_layout(biot_problem_s* h, Layout& L, bool carve) {
     P = new PrecData();
     h->prec = P;
   }
+  // BIOT_PAIR_AUTO: the square-block factorisation where its second pass of level solves
+  // costs less than the iterations it saves (3D, r >= 2)
   P->pair_mode = h->descs[0].pair_mode;
+  if (P->pair_mode == BIOT_PAIR_AUTO) P->pair_mode = (h->dim == 3 && h->r >= 2) ? BIOT_PAIR_PRESB : BIOT_PAIR_DROP;
+  const LevelOrder lo = level_order(h->tc, P->pair_mode == BIOT_PAIR_PRESB);
   P->pairs = PairSet{};
-  int first[2] = {0, 0}, npair = 0;
-  for (int j = 0; j + 1 < h->nl; ++j)
-    if (h->tc.beta[j] > 0 && npair < 2) first[npair++] = j;   // columns j, j+1: alpha_j +- i beta_j
-  for (int k = 0; k < 4; ++k) P->lperm[k] = k;
-  if (P->pair_mode == BIOT_PAIR_PRESB && npair > 0) {
-    int k = 0;
-    for (int i = 0; i < npair; ++i) P->lperm[k++] = first[i];
-    for (int j = 0; j < h->nl; ++j) {
-      bool in_pair = false;
-      for (int i = 0; i < npair; ++i) in_pair = in_pair || j == first[i] || j == first[i] + 1;
-      if (!in_pair) P->lperm[k++] = j;
-    }
-    for (int i = 0; i < npair; ++i) P->lperm[k++] = first[i] + 1;
+  P->pairs.n = lo.npairs;
+  for (int i = 0; i < lo.npairs; ++i) {
+    P->pairs.j[i] = lo.first[i];
+    P->pairs.j2[i] = lo.second[i];
+    P->pairs.beta[i] = lo.beta[i];
   }
   for (int k = 0; k < 4; ++k) {
-    P->lalpha[k] = h->tc.alpha[P->lperm[k]];
-    P->lbeta[k] = h->tc.beta[P->lperm[k]];
+    P->lperm[k] = lo.perm[k];
+    P->lalpha[k] = h->tc.alpha[lo.perm[k]];
+    P->lbeta[k] = h->tc.beta[lo.perm[k]];
   }
-  for (int i = 0; i < npair; ++i)
-    for (int k = 0; k < h->nl; ++k) {
-      if (P->lperm[k] == first[i]) P->pairs.j[i] = k;
-      if (P->lperm[k] == first[i] + 1) P->pairs.j2[i] = k;
-    }
-  for (int i = 0; i < npair; ++i) P->pairs.beta[i] = h->tc.beta[first[i]];
-  P->pairs.n = npair;
   build_hierarchy(h, P);
   carve_bufs<double>(h, P, P->b64, L, false);
   carve_bufs<float>(h, P, P->b32, L, true);

@@ -293,4 +293,30 @@ TemporalConstants make_temporal(int r) {
   return tc;
 }
 
+LevelOrder level_order(const TemporalConstants& tc, bool by_pass) {
+  LevelOrder o;
+  const int n = tc.r + 1;
+  int col[2] = {0, 0};
+  for (int j = 0; j + 1 < n; ++j)
+    if (tc.beta[j] > 0 && o.npairs < 2) col[o.npairs++] = j;   // columns j, j+1
+  if (by_pass && o.npairs > 0) {
+    int k = 0;
+    for (int i = 0; i < o.npairs; ++i) o.perm[k++] = col[i];
+    for (int j = 0; j < n; ++j) {
+      bool in_pair = false;
+      for (int i = 0; i < o.npairs; ++i) in_pair = in_pair || j == col[i] || j == col[i] + 1;
+      if (!in_pair) o.perm[k++] = j;
+    }
+    for (int i = 0; i < o.npairs; ++i) o.perm[k++] = col[i] + 1;
+  }
+  for (int i = 0; i < o.npairs; ++i) {
+    for (int k = 0; k < n; ++k) {
+      if (o.perm[k] == col[i]) o.first[i] = k;
+      if (o.perm[k] == col[i] + 1) o.second[i] = k;
+    }
+    o.beta[i] = tc.beta[col[i]];
+  }
+  return o;
+}
+
 }  // namespace bt

@@ -15,4 +15,17 @@ struct TemporalConstants {
 
 TemporalConstants make_temporal(int r);
 
+// Order of the preconditioner's levels: level k is column perm[k] of Q.  A
+// complex pair alpha +- i beta (columns c, c+1 of Q, beta > 0) sits at levels
+// first[i] and second[i].  by_pass: pair firsts, then the real levels, then
+// the pair seconds (the square-block factorisation solves the first of every
+// pair with the real levels and the seconds after them); otherwise Q's order.
+struct LevelOrder {
+  int perm[4] = {0, 1, 2, 3};
+  int npairs = 0;
+  int first[2] = {0, 0}, second[2] = {0, 0};
+  double beta[2] = {0, 0};
+};
+LevelOrder level_order(const TemporalConstants& tc, bool by_pass);
+
 }  // namespace bt

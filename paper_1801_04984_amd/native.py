@@ -137,10 +137,10 @@ def _check(status):
         raise BiotError(status, msg)
 
 
-PAIR_DROP, PAIR_PRESB, PAIR_SHIFT = 0, 1, 2
+PAIR_AUTO, PAIR_DROP, PAIR_PRESB, PAIR_SHIFT = 0, 1, 2, 3
 
 
-def make_desc(wl, pair_mode=PAIR_DROP, L_fs=0.0) -> Desc:
+def make_desc(wl, pair_mode=PAIR_AUTO, L_fs=0.0) -> Desc:
     """Descriptor from a workloads.Workload."""
     d = Desc()
     d.dim = wl.dim
@@ -177,7 +177,7 @@ def _stream(torch, device):
 class BiotSlab:
     """A handle over one or several (batched) slab problems on one GPU."""
 
-    def __init__(self, workloads: Sequence, log_k: Sequence[np.ndarray], device="cuda:0", pair_mode=PAIR_DROP,
+    def __init__(self, workloads: Sequence, log_k: Sequence[np.ndarray], device="cuda:0", pair_mode=PAIR_AUTO,
                  L_fs=0.0):
         import torch
         self.torch = torch

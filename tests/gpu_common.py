@@ -14,7 +14,8 @@ def torch_cuda():
 
 
 def make_pair(wls, thetas=None, pair_mode=0):
-    """(BiotSlab over all wls, list of oracle SlabProblems)."""
+    """(BiotSlab over all wls, list of oracle SlabProblems); pair_mode 0 is
+    the library's default (BIOT_PAIR_AUTO)."""
     from oracle import slab
     from paper_1801_04984_amd import BiotSlab
     thetas = thetas if thetas is not None else [w.log_k() for w in wls]

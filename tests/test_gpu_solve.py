@@ -404,16 +404,21 @@ def test_mixed_before_refinement_per_field_error():
     h.close()
 
 
-@pytest.mark.parametrize("d,n,r", [(2, (20, 13), 1), (2, (33, 20), 2), (2, (16, 12), 3), (3, (5, 4, 6), 2)])
+@pytest.mark.parametrize("d,n,r", [(2, (20, 13), 1), (2, (33, 20), 2), (2, (16, 12), 3), (3, (5, 4, 6), 2),
+                                   (3, (4, 5, 3), 3), (3, (5, 3, 4), 1)])
 def test_pair_modes_reach_the_oracle(d, n, r):
-    """The three treatments of the complex-pair level blocks (couplings kept
-    by the square-block factorisation, dropped, dropped with the shifted
-    level solve) are preconditioners of one system: all reach the oracle's
-    solution, forward and transposed, FP64 and FP32-preconditioned."""
+    """The treatments of the complex-pair level blocks (couplings kept by the
+    square-block factorisation, dropped, dropped with the shifted level
+    solve) are preconditioners of one system: all reach the oracle's solution,
+    forward and transposed, FP64 and FP32-preconditioned.  The default
+    (automatic) mode takes the square-block factorisation in 3D at r >= 2 and
+    drops the couplings otherwise: its iteration counts are those of that mode."""
+    from paper_1801_04984_amd import native
     torch = torch_cuda()
     wl = small_workload(d, n, r, seed=110 + d + r)
     its = {}
-    for mode in (0, 1, 2):
+    modes = (native.PAIR_DROP, native.PAIR_PRESB, native.PAIR_SHIFT, native.PAIR_AUTO)
+    for mode in modes:
         h, (prob,) = make_pair([wl], pair_mode=mode)
         b = _rhs(prob, seed=12)
         for transpose in (False, True):
@@ -427,6 +432,14 @@ def test_pair_modes_reach_the_oracle(d, n, r):
                 its[(mode, transpose, precision)] = info[0]["iterations"]
         h.close()
     print(f"d={d} n={n} r={r} iterations (mode, transposed, precision): {its}")
+    auto_is = native.PAIR_PRESB if (d == 3 and r >= 2) else native.PAIR_DROP
+    for transpose in (False, True):
+        for precision in (0, 2):
+            assert its[(native.PAIR_AUTO, transpose, precision)] == its[(auto_is, transpose, precision)], its
+    # the kept couplings save iterations wherever the level solves are good enough to show it
+    if r >= 2:
+        for transpose in (False, True):
+            assert its[(native.PAIR_PRESB, transpose, 0)] < its[(native.PAIR_DROP, transpose, 0)], its
 
 
 @pytest.mark.parametrize("d,n,r", [(2, (12, 10), 0), (2, (16, 11), 1), (2, (12, 9), 2), (3, (4, 3, 4), 1)])

@@ -69,6 +69,25 @@ def test_temporal_constants_match_oracle(tmp_path):
         ev = np.sort_complex(np.linalg.eigvals(T))
         got = np.sort_complex(np.linalg.eigvals(expect))
         np.testing.assert_allclose(got, ev, atol=1e-10 * np.abs(ev).max())
+        npairs = int((beta > 0).sum())
+        assert npairs == (rr + 1) // 2   # Radau IIA: one real eigenvalue for odd stage counts
+        for key in ("order_q", "order_pass"):
+            o = c[key]
+            perm = o["perm"][:L]
+            assert sorted(perm) == list(range(L)), (rr, key, perm)
+            assert len(o["first"]) == npairs
+            # in the permuted basis each pair keeps its 2x2 block at (first, second)
+            Lp = Qi[perm, :] @ Tl @ Q[:, perm]
+            ex = np.diag(alpha[perm])
+            for i, (f, s2) in enumerate(zip(o["first"], o["second"])):
+                assert o["beta"][i] > 0 and beta[perm[f]] == o["beta"][i] and beta[perm[s2]] == -o["beta"][i]
+                ex[f, s2], ex[s2, f] = o["beta"][i], -o["beta"][i]
+            np.testing.assert_allclose(Lp, ex, atol=1e-10 * np.abs(Tl).max())
+            if key == "order_q":
+                assert perm == list(range(L)) and o["second"] == [f + 1 for f in o["first"]]
+            else:   # pair firsts, real levels, pair seconds
+                assert o["first"] == list(range(npairs))
+                assert o["second"] == list(range(L - npairs, L))
 
 
 def test_element_matrices_match_oracle(tmp_path):
