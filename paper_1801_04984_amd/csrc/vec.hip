@@ -59,6 +59,27 @@ void vacc(const float* x, double* y, long long n, hipStream_t s) {
 // stage 1: block b of segment s reduces a fixed chunk for KB vectors
 constexpr int kDotThreads = 256;
 constexpr int kKBMax = 32;   // vectors per stage-1 launch: w is read once per 32
+// the values V[(k0 + k) * ldv + i] of one element for k < nk (0 beyond), in FP64,
+// with every load issued before any is used, so that they stay in flight together.
+// FP64 rows past nk are skipped by uniform branches.  For FP32 rows the compiler
+// moves the conversion into such a branch and waits there, so every row is loaded
+// (rows past nk repeat row nk - 1, which the cache serves) and masked afterwards.
+template <typename TV, int K>
+__device__ __forceinline__ void load_column(const TV* __restrict__ V, long long ldv, int k0, int nk, long long i,
+                                            double (&v)[K]) {
+  if constexpr (sizeof(TV) == sizeof(double)) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = k < nk ? (double)V[(long long)(k0 + k) * ldv + i] : 0.0;
+  } else {
+    const int last = nk > 0 ? nk - 1 : 0;
+    TV raw[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) raw[k] = V[(long long)(k0 + (k < last ? k : last)) * ldv + i];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = k < nk ? (double)raw[k] : 0.0;
+  }
+}
+
 template <typename TV, typename TW, int kKB>
 __global__ __launch_bounds__(kDotThreads) void mdot_stage1(const TV* __restrict__ V, long long ldv, int k0, int nk,
                                                            const TW* __restrict__ w, const VSeg* __restrict__ segs,
@@ -72,10 +93,11 @@ __global__ __launch_bounds__(kDotThreads) void mdot_stage1(const TV* __restrict_
 #pragma unroll
   for (int k = 0; k < kKB; ++k) acc[k] = 0.0;
   for (long long i = beg + threadIdx.x; i < end; i += kDotThreads) {
+    double v[kKB];
+    load_column<TV, kKB>(V, ldv, k0, nk, sg.off + i, v);
     const double wi = (double)w[sg.off + i];
 #pragma unroll
-    for (int k = 0; k < kKB; ++k)
-      if (k < nk) acc[k] += (double)V[(long long)(k0 + k) * ldv + sg.off + i] * wi;
+    for (int k = 0; k < kKB; ++k) acc[k] += v[k] * wi;
   }
   __shared__ double red[kKB][kDotThreads / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -118,11 +140,14 @@ int dot_chunks(long long maxlen) {
 template <typename TV, typename TW>
 void seg_mdot(const TV* V, long long ldv, int nk, const TW* w, const VSeg* segs, int nseg, int nchunk,
               double* partial, double* out, hipStream_t s, double* hout) {
-  // groups of up to 32 vectors; a group of at most 8 takes the 8-wide kernel
+  // groups of up to 32 vectors; the unrolled width is the smallest of 8, 16, 32 that holds the group
   for (int k0 = 0; k0 < nk; k0 += kKBMax) {
     int kk = nk - k0 < kKBMax ? nk - k0 : kKBMax;
     if (kk <= 8)
       hipLaunchKernelGGL((mdot_stage1<TV, TW, 8>), dim3(nchunk, nseg), dim3(kDotThreads), 0, s, V, ldv, k0, kk, w,
+                         segs, nchunk, partial);
+    else if (kk <= 16)
+      hipLaunchKernelGGL((mdot_stage1<TV, TW, 16>), dim3(nchunk, nseg), dim3(kDotThreads), 0, s, V, ldv, k0, kk, w,
                          segs, nchunk, partial);
     else
       hipLaunchKernelGGL((mdot_stage1<TV, TW, kKBMax>), dim3(nchunk, nseg), dim3(kDotThreads), 0, s, V, ldv, k0, kk,
@@ -158,8 +183,7 @@ __global__ __launch_bounds__(kDotThreads) void gs_update_dot_kernel(const TV* __
   for (int k = 0; k <= kFuseK; ++k) acc[k] = 0.0;
   for (long long i = beg + threadIdx.x; i < end; i += kDotThreads) {
     double v[kFuseK];
-#pragma unroll
-    for (int k = 0; k < kFuseK; ++k) v[k] = k < nk ? (double)V[(long long)k * ldv + sg.off + i] : 0.0;
+    load_column<TV, kFuseK>(V, ldv, 0, nk, sg.off + i, v);
     double wi = (double)w[sg.off + i];
 #pragma unroll
     for (int k = 0; k < kFuseK; ++k) wi -= cs[k] * v[k];
@@ -209,8 +233,7 @@ __global__ __launch_bounds__(256) void gs_update_scale_kernel(const TV* __restri
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < sg.len;
        i += (long long)gridDim.x * blockDim.x) {
     double v[kFuseK];
-#pragma unroll
-    for (int k = 0; k < kFuseK; ++k) v[k] = k < nk ? (double)V[(long long)k * ldv + sg.off + i] : 0.0;
+    load_column<TV, kFuseK>(V, ldv, 0, nk, sg.off + i, v);
     double wi = (double)w[sg.off + i];
 #pragma unroll
     for (int k = 0; k < kFuseK; ++k) wi -= cs[k] * v[k];
