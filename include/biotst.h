@@ -183,9 +183,10 @@ biot_status apply_operator(biot_problem h, const void* x, void* y, int32_t trans
 
 /* The elasticity block of the slab operator, y_u = tau A x_u (section
  * "Monolithic Approach": the tau-scaled displacement block of every L_j), on
- * the u-blocks of every time level and instance of device slab vectors;
- * essential u rows copy x; the q and p entries of y are not written.  This is
- * the fine-level operator of the preconditioner's elasticity multigrid.
+ * the u-blocks of every time level and instance of device slab vectors, with
+ * the essential u DoFs eliminated: x at essential DoFs is ignored and the
+ * essential rows of y are 0; the q and p entries of y are not written.  This
+ * is the fine-level operator of the preconditioner's elasticity multigrid.
  * dtype 0: double, 1: float.  x and y must not alias.  Asynchronous. */
 biot_status biot_elasticity_apply(biot_problem h, const void* x, void* y, int32_t dtype, void* stream);
 

@@ -9,15 +9,16 @@
 // done on the matrix cores (16x16x4 MFMA, FP64 or FP32): twelve waves, three
 // per SIMD, each keep one 16-row tile of the element matrix in registers for
 // the whole launch and multiply it with one half of the layer's gathered
-// element vectors staged in LDS.  The node loads of the next layer are issued
-// before the matrix-core phase of the current one (software pipeline).
+// element vectors staged in LDS.  The node loads of a layer are issued two
+// layers ahead and stay in flight across the matrix-core phase in between
+// (software pipeline).
 //
 // Work decomposition: one block = an xy tile of 8x8 cells (7x7 owned plus a
 // one-cell halo on the low sides) marching through a z-chunk of cell layers.
-// Per layer the element rows are staged in LDS and every owned node of planes
+// The element rows of layer k are staged in LDS and every owned node of planes
 // 2k (bottom slice of layer k plus the top slice of layer k-1, carried in
-// LDS) and 2k+1 (middle slice) is summed in a fixed order: deterministic, no
-// atomics.  q-rows and p-rows are gathers (rows.h) in their own kernels:
+// LDS) and 2k+1 (middle slice) is summed in a fixed order, in the next layer's
+// first phase: deterministic, no atomics.  q-rows and p-rows are gathers (rows.h) in their own kernels:
 //   q-rows: tau (Mq q + B p);   p-rows: -w [tau div q_i + sum_j T_ij (b div u_j + p_j/M)]
 //   (A^T: p-rows -w [tau div q_i + tau b div u_i + sum_j T_ji p_j / M], u-rows use sum_j T_ji p_j).
 #include "kernels.h"
@@ -73,14 +74,27 @@ struct U3Job {
   int npl;
   int sp[2];
   int mode;          // 0: Y = A x (+ coupling); 1: Y = B - A x
+  bool copy_fixed;   // mode 0, essential rows: copy x (slab operator) or 0 (multigrid level operator)
 };
 
-// KS = k-steps of 4 columns: 23 with the 8 coupling columns, 21 without
+// KS = k-steps of 4 columns: 23 with the 8 coupling columns, 21 without.
+//
+// Two phases per cell layer k, one barrier after each:
+//   A: the node sums of layer k-1 (element rows in Rw, the carried top slice of
+//      layer k-2 in Cc[k & 1]) and the carry of layer k-1's top slice into
+//      Cc[(k & 1) ^ 1], then the element rows of layer k on the matrix cores
+//      (gathered vectors in Ul);
+//   B: the rows of layer k into Rw, the node planes of layer k+1 scattered into
+//      Ul, the loads of layer k+2 issued, the right-hand side of layer k's node
+//      sums (residual mode) prefetched.
+// (Against one phase per step, with five barriers per layer, this is 3-5% faster
+// at 48^3; letting some waves of a SIMD multiply before they sum was slower.)
 template <typename T, int KS>
 __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0, int zc) {
   constexpr int NC = kT3 * kT3, NT = 64 * kW3, KR = 4 * KS;
-  __shared__ T Ul[KR * kLD3];     // gathered element vectors [k][cell], then element rows [row][cell]
-  __shared__ T Cc[27 * NC];       // carried top slice of the layer below [comp*9 + node][cell]
+  __shared__ T Ul[KR * kLD3];     // gathered element vectors of the layer on the matrix cores [k][cell]
+  __shared__ T Rw[81 * kLD3];     // element rows of the layer whose nodes are summed [comp*27 + node][cell]
+  __shared__ T Cc[2][27 * NC];    // carried top slices, by layer parity [comp*9 + node][cell]
   using M = Mfma16<T>;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nx = J.n[0], ny = J.n[1], nz = J.n[2];
@@ -98,7 +112,7 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
   T af[KS];
 #pragma unroll
   for (int s = 0; s < KS; ++s) af[s] = J.A[(rt * KS + s) * 64 + lane];
-  for (int idx = tid; idx < 27 * NC; idx += NT) Cc[idx] = T(0);
+  for (int idx = tid; idx < 2 * 27 * NC; idx += NT) Cc[idx / (27 * NC)][idx % (27 * NC)] = T(0);
   // node-plane gather: 3 planes x 3 components of 17 x 17 nodes per layer.  All
   // of a thread's loads are issued before the LDS scatter; their offsets (less
   // the layer term) and masks do not depend on the layer and are computed here.
@@ -126,17 +140,14 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
     }
   }
 
-  // the node loads of layer k are issued one layer ahead (software pipeline):
-  // they are in flight while the matrix cores and the node sums of layer k-1 run
   T gv[NIT];
-#pragma unroll
-  for (int it = 0; it < NIT; ++it) gv[it] = J.X[(int)(gcode[it] & 0x3fffffffu) + sz * (2 * kbeg)];
-  for (int k = kbeg; k < kend; ++k) {
-    // ---- gather element vectors: the three node planes 2k..2k+2 of the tile
-    // (17 x 17 nodes per plane and component) are read once, coalesced along x,
-    // and every node is written to the element-vector slot of each cell that
-    // shares it (essential u masked).  Cells outside the mesh get partial
-    // vectors; their rows are never summed into an owned node.
+  // ---- the element vectors of layer k into Ul: the three node planes 2k..2k+2
+  // of the tile (17 x 17 nodes per plane and component, loaded into gv, read
+  // once, coalesced along x); every node is written to the element-vector slot
+  // of each cell that shares it (essential u masked).  Cells outside the mesh get
+  // partial vectors; their rows are never summed into an owned node.  Then the
+  // coupling columns (scaled mixed pressure at the cell's Gauss points) and padding.
+  auto scatter_layer = [&](int k) {
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
       // bottom face (plane mz = 0) is essential for every component
@@ -168,13 +179,6 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
         }
       }
     }
-    // next layer's node loads (the last layer re-reads its own planes: in range, unused)
-    {
-      const int kn = k + 1 < kend ? k + 1 : k;
-#pragma unroll
-      for (int it = 0; it < NIT; ++it) gv[it] = J.X[(int)(gcode[it] & 0x3fffffffu) + sz * (2 * kn)];
-    }
-    // coupling columns (scaled mixed pressure at the cell's Gauss points) and padding
     for (int idx = tid; idx < (KR - 81) * NC; idx += NT) {
       const int kr = 81 + (idx >> 6), cell = idx & 63;
       const int i = i0 - 1 + (cell & 7), j = j0 - 1 + (cell >> 3);
@@ -189,98 +193,44 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
       }
       Ul[kr * kLD3 + cell] = v;
     }
-    __syncthreads();
-    // ---- element rows of the layer: rows of tile rt x cells 32 ch .. 32 ch + 31
-    typename M::V acc[2];
+  };
+  // the node loads of layer k (in flight until the scatter that consumes them)
+  auto load_layer = [&](int k) {
 #pragma unroll
-    for (int t = 0; t < 2; ++t) acc[t] = typename M::V{0, 0, 0, 0};
+    for (int it = 0; it < NIT; ++it) gv[it] = J.X[(int)(gcode[it] & 0x3fffffffu) + sz * (2 * k)];
+  };
+
+  // ---- owned node planes 2k (bottom slice of Rw + carried top slice cb) and 2k+1
+  // FP64 residual mode: the right-hand side values are prefetched into bvv (FP32
+  // keeps the single loop, as for the gather)
+  constexpr int NOW = sizeof(T) == 8 ? (6 * (2 * kO3 + 1) * (2 * kO3 + 1) + NT - 1) / NT : 1;
+  T bvv[NOW];
+  auto prefetch_rhs = [&](int k) {
+    if (sizeof(T) == 8 && J.mode != 0) {
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const T* Bs = Ul + (4 * s + (lane >> 4)) * kLD3 + 32 * ch + (lane & 15);
-#pragma unroll
-      for (int t = 0; t < 2; ++t) acc[t] = M::mma(af[s], Bs[16 * t], acc[t]);
-    }
-    __syncthreads();
-    {
-      const int c = rt >> 1, h = rt & 1;
-#pragma unroll
-      for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int pr = 16 * h + M::row(lane, v);
-          if (pr < 27) Ul[(c * 27 + pr) * kLD3 + 32 * ch + 16 * t + (lane & 15)] = acc[t][v];
-        }
-    }
-    __syncthreads();
-    // ---- owned node planes 2k (bottom slice + carried top slice) and 2k+1
-    if (k >= k0) {
-      // FP64 residual mode: the right-hand side values first, all in flight
-      // together (FP32 keeps the single loop, as for the gather)
-      constexpr int NOW = sizeof(T) == 8 ? (6 * (2 * kO3 + 1) * (2 * kO3 + 1) + NT - 1) / NT : 1;
-      T bvv[NOW];
-      if (sizeof(T) == 8 && J.mode != 0) {
-#pragma unroll
-        for (int it = 0; it < NOW; ++it) {
-          const int idx = min(tid + it * NT, 6 * nplane - 1);
-          const int c = idx / (2 * nplane);
-          const int rem = idx - c * 2 * nplane;
-          const int zl = rem >= nplane;
-          const int r2 = rem - zl * nplane;
-          bvv[it] = J.Bv[c * nu1 + (2 * i0 + r2 % nmx) + sy * (2 * j0 + r2 / nmx) + sz * (2 * k + zl)];
-        }
-      }
-#pragma unroll
-      for (int it = 0; it < NOW; ++it)
-      for (int idx = tid + it * NT; idx < 6 * nplane; idx += (sizeof(T) == 8 ? 6 * nplane : NT)) {
+      for (int it = 0; it < NOW; ++it) {
+        const int idx = min(tid + it * NT, 6 * nplane - 1);
         const int c = idx / (2 * nplane);
         const int rem = idx - c * 2 * nplane;
         const int zl = rem >= nplane;
         const int r2 = rem - zl * nplane;
-        const int mx = 2 * i0 + r2 % nmx, my = 2 * j0 + r2 / nmx, mz = 2 * k + zl;
-        const int go = c * nu1 + mx + sy * my + sz * mz;
-        T v;
-        if (ugrid_fixed(3, J.su, c, mx, my, mz)) {
-          v = J.mode == 0 ? J.X[go] : (sizeof(T) == 8 ? bvv[it] : J.Bv[go]);
-        } else {
-          const bool xo = mx & 1, yo = my & 1;
-          const int cx0 = xo ? (mx - 1) / 2 : mx / 2 - 1, ax0 = xo ? 1 : 2;
-          const int cy0 = yo ? (my - 1) / 2 : my / 2 - 1, ay0 = yo ? 1 : 2;
-          const bool vx0 = cx0 >= 0, vx1 = !xo && (mx / 2 < nx);
-          const bool vy0 = cy0 >= 0, vy1 = !yo && (my / 2 < ny);
-          const int tx0 = cx0 - i0 + 1, ty0 = cy0 - j0 + 1;
-          v = 0;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int qx = q & 1, qy = q >> 1;
-            if (!((qy ? vy1 : vy0) && (qx ? vx1 : vx0))) continue;
-            const int cell = (ty0 + qy) * kT3 + tx0 + qx;
-            const int nd = (qy ? 0 : ay0) * 3 + (qx ? 0 : ax0);
-            v += Ul[(c * 27 + zl * 9 + nd) * kLD3 + cell];
-            if (zl == 0) v += Cc[(c * 9 + nd) * NC + cell];
-          }
-          if (J.mode != 0) v = (sizeof(T) == 8 ? bvv[it] : J.Bv[go]) - v;
-        }
-        J.Y[go] = v;
+        bvv[it] = J.Bv[c * nu1 + (2 * i0 + r2 % nmx) + sy * (2 * j0 + r2 / nmx) + sz * (2 * k + zl)];
       }
     }
-    __syncthreads();
-    for (int idx = tid; idx < 27 * NC; idx += NT) {
-      const int r = idx >> 6, cell = idx & 63;     // r = comp * 9 + node of the top slice
-      const int c = r / 9;
-      Cc[idx] = Ul[(c * 27 + 18 + (r - 9 * c)) * kLD3 + cell];
-    }
-    __syncthreads();
-  }
-  // ---- top plane 2 nz (only the layer below contributes)
-  if (kend == nz) {
-    for (int idx = tid; idx < 3 * nplane; idx += NT) {
-      const int c = idx / nplane;
-      const int r2 = idx - c * nplane;
-      const int mx = 2 * i0 + r2 % nmx, my = 2 * j0 + r2 / nmx, mz = 2 * nz;
+  };
+  auto node_sums = [&](int k, const T* __restrict__ cb) {
+#pragma unroll
+    for (int it = 0; it < NOW; ++it)
+    for (int idx = tid + it * NT; idx < 6 * nplane; idx += (sizeof(T) == 8 ? 6 * nplane : NT)) {
+      const int c = idx / (2 * nplane);
+      const int rem = idx - c * 2 * nplane;
+      const int zl = rem >= nplane;
+      const int r2 = rem - zl * nplane;
+      const int mx = 2 * i0 + r2 % nmx, my = 2 * j0 + r2 / nmx, mz = 2 * k + zl;
       const int go = c * nu1 + mx + sy * my + sz * mz;
       T v;
       if (ugrid_fixed(3, J.su, c, mx, my, mz)) {
-        v = J.mode == 0 ? J.X[go] : J.Bv[go];
+        v = J.mode == 0 ? (J.copy_fixed ? J.X[go] : T(0)) : (sizeof(T) == 8 ? bvv[it] : J.Bv[go]);
       } else {
         const bool xo = mx & 1, yo = my & 1;
         const int cx0 = xo ? (mx - 1) / 2 : mx / 2 - 1, ax0 = xo ? 1 : 2;
@@ -294,7 +244,96 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
           const int qx = q & 1, qy = q >> 1;
           if (!((qy ? vy1 : vy0) && (qx ? vx1 : vx0))) continue;
           const int cell = (ty0 + qy) * kT3 + tx0 + qx;
-          v += Cc[(c * 9 + (qy ? 0 : ay0) * 3 + (qx ? 0 : ax0)) * NC + cell];
+          const int nd = (qy ? 0 : ay0) * 3 + (qx ? 0 : ax0);
+          v += Rw[(c * 27 + zl * 9 + nd) * kLD3 + cell];
+          if (zl == 0) v += cb[(c * 9 + nd) * NC + cell];
+        }
+        if (J.mode != 0) v = (sizeof(T) == 8 ? bvv[it] : J.Bv[go]) - v;
+      }
+      J.Y[go] = v;
+    }
+  };
+  // top slice of the rows in Rw (comp * 9 + node) into the carry buffer cn
+  auto carry = [&](T* __restrict__ cn) {
+    for (int idx = tid; idx < 27 * NC; idx += NT) {
+      const int r = idx >> 6, cell = idx & 63;
+      const int c = r / 9;
+      cn[idx] = Rw[(c * 27 + 18 + (r - 9 * c)) * kLD3 + cell];
+    }
+  };
+  // phase A of the layer below (its node sums when owned, and its carry)
+  auto finish_below = [&](int k) {
+    if (k > kbeg) {
+      if (k - 1 >= k0) node_sums(k - 1, Cc[k & 1]);
+      carry(Cc[(k & 1) ^ 1]);
+    }
+  };
+
+  // prologue: layer kbeg gathered into Ul, the loads of layer kbeg + 1 in flight
+  load_layer(kbeg);
+  scatter_layer(kbeg);
+  load_layer(kbeg + 1 < kend ? kbeg + 1 : kbeg);
+  __syncthreads();
+  for (int k = kbeg; k < kend; ++k) {
+    // ---- phase A: the layer below; element rows of layer k: rows of tile rt x cells 32 ch .. 32 ch + 31
+    finish_below(k);
+    typename M::V acc[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) acc[t] = typename M::V{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const T* Bs = Ul + (4 * s + (lane >> 4)) * kLD3 + 32 * ch + (lane & 15);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) acc[t] = M::mma(af[s], Bs[16 * t], acc[t]);
+    }
+    __syncthreads();
+    // ---- phase B: rows of layer k into Rw; layer k+1 into Ul, loads of layer k+2
+    {
+      const int c = rt >> 1, h = rt & 1;
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int pr = 16 * h + M::row(lane, v);
+          if (pr < 27) Rw[(c * 27 + pr) * kLD3 + 32 * ch + 16 * t + (lane & 15)] = acc[t][v];
+        }
+    }
+    if (k + 1 < kend) {
+      scatter_layer(k + 1);
+      // (the last layer re-reads its own planes: in range, unused)
+      load_layer(k + 2 < kend ? k + 2 : k + 1);
+    }
+    if (k >= k0) prefetch_rhs(k);
+    __syncthreads();
+  }
+  // the last layer's node sums and carry
+  finish_below(kend);
+  __syncthreads();
+  // ---- top plane 2 nz (only the layer below contributes)
+  if (kend == nz) {
+    const T* cb = Cc[(kend & 1) ^ 1];
+    for (int idx = tid; idx < 3 * nplane; idx += NT) {
+      const int c = idx / nplane;
+      const int r2 = idx - c * nplane;
+      const int mx = 2 * i0 + r2 % nmx, my = 2 * j0 + r2 / nmx, mz = 2 * nz;
+      const int go = c * nu1 + mx + sy * my + sz * mz;
+      T v;
+      if (ugrid_fixed(3, J.su, c, mx, my, mz)) {
+        v = J.mode == 0 ? (J.copy_fixed ? J.X[go] : T(0)) : J.Bv[go];
+      } else {
+        const bool xo = mx & 1, yo = my & 1;
+        const int cx0 = xo ? (mx - 1) / 2 : mx / 2 - 1, ax0 = xo ? 1 : 2;
+        const int cy0 = yo ? (my - 1) / 2 : my / 2 - 1, ay0 = yo ? 1 : 2;
+        const bool vx0 = cx0 >= 0, vx1 = !xo && (mx / 2 < nx);
+        const bool vy0 = cy0 >= 0, vy1 = !yo && (my / 2 < ny);
+        const int tx0 = cx0 - i0 + 1, ty0 = cy0 - j0 + 1;
+        v = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int qx = q & 1, qy = q >> 1;
+          if (!((qy ? vy1 : vy0) && (qx ? vx1 : vx0))) continue;
+          const int cell = (ty0 + qy) * kT3 + tx0 + qx;
+          v += cb[(c * 9 + (qy ? 0 : ay0) * 3 + (qx ? 0 : ax0)) * NC + cell];
         }
         if (J.mode != 0) v = J.Bv[go] - v;
       }
@@ -319,6 +358,7 @@ __global__ __launch_bounds__(64 * kW3) void apply3d_u_kernel(const InstDev* __re
   J.Y = Y + I.x_off + lev * I.N + I.off_u[0];
   J.Bv = nullptr;
   J.mode = 0;
+  J.copy_fixed = true;
   J.P = X + I.x_off + I.off_p;
   J.plstride = I.N;
   J.sp[0] = I.sp[0]; J.sp[1] = I.sp[1];
@@ -486,7 +526,8 @@ void launch_apply3d(const ApplyArgs& a, const void* x, void* y, int transpose) {
 template void launch_apply3d<double>(const ApplyArgs&, const void*, void*, int);
 template void launch_apply3d<float>(const ApplyArgs&, const void*, void*, int);
 
-// elasticity multigrid level: y = tau A x (mode 0) or y = b - tau A x (mode 1)
+// elasticity multigrid level: y = tau A x (mode 0; essential rows 0) or y = b - tau A x
+// (mode 1; essential rows b)
 template <typename T>
 __global__ __launch_bounds__(64 * kW3) void uapply3d_kernel(const UGridSeg* __restrict__ segs,
                                                             const int4* __restrict__ work, int zc, int mode,
@@ -503,6 +544,7 @@ __global__ __launch_bounds__(64 * kW3) void uapply3d_kernel(const UGridSeg* __re
   J.Y = Y + vo;
   J.Bv = Bv ? Bv + vo : nullptr;
   J.mode = mode;
+  J.copy_fixed = false;
   J.P = nullptr;
   J.plstride = 0;
   J.npl = 0;

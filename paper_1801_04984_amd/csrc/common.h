@@ -23,6 +23,7 @@ constexpr int kBlk = 256;
 // share halo data through that XCD's L2): XCD x = b % 8 takes its k-th
 // (k = b / 8) tile from the x-th run.
 constexpr int kXcds = 8;
+constexpr int kCus = 256;    // compute units of the MI355X (32 per XCD)
 inline long long xcd_tile(long long b, long long n) {
   const long long x = b % kXcds, k = b / kXcds;
   const long long base = n / kXcds, rem = n % kXcds;   // run x holds base + (x < rem) tiles

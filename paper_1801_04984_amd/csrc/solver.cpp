@@ -96,8 +96,10 @@ struct PrecData {
   std::vector<UGridSeg> ug0c;                   // level 0 compact layout (set-up)
   UGridSeg* d_ug0c = nullptr;
   std::vector<long long> u_total, u_max;
+  // elasticity operator work lists and tile variants per u level l and number of time
+  // levels nj of a launch (index uvar(l, nj)): 2D tile edge variant, 3D z-chunk
   std::vector<std::vector<int4>> uwork;
-  std::vector<int> utile;   // 2D tile variant per u level
+  std::vector<int> utile;
   std::vector<int4*> d_uwork;
   std::vector<std::vector<std::vector<RPass>>> rp;   // [transition][pass][inst]
   std::vector<std::vector<RPass*>> d_rp;
@@ -197,6 +199,33 @@ static void interp_table(int nf, int nc, std::vector<double>& prol, std::vector<
       if (w != 0.0) rows[2 * C + a].push_back({m, w});
     }
   }
+}
+
+// work-list index of u level l for launches over nj time levels (1..4)
+static inline int uvar(int l, int nj) { return 4 * l + nj - 1; }
+
+// z-chunk (cell layers per block) of the 3D elasticity kernel for a launch over nj
+// time levels.  A block (an xy tile of a chunk of one level) holds a whole CU, so a
+// launch takes ceil(blocks / CUs) rounds, each of about chunk + halo layer + one
+// layer's worth of set-up; the chunk with the fewest such layer steps is taken
+// (ties: the longer chunk).  At 48^3 this gives 16 layers for three levels, 10 for
+// one or two; the small levels, which are bound by the latency of the serial layer
+// march, get chunks of one or two layers.
+static int zchunk3d(const std::vector<UGridSeg>& segs, int nj) {
+  const int t = apply3d_tile_cells_xy();
+  int nzmax = 1;
+  for (const auto& g : segs) nzmax = std::max(nzmax, g.n[2]);
+  int best = 1;
+  long long bestc = -1;
+  for (int zc = 1; zc <= 16; ++zc) {
+    long long blocks = 0;
+    for (const auto& g : segs)
+      blocks += (long long)((g.n[0] + t - 1) / t) * ((g.n[1] + t - 1) / t) * ((g.n[2] + zc - 1) / zc);
+    const long long rounds = (blocks * nj + kCus - 1) / kCus;
+    const long long c = rounds * (std::min(zc, nzmax) + (nzmax > zc ? 1 : 0) + 1);
+    if (bestc < 0 || c <= bestc) { bestc = c; best = zc; }
+  }
+  return best;
 }
 
 static void build_hierarchy(biot_problem_s* h, PrecData* P) {
@@ -334,44 +363,35 @@ static void build_hierarchy(biot_problem_s* h, PrecData* P) {
   }
   P->nul = (int)P->ug.size();
   P->uemat_len = uemat_off;
-  // work lists per u level; 2D levels with few 16x16 tiles use 8x8 tiles
-  P->uwork.assign(P->nul, {});
-  P->utile.assign(P->nul, 0);
-  for (int l = 0; l < P->nul; ++l) {
-    if (d == 3) {
-      // z-chunk of the z-marching 3D kernel: 8 cell layers, halved (down to 2) while the
-      // level would give fewer blocks than CUs -- the small levels are bound by the
-      // latency of the serial layer march, which shorter chunks cut
-      long long txy = 0, nzmax = 1;
-      const int t = apply3d_tile_cells_xy();
-      for (const auto& g : P->ug[l]) {
-        txy += (long long)((g.n[0] + t - 1) / t) * ((g.n[1] + t - 1) / t);
-        nzmax = std::max<long long>(nzmax, g.n[2]);
-      }
-      int zc = 8;
-      while (zc > 2 && txy * ((nzmax + zc - 1) / zc) * nl < 256) zc /= 2;
-      P->utile[l] = zc;
-      continue;
-    }
-    long long t16 = 0;
-    for (const auto& g : P->ug[l]) t16 += (long long)((g.n[0] + 14) / 15) * ((g.n[1] + 14) / 15);
-    P->utile[l] = t16 * nl < kUTile16MinTiles ? 1 : 0;
-  }
+  // work lists per u level and launch width nj; 2D levels with few 16x16 tiles use 8x8 tiles
+  P->uwork.assign(P->nul * 4, {});
+  P->utile.assign(P->nul * 4, 0);
   for (int l = 0; l < P->nul; ++l)
-    for (int k = 0; k < cnt; ++k) {
-      const UGridSeg& g = P->ug[l][k];
-      const int t = uapply_tile(d, P->utile[l]);
-      if (d == 2) {
-        for (int ty = 0; ty < (g.n[1] + t - 1) / t; ++ty)
-          for (int tx = 0; tx < (g.n[0] + t - 1) / t; ++tx) P->uwork[l].push_back(make_int4(k, tx, ty, 0));
+    for (int nj = 1; nj <= nl; ++nj) {
+      const int v = uvar(l, nj);
+      if (d == 3) {
+        P->utile[v] = zchunk3d(P->ug[l], nj);
       } else {
-        const int txy = apply3d_tile_cells_xy(), tz = P->utile[l];
-        for (int z = 0; z < (g.n[2] + tz - 1) / tz; ++z)
-          for (int ty = 0; ty < (g.n[1] + txy - 1) / txy; ++ty)
-            for (int tx = 0; tx < (g.n[0] + txy - 1) / txy; ++tx) P->uwork[l].push_back(make_int4(k, tx, ty, z));
+        long long t16 = 0;
+        for (const auto& g : P->ug[l]) t16 += (long long)((g.n[0] + 14) / 15) * ((g.n[1] + 14) / 15);
+        P->utile[v] = t16 * nj < kUTile16MinTiles ? 1 : 0;
       }
+      for (int k = 0; k < cnt; ++k) {
+        const UGridSeg& g = P->ug[l][k];
+        if (d == 2) {
+          const int t = uapply_tile(d, P->utile[v]);
+          for (int ty = 0; ty < (g.n[1] + t - 1) / t; ++ty)
+            for (int tx = 0; tx < (g.n[0] + t - 1) / t; ++tx) P->uwork[v].push_back(make_int4(k, tx, ty, 0));
+        } else {
+          const int txy = apply3d_tile_cells_xy(), tz = P->utile[v];
+          for (int z = 0; z < (g.n[2] + tz - 1) / tz; ++z)
+            for (int ty = 0; ty < (g.n[1] + txy - 1) / txy; ++ty)
+              for (int tx = 0; tx < (g.n[0] + txy - 1) / txy; ++tx)
+                P->uwork[v].push_back(make_int4(k, tx, ty, z));
+        }
+      }
+      P->uwork[v] = xcd_ordered(P->uwork[v]);
     }
-  for (int l = 0; l < P->nul; ++l) P->uwork[l] = xcd_ordered(P->uwork[l]);
   // transfers per transition l -> l+1
   P->utab_h.clear();
   P->rp.assign(std::max(0, P->nul - 1), {});
@@ -564,13 +584,14 @@ void plan_solver_layout(biot_problem_s* h, Layout& L, bool carve) {
   P->d_pc.assign(P->npl, nullptr);
   for (int l = 0; l < P->npl; ++l) P->d_pc[l] = L.take<PCellSeg>(P->pc[l].size());
   P->d_ug.assign(P->nul, nullptr);
-  P->d_uwork.assign(P->nul, nullptr);
+  P->d_uwork.assign(P->uwork.size(), nullptr);
   P->d_ul.assign(P->nul, nullptr);
   for (int l = 0; l < P->nul; ++l) {
     P->d_ug[l] = L.take<UGridSeg>(P->ug[l].size());
-    P->d_uwork[l] = L.take<int4>(P->uwork[l].size());
     P->d_ul[l] = L.take<LSeg>(P->ul[l].size());
   }
+  for (size_t v = 0; v < P->uwork.size(); ++v)
+    if (!P->uwork[v].empty()) P->d_uwork[v] = L.take<int4>(P->uwork[v].size());
   P->d_ug0c = L.take<UGridSeg>(P->ug0c.size());
   P->d_ul0c = L.take<LSeg>(P->ul0c.size());
   P->d_rp.assign(std::max(0, P->nul - 1), {});
@@ -891,11 +912,12 @@ static void setup_elasticity(biot_problem_s* h, hipStream_t s) {
       for (auto& g : P->ug[l]) segs.push_back({g.voff, g.nu});
       dseg = P->d_ug[l]; dls = P->d_ul[l]; x = B.u_x[l]; y = B.u_y[l];
     }
-    const int4* work = P->d_uwork[l];
-    const int nwork = (int)P->uwork[l].size();
+    const int uv = uvar(l, 1);
+    const int4* work = P->d_uwork[uv];
+    const int nwork = (int)P->uwork[uv].size();
     const long long mx = P->u_max[l];
     auto apply = [&](double* xx, double* yy) {
-      launch_uapply<double>(d, dseg, work, nwork, 1, 0, xx, nullptr, yy, P->d_uemat64, s, P->utile[l]);
+      launch_uapply<double>(d, dseg, work, nwork, 1, 0, xx, nullptr, yy, P->d_uemat64, s, P->utile[uv]);
       launch_mul_dinv<double>(dls, cnt, 1, mx, B.u_dinv[0], yy, yy, s);
     };
     auto lam = power_max(P, apply, x, y, segs, s);
@@ -926,9 +948,10 @@ void setup_solver(biot_problem_s* h, hipStream_t s) {
   for (int l = 0; l < P->npl; ++l) upload(P->pc[l], P->d_pc[l], s);
   for (int l = 0; l < P->nul; ++l) {
     upload(P->ug[l], P->d_ug[l], s);
-    upload(P->uwork[l], P->d_uwork[l], s);
     upload(P->ul[l], P->d_ul[l], s);
   }
+  for (size_t v = 0; v < P->uwork.size(); ++v)
+    if (!P->uwork[v].empty()) upload(P->uwork[v], P->d_uwork[v], s);
   upload(P->ug0c, P->d_ug0c, s);
   upload(P->ul0c, P->d_ul0c, s);
   for (int l = 0; l + 1 < P->nul; ++l) {
@@ -1065,13 +1088,14 @@ static void u_vcycle(biot_problem_s* h, int l, int nl, T* x, const T* b, T* r, T
   const LSeg* ls = P->d_ul[l];
   const long long mx = P->u_max[l];
   const UGridSeg* gs = P->d_ug[l];
-  const int4* work = P->d_uwork[l];
-  const int nwork = (int)P->uwork[l].size();
+  const int uv = uvar(l, nl);
+  const int4* work = P->d_uwork[uv];
+  const int nwork = (int)P->uwork[uv].size();
   const T* dinv = B.u_dinv[0];
   // pre-smoothing from x = 0
   cheb_update<T>(ls, cnt, nl, mx, 2, 0.0, cs.s0, x, r, d0, nullptr, dinv, b, s);
   for (int k = 0; k < ud; ++k) {
-    launch_uapply<T>(d, gs, work, nwork, nl, 0, d0, nullptr, y, uemat<T>(P), s, P->utile[l]);
+    launch_uapply<T>(d, gs, work, nwork, nl, 0, d0, nullptr, y, uemat<T>(P), s, P->utile[uv]);
     cheb_update<T>(ls, cnt, nl, mx, 1, cs.steps[k].first, cs.steps[k].second, x, r, d0, y, dinv, nullptr, s);
   }
   // restriction of r
@@ -1084,10 +1108,10 @@ static void u_vcycle(biot_problem_s* h, int l, int nl, T* x, const T* b, T* r, T
   u_vcycle<T>(h, l + 1, nl, B.u_x[l + 1], B.u_b[l + 1], B.u_r[l + 1], B.u_d0[l + 1], B.u_y[l + 1], s);
   launch_uprolong<T>(P->d_up[l], cnt, nl, mx, P->d_utab, B.u_x[l + 1], x, s);
   // post-smoothing
-  launch_uapply<T>(d, gs, work, nwork, nl, 1, x, b, r, uemat<T>(P), s, P->utile[l]);
+  launch_uapply<T>(d, gs, work, nwork, nl, 1, x, b, r, uemat<T>(P), s, P->utile[uv]);
   cheb_update<T>(ls, cnt, nl, mx, 0, 0.0, cs.s0, x, r, d0, nullptr, dinv, nullptr, s);
   for (int k = 0; k < ud; ++k) {
-    launch_uapply<T>(d, gs, work, nwork, nl, 0, d0, nullptr, y, uemat<T>(P), s, P->utile[l]);
+    launch_uapply<T>(d, gs, work, nwork, nl, 0, d0, nullptr, y, uemat<T>(P), s, P->utile[uv]);
     cheb_update<T>(ls, cnt, nl, mx, 1, cs.steps[k].first, cs.steps[k].second, x, r, d0, y, dinv, nullptr, s);
   }
 }
@@ -1233,8 +1257,9 @@ static void sys_apply(biot_problem_s* h, const T* x, T* y, int transpose, int sy
   const int dt = std::is_same<T, float>::value ? 1 : 0;
   PrecData* P = h->prec;
   if (sys == kSysMech) {
-    launch_uapply<T>(h->dim, P->d_ug[0], P->d_uwork[0], (int)P->uwork[0].size(), h->nl, 0, x, nullptr, y,
-                     uemat<T>(P), s, P->utile[0]);
+    const int uv = uvar(0, h->nl);
+    launch_uapply<T>(h->dim, P->d_ug[0], P->d_uwork[uv], (int)P->uwork[uv].size(), h->nl, 0, x, nullptr, y,
+                     uemat<T>(P), s, P->utile[uv]);
     launch_zero_rows<T>(h->d_inst, h->count, P->maxN, h->nl, 1, y, s);
     return;
   }
@@ -1813,13 +1838,14 @@ biot_status biot_elasticity_apply(biot_problem h, const void* x, void* y, int32_
     need(dtype == 0 || dtype == 1, "dtype must be 0 (double) or 1 (float)");
     PrecData* P = h->prec;
     hipStream_t s = (hipStream_t)stream;
-    const int nwork = (int)P->uwork[0].size();
+    const int uv = uvar(0, h->nl);
+    const int nwork = (int)P->uwork[uv].size();
     if (dtype == 0)
-      launch_uapply<double>(h->dim, P->d_ug[0], P->d_uwork[0], nwork, h->nl, 0, (const double*)x, nullptr, (double*)y,
-                            uemat<double>(P), s, P->utile[0]);
+      launch_uapply<double>(h->dim, P->d_ug[0], P->d_uwork[uv], nwork, h->nl, 0, (const double*)x, nullptr,
+                            (double*)y, uemat<double>(P), s, P->utile[uv]);
     else
-      launch_uapply<float>(h->dim, P->d_ug[0], P->d_uwork[0], nwork, h->nl, 0, (const float*)x, nullptr, (float*)y,
-                           uemat<float>(P), s, P->utile[0]);
+      launch_uapply<float>(h->dim, P->d_ug[0], P->d_uwork[uv], nwork, h->nl, 0, (const float*)x, nullptr,
+                           (float*)y, uemat<float>(P), s, P->utile[uv]);
     hip_check(hipGetLastError(), "elasticity apply launch");
     return BIOT_OK;
   } catch (const BiotError& e) {

@@ -247,7 +247,8 @@ class BiotSlab:
         return y
 
     def elasticity_apply(self, x, y=None):
-        """y_u = tau A x_u on the u-blocks of every level (q, p entries of y untouched)."""
+        """y_u = tau A x_u on the u-blocks of every level, essential DoFs eliminated (their rows 0;
+        q, p entries of y untouched)."""
         torch = self.torch
         dtype = 1 if x.dtype == torch.float32 else 0
         if y is None:

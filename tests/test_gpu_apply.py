@@ -145,3 +145,47 @@ def test_tile_variants_identical_and_autotune(d, r, tmp_path):
     again = tuning.tune(h, path=path)
     assert again["source"] == "cache" and h.get_tuning()["apply_variant"] == first["apply_variant"]
     h.close()
+
+
+@pytest.mark.parametrize("dims,r", [(3, 2), (2, 1)])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_elasticity_apply(dims, r, fp32):
+    """The elasticity operator of the preconditioner's fine multigrid level
+    (biot_elasticity_apply: y_u = tau A x_u per time level with the essential
+    DoFs eliminated, so essential rows 0; q and p entries of y untouched)
+    against tau times the u-u block of the oracle's assembled K_s with the
+    essential rows and columns removed.  3D covers several xy tiles, z-chunks
+    with their halo layer and a batch of two uneven instances."""
+    torch = torch_cuda()
+    if dims == 3:
+        wls = [small_workload(3, (15, 7, 9), r, seed=51), small_workload(3, (9, 8, 10), r, seed=52)]
+    else:
+        wls = [small_workload(2, (31, 16), r, seed=53), small_workload(2, (20, 17), r, seed=54)]
+    h, probs = make_pair(wls)
+    rng = np.random.default_rng(5)
+    dt = torch.float32 if fp32 else torch.float64
+    x = rng.standard_normal(h.slab_len)
+    if fp32:
+        x = x.astype(np.float32).astype(np.float64)
+    sentinel = 7.25
+    yt = torch.full((h.slab_len,), sentinel, dtype=dt, device="cuda")
+    h.elasticity_apply(torch.tensor(x, dtype=dt, device="cuda"), yt)
+    torch.cuda.synchronize()
+    y = yt.double().cpu().numpy()
+    for k, prob in enumerate(probs):
+        su = prob.mesh.field_slices()["u"]
+        Kuu = prob.Ks[su, su]
+        mu = prob.mask[su]
+        xs = x[h.slab_offsets[k]: h.slab_offsets[k] + prob.L * prob.N]
+        ys = y[h.slab_offsets[k]: h.slab_offsets[k] + prob.L * prob.N]
+        for lev in range(prob.L):
+            xl, yl = prob.level(xs, lev), prob.level(ys, lev)
+            xu = np.where(mu, 0.0, xl[su])
+            ref = prob.tau * (Kuu @ xu)
+            ref[mu] = 0.0
+            got = yl[su]
+            tol = (1e-5 if fp32 else 1e-12) * np.abs(ref).max()
+            bad = np.abs(got - ref) > tol
+            assert not bad.any(), (wls[k].name, lev, int(bad.sum()), np.abs(got - ref).max(), tol)
+            assert np.all(yl[su.stop:] == sentinel), (wls[k].name, lev)
+    h.close()
