@@ -1248,6 +1248,7 @@ struct SolveCtl {
   bool graph;
   bool flex32 = false;   // FP64 flexible GMRES with the preconditioner applied in FP32
   int sys = kSysSlab;    // the system solved (SubSystem)
+  bool lowsync = false;  // Gram-Schmidt with delayed reorthogonalisation (set by gmres)
 };
 
 // y = A x for the slab system or a fixed-stress sub-system (x zero outside the
@@ -1319,6 +1320,12 @@ static void arnoldi_step(biot_problem_s* h, int jj, int transpose, const SolveCt
   sys_apply<T>(h, B.t, vn, transpose, ctl.sys, s);
   const int nch = dot_chunks(P->gmax);
   double* hd = P->hdots;
+  if (ctl.lowsync) {
+    // slot jj held the candidate (its operator image is in slot jj+1): one reduction
+    // and one update sweep make slot jj final and slot jj+1 the next candidate
+    dcgs_step<T>(B.V, S, jj, P->d_gseg, cnt, nch, P->partial, P->dot1, P->dot2, s, hd, hd + 64 * cnt);
+    return;
+  }
   seg_mdot<T, T>(B.V, S, jj + 1, vn, P->d_gseg, cnt, nch, P->partial, P->dot1, s, hd);
   if (jj + 1 <= kFuseK) {
     // the same two passes with three sweeps over the basis: the update of pass 1
@@ -1352,8 +1359,8 @@ static void arnoldi_step_graph(biot_problem_s* h, int jj, int transpose, const S
     return;
   }
   const long long key =
-      (((((long long)jj * 2 + (transpose ? 1 : 0)) * 2 + (ctl.flex32 ? 1 : 0)) * 2 +
-        (std::is_same<T, float>::value ? 1 : 0)) * 128 + ctl.qdeg) * 3 + ctl.sys;
+      ((((((long long)jj * 2 + (transpose ? 1 : 0)) * 2 + (ctl.flex32 ? 1 : 0)) * 2 +
+         (std::is_same<T, float>::value ? 1 : 0)) * 128 + ctl.qdeg) * 3 + ctl.sys) * 2 + (ctl.lowsync ? 1 : 0);
   auto it = P->arnoldi.find(key);
   if (it == P->arnoldi.end()) {
     if (!P->cap_stream) hip_check(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking), "capture stream");
@@ -1404,6 +1411,15 @@ static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const Solv
   std::vector<double> coef(cnt * 64);
   std::vector<int> stall(cnt, 0);
   int total = 0;
+  // Gram-Schmidt with delayed reorthogonalisation (dcgs_step) for restart lengths whose
+  // dot sets fit the 64 slots per instance; the flexible mode keeps the plain passes
+  SolveCtl c = ctl;
+  c.lowsync = !ctl.flex32 && m <= kLowSyncMax;
+  // delayed mode: unrotated Hessenberg columns, the provisional column of the last step,
+  // and whether a column was already completed by an early check of convergence
+  std::vector<double> Hr(c.lowsync ? (size_t)cnt * (kMaxRestart + 1) * kMaxRestart : 0),
+      hp(c.lowsync ? (size_t)cnt * (kMaxRestart + 1) : 0);
+  std::vector<char> early(cnt, 0);
   while (true) {
     bool all = true;
     for (int k = 0; k < cnt; ++k) all = all && done[k];
@@ -1418,8 +1434,117 @@ static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const Solv
       ++rst[k];
     }
     int jj = 0;
-    for (; jj < m && total < ctl.maxit; ++jj) {
-      arnoldi_step_graph<T>(h, jj, transpose, ctl, s);
+    // column cc of instance k from its unrotated entries raw[0..cc+1]: stored, rotated,
+    // the residual estimate updated; the instance stops when it has converged
+    auto complete_column = [&](int k, int cc, const double* raw) {
+      double* Hk = &H[(size_t)k * (kMaxRestart + 1) * kMaxRestart];
+      double* Hrk = &Hr[(size_t)k * (kMaxRestart + 1) * kMaxRestart];
+      double col[kMaxRestart + 1];
+      for (int i = 0; i <= cc + 1; ++i) {
+        Hrk[i * kMaxRestart + cc] = raw[i];
+        col[i] = raw[i];
+      }
+      for (int i = 0; i < cc; ++i) {
+        const double cr = cs[k * kMaxRestart + i], sv = sn[k * kMaxRestart + i];
+        const double t0 = cr * col[i] + sv * col[i + 1];
+        col[i + 1] = -sv * col[i] + cr * col[i + 1];
+        col[i] = t0;
+      }
+      const double den = std::hypot(col[cc], col[cc + 1]);
+      const double cr = den > 0 ? col[cc] / den : 1.0, sv = den > 0 ? col[cc + 1] / den : 0.0;
+      cs[k * kMaxRestart + cc] = cr;
+      sn[k * kMaxRestart + cc] = sv;
+      col[cc] = den;
+      for (int i = 0; i <= cc; ++i) Hk[i * kMaxRestart + cc] = col[i];
+      double* gk = &g[k * (kMaxRestart + 1)];
+      gk[cc + 1] = -sv * gk[cc];
+      gk[cc] = cr * gk[cc];
+      jk[k] = cc + 1;
+      ++its[k];
+      if (std::fabs(gk[cc + 1]) <= ctl.rtol * bn[k] || raw[cc + 1] == 0.0) act[k] = 0;
+    };
+    for (int k = 0; k < cnt; ++k) early[k] = 0;
+    for (; c.lowsync && jj < m && total < ctl.maxit; ++jj) {
+      // slot jj becomes final, which completes column jj - 1; column jj is provisional
+      arnoldi_step_graph<T>(h, jj, transpose, c, s);
+      spin_wait(s);
+      bool check = false;
+      for (int k = 0; k < cnt; ++k) {
+        const double* d = P->hdots + k * 64;
+        const double* a = d;
+        const double* bb = d + jj;
+        double n2 = d[2 * jj], ab = 0.0;
+        for (int i = 0; i < jj; ++i) {
+          n2 -= a[i] * a[i];
+          ab += a[i] * bb[i];
+        }
+        const double nu = std::sqrt(std::max(n2, 0.0));
+        const double un2 = P->hdots[64 * cnt + k * 64];
+        if (!std::isfinite(nu) || !std::isfinite(un2)) throw BiotError{BIOT_ERR_NONFINITE, "non-finite Krylov vector"};
+        if (!act[k]) continue;
+        double* hpk = &hp[(size_t)k * (kMaxRestart + 1)];
+        if (jj == 0) {
+          g[k * (kMaxRestart + 1)] *= nu;   // v0 / nu is the final first vector
+        } else if (!early[k]) {
+          double raw[kMaxRestart + 1];
+          for (int i = 0; i < jj; ++i) raw[i] = hpk[i] + a[i];
+          raw[jj] = nu;
+          complete_column(k, jj - 1, raw);
+        }
+        early[k] = 0;
+        if (!act[k] || nu == 0.0) continue;
+        // provisional column jj: ([V^T w; v.w] - Hbar a) / nu (unrotated Hbar = columns 0..jj-1)
+        const double* Hrk = &Hr[(size_t)k * (kMaxRestart + 1) * kMaxRestart];
+        for (int i = 0; i <= jj; ++i) {
+          double ha = 0.0;
+          for (int cc = std::max(i - 1, 0); cc < jj; ++cc) ha += Hrk[i * kMaxRestart + cc] * a[cc];
+          const double wi = i < jj ? bb[i] : (d[2 * jj + 1] - ab) / nu;
+          hpk[i] = (wi - ha) / nu;
+        }
+        // predicted estimate with |u_{jj+1}| for the subdiagonal (an upper bound)
+        double col[kMaxRestart + 1];
+        for (int i = 0; i <= jj; ++i) col[i] = hpk[i];
+        col[jj + 1] = std::sqrt(std::max(un2, 0.0));
+        for (int i = 0; i < jj; ++i) {
+          const double cr = cs[k * kMaxRestart + i], sv = sn[k * kMaxRestart + i];
+          const double t0 = cr * col[i] + sv * col[i + 1];
+          col[i + 1] = -sv * col[i] + cr * col[i + 1];
+          col[i] = t0;
+        }
+        const double den = std::hypot(col[jj], col[jj + 1]);
+        const double est = den > 0 ? std::fabs(g[k * (kMaxRestart + 1) + jj]) * col[jj + 1] / den : 0.0;
+        if (est <= ctl.rtol * bn[k]) check = true;
+      }
+      ++total;
+      bool any = false;
+      for (int k = 0; k < cnt; ++k) any = any || act[k];
+      if (!any) break;
+      if (check || jj == m - 1 || total >= ctl.maxit) {
+        // complete column jj now: the second-pass coefficients of the candidate in slot jj+1
+        const int nch = dot_chunks(P->gmax);
+        seg_mdot<T, T>(B.V, S, jj + 2, B.V + (long long)(jj + 1) * S, P->d_gseg, cnt, nch, P->partial, P->dot3, s,
+                       P->hdots + 128 * cnt);
+        spin_wait(s);
+        for (int k = 0; k < cnt; ++k) {
+          if (!act[k]) continue;
+          const double* d = P->hdots + 128 * cnt + k * 64;
+          const double* hpk = &hp[(size_t)k * (kMaxRestart + 1)];
+          double raw[kMaxRestart + 1], n2 = d[jj + 1];
+          for (int i = 0; i <= jj; ++i) {
+            raw[i] = hpk[i] + d[i];
+            n2 -= d[i] * d[i];
+          }
+          raw[jj + 1] = std::sqrt(std::max(n2, 0.0));
+          complete_column(k, jj, raw);
+          early[k] = 1;
+        }
+        any = false;
+        for (int k = 0; k < cnt; ++k) any = any || act[k];
+        if (!any) { ++jj; break; }
+      }
+    }
+    for (; !c.lowsync && jj < m && total < ctl.maxit; ++jj) {
+      arnoldi_step_graph<T>(h, jj, transpose, c, s);
       spin_wait(s);
       const double* h1 = P->hdots;
       const double* h2 = P->hdots + 64 * cnt;

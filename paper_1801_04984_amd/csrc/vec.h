@@ -48,6 +48,15 @@ void gs_update_dot(const TV* V, long long ldv, int nk, const double* c1, TW* w, 
 template <typename TV, typename TW>
 void gs_update_scale(const TV* V, long long ldv, int nk, const double* c2, TW* w, const VSeg* segs, int nseg,
                      long long maxlen, hipStream_t s);
+// one Arnoldi step of classical Gram-Schmidt twice with delayed reorthogonalisation
+// (vec.hip), nk <= kLowSyncMax final basis vectors: slot nk (candidate u) becomes
+// final, slot nk+1 (w = A P^-1 u) the next candidate.  dots[seg*64 + ...]:
+// V^T u (nk), V^T w (nk), u.u, u.w; norm[seg*64] = |next candidate|^2; hdots,
+// hnorm: host-mapped copies.
+constexpr int kLowSyncMax = 31;
+template <typename T>
+void dcgs_step(T* V, long long ldv, int nk, const VSeg* segs, int nseg, int nchunk, double* partial, double* dots,
+               double* norm, hipStream_t s, double* hdots, double* hnorm);
 template <typename TV, typename TW>
 void seg_maxpy(const TV* V, long long ldv, int nk, const double* c, double csign, TW* w, const VSeg* segs, int nseg,
                long long maxlen, hipStream_t s);

@@ -279,6 +279,149 @@ template void gs_update_scale<double, double>(const double*, long long, int, con
 template void gs_update_scale<float, float>(const float*, long long, int, const double*, float*, const VSeg*, int,
                                             long long, hipStream_t);
 
+// ---- classical Gram-Schmidt twice with delayed reorthogonalisation ---------------
+// (one reduction and one update sweep over the basis per Arnoldi step instead of
+// two and three).  Step nk: basis slots 0..nk-1 hold the final orthonormal vectors,
+// slot nk the candidate u of the next one (projected once, not normalised), slot
+// nk+1 the operator applied to u, w.  The reduction gives a = V^T u, b = V^T w,
+// alpha = u.u and gamma = u.w:
+//   out[seg*64 + k] = a_k, out[seg*64 + nk + k] = b_k (k < nk),
+//   out[seg*64 + 2 nk] = alpha, out[seg*64 + 2 nk + 1] = gamma.
+// The update then writes the final vector of slot nk, v = (u - V a) / nu with
+// nu = sqrt(alpha - |a|^2) (the removed components are orthogonal: Pythagoras), and
+// the next candidate into slot nk+1, u' = (w - V b - e v) / nu with e = v.w =
+// (gamma - a.b) / nu: w projected once on the complement of the basis including
+// v, scaled by 1/nu, which is the once-projected A P^-1 v (A P^-1 V a lies in the
+// span of the basis).  |u'|^2 is reduced on the way.
+template <typename TV, int K>
+__global__ __launch_bounds__(kDotThreads) void dcgs_dots_kernel(const TV* __restrict__ V, long long ldv, int nk,
+                                                                const VSeg* __restrict__ segs, int nchunk,
+                                                                double* __restrict__ partial) {
+  const VSeg sg = segs[blockIdx.y];
+  const int chunk = blockIdx.x;
+  const long long len = sg.len;
+  const long long per = (len + nchunk - 1) / nchunk;
+  const long long beg = chunk * per, end = beg + per < len ? beg + per : len;
+  const TV* u = V + (long long)nk * ldv;
+  const TV* w = u + ldv;
+  double acc[2 * K + 2];
+#pragma unroll
+  for (int k = 0; k < 2 * K + 2; ++k) acc[k] = 0.0;
+  for (long long i = beg + threadIdx.x; i < end; i += kDotThreads) {
+    double v[K];
+    load_column<TV, K>(V, ldv, 0, nk, sg.off + i, v);
+    const double ui = (double)u[sg.off + i], wi = (double)w[sg.off + i];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      acc[k] += v[k] * ui;
+      acc[K + k] += v[k] * wi;
+    }
+    acc[2 * K] += ui * ui;
+    acc[2 * K + 1] += ui * wi;
+  }
+  __shared__ double red[2 * K + 2][kDotThreads / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 2 * K + 2; ++k) {
+    double x = acc[k];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    if (lane == 0) red[k][wv] = x;
+  }
+  __syncthreads();
+  // output slot q < 2 nk + 2 from accumulator: a_k at k, b_k at K + k, alpha, gamma at 2K, 2K+1
+  for (int q = threadIdx.x; q < 2 * nk + 2; q += kDotThreads) {
+    const int src = q < nk ? q : (q < 2 * nk ? K + q - nk : 2 * K + q - 2 * nk);
+    double x = 0.0;
+    for (int r = 0; r < kDotThreads / 64; ++r) x += red[src][r];
+    partial[((long long)blockIdx.y * 64 + q) * nchunk + chunk] = x;
+  }
+}
+
+template <typename TV, int K>
+__global__ __launch_bounds__(kDotThreads) void dcgs_update_kernel(TV* __restrict__ V, long long ldv, int nk,
+                                                                  const double* __restrict__ c,
+                                                                  const VSeg* __restrict__ segs, int nchunk,
+                                                                  double* __restrict__ partial) {
+  const VSeg sg = segs[blockIdx.y];
+  const int chunk = blockIdx.x;
+  const long long len = sg.len;
+  const long long per = (len + nchunk - 1) / nchunk;
+  const long long beg = chunk * per, end = beg + per < len ? beg + per : len;
+  __shared__ double ca[K], cb[K];
+  __shared__ double fs, es;
+  const double* cs = c + blockIdx.y * 64;
+  if (threadIdx.x < K) {
+    ca[threadIdx.x] = threadIdx.x < nk ? cs[threadIdx.x] : 0.0;
+    cb[threadIdx.x] = threadIdx.x < nk ? cs[nk + threadIdx.x] : 0.0;
+  }
+  if (threadIdx.x == 0) {
+    double n2 = cs[2 * nk], ab = 0.0;
+    for (int k = 0; k < nk; ++k) {
+      n2 -= cs[k] * cs[k];
+      ab += cs[k] * cs[nk + k];
+    }
+    const double nu = n2 > 0.0 ? sqrt(n2) : 0.0;
+    fs = nu > 0.0 ? 1.0 / nu : 0.0;      // a zero norm (breakdown) gives zero vectors
+    es = (cs[2 * nk + 1] - ab) * fs;
+  }
+  __syncthreads();
+  const double f = fs, e = es;
+  TV* u = V + (long long)nk * ldv;
+  TV* w = u + ldv;
+  double nacc = 0.0;
+  for (long long i = beg + threadIdx.x; i < end; i += kDotThreads) {
+    double v[K];
+    load_column<TV, K>(V, ldv, 0, nk, sg.off + i, v);
+    double ui = (double)u[sg.off + i], wi = (double)w[sg.off + i];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      ui -= ca[k] * v[k];
+      wi -= cb[k] * v[k];
+    }
+    const TV vt = (TV)(f * ui);          // the final vector, in the storage type
+    const TV ut = (TV)(f * (wi - e * (double)vt));
+    u[sg.off + i] = vt;
+    w[sg.off + i] = ut;
+    nacc += (double)ut * (double)ut;
+  }
+  __shared__ double red[kDotThreads / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) nacc += __shfl_down(nacc, o, 64);
+  if (lane == 0) red[wv] = nacc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double x = 0.0;
+    for (int r = 0; r < kDotThreads / 64; ++r) x += red[r];
+    partial[((long long)blockIdx.y * 64) * nchunk + chunk] = x;
+  }
+}
+
+template <typename T>
+void dcgs_step(T* V, long long ldv, int nk, const VSeg* segs, int nseg, int nchunk, double* partial, double* dots,
+               double* norm, hipStream_t s, double* hdots, double* hnorm) {
+  const dim3 g(nchunk, nseg), b(kDotThreads);
+  if (nk <= 8) {
+    hipLaunchKernelGGL((dcgs_dots_kernel<T, 8>), g, b, 0, s, V, ldv, nk, segs, nchunk, partial);
+  } else if (nk <= 16) {
+    hipLaunchKernelGGL((dcgs_dots_kernel<T, 16>), g, b, 0, s, V, ldv, nk, segs, nchunk, partial);
+  } else {
+    hipLaunchKernelGGL((dcgs_dots_kernel<T, kLowSyncMax>), g, b, 0, s, V, ldv, nk, segs, nchunk, partial);
+  }
+  hipLaunchKernelGGL(mdot_stage2, dim3(2 * nk + 2, nseg), dim3(256), 0, s, partial, nchunk, dots, hdots);
+  if (nk <= 8) {
+    hipLaunchKernelGGL((dcgs_update_kernel<T, 8>), g, b, 0, s, V, ldv, nk, dots, segs, nchunk, partial);
+  } else if (nk <= 16) {
+    hipLaunchKernelGGL((dcgs_update_kernel<T, 16>), g, b, 0, s, V, ldv, nk, dots, segs, nchunk, partial);
+  } else {
+    hipLaunchKernelGGL((dcgs_update_kernel<T, kLowSyncMax>), g, b, 0, s, V, ldv, nk, dots, segs, nchunk, partial);
+  }
+  hipLaunchKernelGGL(mdot_stage2, dim3(1, nseg), dim3(256), 0, s, partial, nchunk, norm, hnorm);
+}
+template void dcgs_step<double>(double*, long long, int, const VSeg*, int, int, double*, double*, double*, hipStream_t,
+                                double*, double*);
+template void dcgs_step<float>(float*, long long, int, const VSeg*, int, int, double*, double*, double*, hipStream_t,
+                               double*, double*);
+
 // ---- plain copy (a kernel, so that it can sit in a captured graph) ----------------
 template <typename T>
 __global__ __launch_bounds__(256) void vcopy_kernel(const T* __restrict__ x, T* __restrict__ y, long long n) {
