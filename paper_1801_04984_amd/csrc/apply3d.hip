@@ -73,8 +73,14 @@ struct U3Job {
   T pw[4];           // time-level weights of the coupling pressure
   int npl;
   int sp[2];
-  int mode;          // 0: Y = A x (+ coupling); 1: Y = B - A x
+  int mode;          // 0: Y = A x (+ coupling); 1: Y = B - A x; 2: Chebyshev step (below)
   bool copy_fixed;   // mode 0, essential rows: copy x (slab operator) or 0 (multigrid level operator)
+  // mode 2, with y = A d for d = X (essential rows 0): Xs += d, Rs -= y,
+  // Y = rho d + sig Dv Rs (the next direction; Y must not be X)
+  T* Xs;
+  T* Rs;
+  const T* Dv;
+  T rho, sig;
 };
 
 // KS = k-steps of 4 columns: 23 with the 8 coupling columns, 21 without.
@@ -201,11 +207,12 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
   };
 
   // ---- owned node planes 2k (bottom slice of Rw + carried top slice cb) and 2k+1
-  // FP64 residual mode: the right-hand side values are prefetched into bvv (FP32
-  // keeps the single loop, as for the gather)
+  // FP64 residual mode and Chebyshev step: the values of the owned nodes that the
+  // sums need are prefetched into pf (residual: the right-hand side; Chebyshev
+  // step: d, x, r, Dinv); FP32 keeps the single loop, as for the gather
   constexpr int NOW = sizeof(T) == 8 ? (6 * (2 * kO3 + 1) * (2 * kO3 + 1) + NT - 1) / NT : 1;
-  T bvv[NOW];
-  auto prefetch_rhs = [&](int k) {
+  T pf[4][NOW];
+  auto prefetch_nodes = [&](int k) {
     if (sizeof(T) == 8 && J.mode != 0) {
 #pragma unroll
       for (int it = 0; it < NOW; ++it) {
@@ -214,9 +221,30 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
         const int rem = idx - c * 2 * nplane;
         const int zl = rem >= nplane;
         const int r2 = rem - zl * nplane;
-        bvv[it] = J.Bv[c * nu1 + (2 * i0 + r2 % nmx) + sy * (2 * j0 + r2 / nmx) + sz * (2 * k + zl)];
+        const int go = c * nu1 + (2 * i0 + r2 % nmx) + sy * (2 * j0 + r2 / nmx) + sz * (2 * k + zl);
+        if (J.mode == 1) {
+          pf[0][it] = J.Bv[go];
+        } else {
+          pf[0][it] = J.X[go];
+          pf[1][it] = J.Xs[go];
+          pf[2][it] = J.Rs[go];
+          pf[3][it] = J.Dv[go];
+        }
       }
     }
+  };
+  // the result v of an owned node (y = A x of mode 0 and 2, b - A x of mode 1)
+  auto store_node = [&](int go, T v, int it) {
+    if (J.mode != 2) {
+      J.Y[go] = v;
+      return;
+    }
+    const bool pre = sizeof(T) == 8;
+    const T dd = pre ? pf[0][it] : J.X[go];
+    const T rr = (pre ? pf[2][it] : J.Rs[go]) - v;
+    J.Xs[go] = (pre ? pf[1][it] : J.Xs[go]) + dd;
+    J.Rs[go] = rr;
+    J.Y[go] = J.rho * dd + J.sig * (pre ? pf[3][it] : J.Dv[go]) * rr;
   };
   auto node_sums = [&](int k, const T* __restrict__ cb) {
 #pragma unroll
@@ -230,7 +258,7 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
       const int go = c * nu1 + mx + sy * my + sz * mz;
       T v;
       if (ugrid_fixed(3, J.su, c, mx, my, mz)) {
-        v = J.mode == 0 ? (J.copy_fixed ? J.X[go] : T(0)) : (sizeof(T) == 8 ? bvv[it] : J.Bv[go]);
+        v = J.mode == 1 ? (sizeof(T) == 8 ? pf[0][it] : J.Bv[go]) : (J.copy_fixed ? J.X[go] : T(0));
       } else {
         const bool xo = mx & 1, yo = my & 1;
         const int cx0 = xo ? (mx - 1) / 2 : mx / 2 - 1, ax0 = xo ? 1 : 2;
@@ -248,9 +276,9 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
           v += Rw[(c * 27 + zl * 9 + nd) * kLD3 + cell];
           if (zl == 0) v += cb[(c * 9 + nd) * NC + cell];
         }
-        if (J.mode != 0) v = (sizeof(T) == 8 ? bvv[it] : J.Bv[go]) - v;
+        if (J.mode == 1) v = (sizeof(T) == 8 ? pf[0][it] : J.Bv[go]) - v;
       }
-      J.Y[go] = v;
+      store_node(go, v, it);
     }
   };
   // top slice of the rows in Rw (comp * 9 + node) into the carry buffer cn
@@ -303,7 +331,7 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
       // (the last layer re-reads its own planes: in range, unused)
       load_layer(k + 2 < kend ? k + 2 : k + 1);
     }
-    if (k >= k0) prefetch_rhs(k);
+    if (k >= k0) prefetch_nodes(k);
     __syncthreads();
   }
   // the last layer's node sums and carry
@@ -319,7 +347,7 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
       const int go = c * nu1 + mx + sy * my + sz * mz;
       T v;
       if (ugrid_fixed(3, J.su, c, mx, my, mz)) {
-        v = J.mode == 0 ? (J.copy_fixed ? J.X[go] : T(0)) : J.Bv[go];
+        v = J.mode == 1 ? J.Bv[go] : (J.copy_fixed ? J.X[go] : T(0));
       } else {
         const bool xo = mx & 1, yo = my & 1;
         const int cx0 = xo ? (mx - 1) / 2 : mx / 2 - 1, ax0 = xo ? 1 : 2;
@@ -335,9 +363,17 @@ __device__ __forceinline__ void u3_run(const U3Job<T>& J, int i0, int j0, int k0
           const int cell = (ty0 + qy) * kT3 + tx0 + qx;
           v += cb[(c * 9 + (qy ? 0 : ay0) * 3 + (qx ? 0 : ax0)) * NC + cell];
         }
-        if (J.mode != 0) v = J.Bv[go] - v;
+        if (J.mode == 1) v = J.Bv[go] - v;
       }
-      J.Y[go] = v;
+      if (J.mode == 2) {
+        const T dd = J.X[go];
+        const T rr = J.Rs[go] - v;
+        J.Xs[go] += dd;
+        J.Rs[go] = rr;
+        J.Y[go] = J.rho * dd + J.sig * J.Dv[go] * rr;
+      } else {
+        J.Y[go] = v;
+      }
     }
   }
 }
@@ -526,13 +562,16 @@ void launch_apply3d(const ApplyArgs& a, const void* x, void* y, int transpose) {
 template void launch_apply3d<double>(const ApplyArgs&, const void*, void*, int);
 template void launch_apply3d<float>(const ApplyArgs&, const void*, void*, int);
 
-// elasticity multigrid level: y = tau A x (mode 0; essential rows 0) or y = b - tau A x
-// (mode 1; essential rows b)
+// elasticity multigrid level: y = tau A x (mode 0; essential rows 0), y = b - tau A x
+// (mode 1; essential rows b), or one Chebyshev step with the operator applied to the
+// direction d = x (mode 2: xs += d, rs -= tau A d, y = rho d + sig Dinv rs)
 template <typename T>
 __global__ __launch_bounds__(64 * kW3) void uapply3d_kernel(const UGridSeg* __restrict__ segs,
                                                             const int4* __restrict__ work, int zc, int mode,
                                                             const T* __restrict__ emat, const T* __restrict__ X,
-                                                            const T* __restrict__ Bv, T* __restrict__ Y) {
+                                                            const T* __restrict__ Bv, T* __restrict__ Y,
+                                                            T* __restrict__ Xs, T* __restrict__ Rs,
+                                                            const T* __restrict__ dinv, double rho, double sig) {
   const int4 w = work[blockIdx.x];
   const UGridSeg& G = segs[w.x];
   const long long vo = G.voff + blockIdx.y * G.vjstride;
@@ -550,17 +589,32 @@ __global__ __launch_bounds__(64 * kW3) void uapply3d_kernel(const UGridSeg* __re
   J.npl = 0;
   J.sp[0] = 1; J.sp[1] = 1;
   for (int l = 0; l < 4; ++l) J.pw[l] = T(0);
+  J.Xs = Xs ? Xs + vo : nullptr;
+  J.Rs = Rs ? Rs + vo : nullptr;
+  J.Dv = dinv ? dinv + G.doff : nullptr;
+  J.rho = T(rho);
+  J.sig = T(sig);
   u3_run<T, 21>(J, w.y * kO3, w.z * kO3, w.w * zc, zc);
 }
 template <typename T>
 void launch_uapply3d(const UGridSeg* segs, const int4* work, int nwork, int nj, int zc, int mode, const T* x,
                      const T* b, T* y, const T* emat, hipStream_t s) {
   hipLaunchKernelGGL((uapply3d_kernel<T>), dim3(nwork, nj), dim3(64 * kW3), 0, s, segs, work, zc, mode, emat, x, b,
-                     y);
+                     y, (T*)nullptr, (T*)nullptr, (const T*)nullptr, 0.0, 0.0);
+}
+template <typename T>
+void launch_uapply3d_cheb(const UGridSeg* segs, const int4* work, int nwork, int nj, int zc, const T* d, T* x, T* r,
+                          T* dnext, const T* dinv, double rho, double sig, const T* emat, hipStream_t s) {
+  hipLaunchKernelGGL((uapply3d_kernel<T>), dim3(nwork, nj), dim3(64 * kW3), 0, s, segs, work, zc, 2, emat, d,
+                     (const T*)nullptr, dnext, x, r, dinv, rho, sig);
 }
 template void launch_uapply3d<double>(const UGridSeg*, const int4*, int, int, int, int, const double*, const double*,
                                       double*, const double*, hipStream_t);
 template void launch_uapply3d<float>(const UGridSeg*, const int4*, int, int, int, int, const float*, const float*,
                                      float*, const float*, hipStream_t);
+template void launch_uapply3d_cheb<double>(const UGridSeg*, const int4*, int, int, int, const double*, double*, double*,
+                                           double*, const double*, double, double, const double*, hipStream_t);
+template void launch_uapply3d_cheb<float>(const UGridSeg*, const int4*, int, int, int, const float*, float*, float*,
+                                          float*, const float*, double, double, const float*, hipStream_t);
 
 }  // namespace bt

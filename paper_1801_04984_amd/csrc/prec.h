@@ -161,6 +161,11 @@ void launch_mq_lines(int dim, const InstDev* insts, int count, int nj, long long
 template <typename T>
 void launch_uapply3d(const UGridSeg* segs, const int4* work, int nwork, int nj, int zc, int mode, const T* x,
                      const T* b, T* y, const T* emat, hipStream_t s);
+// one Chebyshev step of the 3D elasticity smoother with its operator product in the same
+// sweep: x += d, r -= tau A d, dnext = rho d + sig Dinv r (dnext must not be d)
+template <typename T>
+void launch_uapply3d_cheb(const UGridSeg* segs, const int4* work, int nwork, int nj, int zc, const T* d, T* x, T* r,
+                          T* dnext, const T* dinv, double rho, double sig, const T* emat, hipStream_t s);
 template <typename T>
 void launch_rpass(const RPass* segs, int nseg, int nj, long long maxout, const double* tab, const T* in, T* out,
                   hipStream_t s);

@@ -1092,12 +1092,26 @@ static void u_vcycle(biot_problem_s* h, int l, int nl, T* x, const T* b, T* r, T
   const int4* work = P->d_uwork[uv];
   const int nwork = (int)P->uwork[uv].size();
   const T* dinv = B.u_dinv[0];
+  // the ud Chebyshev steps from the direction in d0 (3D: the operator product and the
+  // update in one sweep, the direction alternating between d0 and y)
+  auto cheb_steps = [&]() {
+    if (d == 3) {
+      T *din = d0, *dout = y;
+      for (int k = 0; k < ud; ++k) {
+        launch_uapply3d_cheb<T>(gs, work, nwork, nl, P->utile[uv], din, x, r, dout, dinv, cs.steps[k].first,
+                                cs.steps[k].second, uemat<T>(P), s);
+        std::swap(din, dout);
+      }
+      return;
+    }
+    for (int k = 0; k < ud; ++k) {
+      launch_uapply<T>(d, gs, work, nwork, nl, 0, d0, nullptr, y, uemat<T>(P), s, P->utile[uv]);
+      cheb_update<T>(ls, cnt, nl, mx, 1, cs.steps[k].first, cs.steps[k].second, x, r, d0, y, dinv, nullptr, s);
+    }
+  };
   // pre-smoothing from x = 0
   cheb_update<T>(ls, cnt, nl, mx, 2, 0.0, cs.s0, x, r, d0, nullptr, dinv, b, s);
-  for (int k = 0; k < ud; ++k) {
-    launch_uapply<T>(d, gs, work, nwork, nl, 0, d0, nullptr, y, uemat<T>(P), s, P->utile[uv]);
-    cheb_update<T>(ls, cnt, nl, mx, 1, cs.steps[k].first, cs.steps[k].second, x, r, d0, y, dinv, nullptr, s);
-  }
+  cheb_steps();
   // restriction of r
   const T* in = r;
   for (int pass = 0; pass < d; ++pass) {
@@ -1110,10 +1124,7 @@ static void u_vcycle(biot_problem_s* h, int l, int nl, T* x, const T* b, T* r, T
   // post-smoothing
   launch_uapply<T>(d, gs, work, nwork, nl, 1, x, b, r, uemat<T>(P), s, P->utile[uv]);
   cheb_update<T>(ls, cnt, nl, mx, 0, 0.0, cs.s0, x, r, d0, nullptr, dinv, nullptr, s);
-  for (int k = 0; k < ud; ++k) {
-    launch_uapply<T>(d, gs, work, nwork, nl, 0, d0, nullptr, y, uemat<T>(P), s, P->utile[uv]);
-    cheb_update<T>(ls, cnt, nl, mx, 1, cs.steps[k].first, cs.steps[k].second, x, r, d0, y, dinv, nullptr, s);
-  }
+  cheb_steps();
 }
 
 // the fixed-stress level solves of the levels j < nl at once: B.Wr -> B.Wz (B.Wr is read only).
