@@ -1423,14 +1423,19 @@ static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const Solv
   std::vector<int> stall(cnt, 0);
   int total = 0;
   // Gram-Schmidt with delayed reorthogonalisation (dcgs_step) for restart lengths whose
-  // dot sets fit the 64 slots per instance; the flexible mode keeps the plain passes
+  // dot sets fit the 64 slots per instance.  The operator is applied to the candidate
+  // u_j of each slot: right preconditioning reconstructs A P^-1 of the final vector (the
+  // columns below); the flexible mode keeps z_j = P(u_j) itself, whose image
+  // w = V b + e v + nu_j u_{j+1} gives its column directly.
   SolveCtl c = ctl;
-  c.lowsync = !ctl.flex32 && m <= kLowSyncMax;
+  c.lowsync = m <= kLowSyncMax;
+  const bool flex = ctl.flex32;
   // delayed mode: unrotated Hessenberg columns, the provisional column of the last step,
   // and whether a column was already completed by an early check of convergence
   std::vector<double> Hr(c.lowsync ? (size_t)cnt * (kMaxRestart + 1) * kMaxRestart : 0),
       hp(c.lowsync ? (size_t)cnt * (kMaxRestart + 1) : 0);
   std::vector<char> early(cnt, 0);
+  std::vector<double> nuc(cnt, 1.0);   // flexible mode: nu of the candidate whose column is provisional
   while (true) {
     bool all = true;
     for (int k = 0; k < cnt; ++k) all = all && done[k];
@@ -1497,25 +1502,34 @@ static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const Solv
         if (jj == 0) {
           g[k * (kMaxRestart + 1)] *= nu;   // v0 / nu is the final first vector
         } else if (!early[k]) {
+          // completed with the second-pass coefficients a of the candidate (flexible
+          // mode: scaled by the previous candidate's nu, as that candidate was)
+          const double sc = flex ? nuc[k] : 1.0;
           double raw[kMaxRestart + 1];
-          for (int i = 0; i < jj; ++i) raw[i] = hpk[i] + a[i];
-          raw[jj] = nu;
+          for (int i = 0; i < jj; ++i) raw[i] = hpk[i] + sc * a[i];
+          raw[jj] = sc * nu;
           complete_column(k, jj - 1, raw);
         }
         early[k] = 0;
         if (!act[k] || nu == 0.0) continue;
-        // provisional column jj: ([V^T w; v.w] - Hbar a) / nu (unrotated Hbar = columns 0..jj-1)
+        // provisional column jj: ([V^T w; v.w] - Hbar a) / nu (unrotated Hbar = columns
+        // 0..jj-1); flexible mode: [V^T w; v.w]
         const double* Hrk = &Hr[(size_t)k * (kMaxRestart + 1) * kMaxRestart];
         for (int i = 0; i <= jj; ++i) {
+          const double wi = i < jj ? bb[i] : (d[2 * jj + 1] - ab) / nu;
+          if (flex) {
+            hpk[i] = wi;
+            continue;
+          }
           double ha = 0.0;
           for (int cc = std::max(i - 1, 0); cc < jj; ++cc) ha += Hrk[i * kMaxRestart + cc] * a[cc];
-          const double wi = i < jj ? bb[i] : (d[2 * jj + 1] - ab) / nu;
           hpk[i] = (wi - ha) / nu;
         }
+        nuc[k] = nu;
         // predicted estimate with |u_{jj+1}| for the subdiagonal (an upper bound)
         double col[kMaxRestart + 1];
         for (int i = 0; i <= jj; ++i) col[i] = hpk[i];
-        col[jj + 1] = std::sqrt(std::max(un2, 0.0));
+        col[jj + 1] = (flex ? nu : 1.0) * std::sqrt(std::max(un2, 0.0));
         for (int i = 0; i < jj; ++i) {
           const double cr = cs[k * kMaxRestart + i], sv = sn[k * kMaxRestart + i];
           const double t0 = cr * col[i] + sv * col[i + 1];
@@ -1540,12 +1554,13 @@ static void gmres(biot_problem_s* h, const T* b, T* x, int transpose, const Solv
           if (!act[k]) continue;
           const double* d = P->hdots + 128 * cnt + k * 64;
           const double* hpk = &hp[(size_t)k * (kMaxRestart + 1)];
+          const double sc = flex ? nuc[k] : 1.0;
           double raw[kMaxRestart + 1], n2 = d[jj + 1];
           for (int i = 0; i <= jj; ++i) {
-            raw[i] = hpk[i] + d[i];
+            raw[i] = hpk[i] + sc * d[i];
             n2 -= d[i] * d[i];
           }
-          raw[jj + 1] = std::sqrt(std::max(n2, 0.0));
+          raw[jj + 1] = sc * std::sqrt(std::max(n2, 0.0));
           complete_column(k, jj, raw);
           early[k] = 1;
         }
