@@ -35,9 +35,12 @@ constexpr int kMaxRestart = 64;
 // coarse-correction over-relaxation of the aggregation multigrid (2^d cells per
 // aggregate; measured best on the 2D 128^2 / 3D 48^3 workloads: 2.1 / 1.9)
 inline double omega_p(int dim) { return dim == 2 ? 2.1 : 1.9; }
-// Chebyshev smoothing degree on the pressure levels: 3 in 2D; in 3D degree 5
+// Chebyshev smoothing degree on the DG pressure level: 3 in 2D; in 3D degree 5
 // costs fewer slab iterations than it adds per iteration (measured on 32^3)
 inline int pdeg(int dim) { return dim == 2 ? 3 : 5; }
+// degree on the aggregated cell levels below it: 3 in both dimensions (in 3D,
+// degree 5 there saves at most one slab iteration in forty, less than it costs)
+inline int pcdeg(int) { return 3; }
 constexpr double kPLo = 1.0 / 8.0, kPHi = 1.1;
 // Chebyshev degree of the elasticity smoother
 inline int udeg(int) { return 2; }
@@ -53,7 +56,7 @@ constexpr long long kPCoarseCells = 256;
 constexpr long long kUCoarseDofs = 1100;
 // 2D elasticity levels with fewer 16x16 tiles (times levels j) than this use 8x8 tiles
 constexpr long long kUTile16MinTiles = 1024;
-constexpr long long kPCoarseBytes = 24LL << 20;   // sum over instances and levels j
+constexpr long long kPCoarseBytes = 96LL << 20;   // sum over instances and levels j
 constexpr long long kUCoarseBytes = 48LL << 20;   // sum over instances (shared by the levels)
 
 template <typename T>
@@ -1020,7 +1023,7 @@ static void p_vcycle(biot_problem_s* h, int l, int nl, hipStream_t s) {
   PrecData* P = h->prec;
   auto& B = bufs<T>(P);
   const int cnt = h->count;
-  const int pd = pdeg(h->dim);
+  const int pd = pcdeg(h->dim);
   const ChebSeq cs = cheb_seq(kPLo, kPHi, pd);
   if (l == P->npl - 1) {
     dense_solve<T>(P->d_pd, cnt, nl, P->p_maxn, false, P->pAinv, B.pc_b[l], B.pc_x[l], s);
