@@ -41,10 +41,15 @@ inline int pdeg(int dim) { return dim == 2 ? 3 : 5; }
 // degree on the aggregated cell levels below it: 3 in both dimensions (in 3D,
 // degree 5 there saves at most one slab iteration in forty, less than it costs)
 inline int pcdeg(int) { return 3; }
-constexpr double kPLo = 1.0 / 8.0, kPHi = 1.1;
+// Chebyshev smoothing intervals [lo, hi] in units of the power-iteration estimate of
+// lambda_max(D^-1 A).  A degree-2 smoother damps a narrow upper band far better than a
+// wide one: on the 3D elasticity levels lo = 1/15 cost 48 slab iterations at 48^3 dG(2)
+// (the V-cycle barely contracts; lo = 1/20 stagnates), lo = 1/6 cost 31; 1/4 to 1/10 are
+// alike.  hi = 1.3 leaves room for an underestimated lambda_max.
+constexpr double kPLo = 1.0 / 4.0, kPHi = 1.1;
 // Chebyshev degree of the elasticity smoother
 inline int udeg(int) { return 2; }
-constexpr double kULo = 1.0 / 15.0, kUHi = 1.1;
+constexpr double kULo = 1.0 / 6.0, kUHi = 1.3;
 constexpr double kQLo = 0.25, kQHi = 1.75;  // Gershgorin interval of Dq^-1 Mq
 constexpr long long kLineSolveMinLines = 16384;   // automatic flux-block choice
 constexpr int kQDegDefault = 8;                     // Chebyshev degree when line solves are not used
