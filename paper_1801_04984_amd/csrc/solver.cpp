@@ -33,11 +33,12 @@ namespace bt {
 
 constexpr int kMaxRestart = 64;
 // coarse-correction over-relaxation of the aggregation multigrid (2^d cells per
-// aggregate; measured best on the 2D 128^2 / 3D 48^3 workloads: 2.1 / 1.9)
-inline double omega_p(int dim) { return dim == 2 ? 2.1 : 1.9; }
-// Chebyshev smoothing degree on the DG pressure level: 3 in 2D; in 3D degree 5
-// costs fewer slab iterations than it adds per iteration (measured on 32^3)
-inline int pdeg(int dim) { return dim == 2 ? 3 : 5; }
+// aggregate; measured best on the 2D 128^2 / 3D 48^3 workloads: 2.1 / 2.1)
+inline double omega_p(int) { return 2.1; }
+// Chebyshev smoothing degree on the DG pressure level: 3 in 2D, 4 in 3D (measured
+// on 32^3 and 48^3: degree 3 costs more slab iterations than it saves per
+// iteration, degree 5 saves none)
+inline int pdeg(int dim) { return dim == 2 ? 3 : 4; }
 // degree on the aggregated cell levels below it: 3 in both dimensions (in 3D,
 // degree 5 there saves at most one slab iteration in forty, less than it costs)
 inline int pcdeg(int) { return 3; }
@@ -46,7 +47,7 @@ inline int pcdeg(int) { return 3; }
 // wide one: on the 3D elasticity levels lo = 1/15 cost 48 slab iterations at 48^3 dG(2)
 // (the V-cycle barely contracts; lo = 1/20 stagnates), lo = 1/6 cost 31; 1/4 to 1/10 are
 // alike.  hi = 1.3 leaves room for an underestimated lambda_max.
-constexpr double kPLo = 1.0 / 4.0, kPHi = 1.1;
+constexpr double kPLo = 1.0 / 3.0, kPHi = 1.1;
 // Chebyshev degree of the elasticity smoother
 inline int udeg(int) { return 2; }
 constexpr double kULo = 1.0 / 6.0, kUHi = 1.3;

@@ -209,7 +209,7 @@ def test_adjoint_3d_48_dg2_mixed_matches_fd_20_directions():
     at 64 sensors with respect to all 110,592 cellwise log K values, computed by
     adjoint_sweep with the slab solves in mixed precision (FP32 inner solves in
     FP64 refinement), against central FP64 finite differences of the forward map
-    along 20 random unit directions (eps = 1e-5), on the first two slabs."""
+    along 20 random unit directions (eps = 1e-4), on the first two slabs."""
     torch = torch_cuda()
     from paper_1801_04984_amd import tuning
     wl = W.c4_adjoint3d()
@@ -248,7 +248,11 @@ def test_adjoint_3d_48_dg2_mixed_matches_fd_20_directions():
     assert abs(J[0] - J0) <= 1e-12 * abs(J0)
     g = g.cpu().numpy()
     dirs = W.unit_directions(W.C4_NDIRS, theta.size, W.C4_DIRECTION_SEED)
-    eps = 1e-5
+    # central differences: truncation O(eps^2), rounding (the forward solves end at a
+    # relative residual of 1e-13, so J carries about 1e-13 J) O(1e-13 J / eps).  At
+    # eps = 1e-5 that rounding, ~1e-8 absolute whatever the direction, is already 1e-3 of
+    # the smallest directional derivatives here; eps = 1e-4 leaves it at ~1e-9.
+    eps = 1e-4
     errs = []
     for d in dirs:
         jp, _ = J_of(theta + eps * d)
@@ -261,6 +265,6 @@ def test_adjoint_3d_48_dg2_mixed_matches_fd_20_directions():
     rel = [abs(fd - ad) / max(abs(ad), 1e-3 * gn) for fd, ad in errs]
     print(f"48^3 dG(2) adjoint: J {J0:.6e}, |grad| {gn:.3e}; directional derivatives (fd, adjoint) {errs}; "
           f"max rel diff {max(rel):.2e}")
-    # the central difference carries the forward solves' rounding, about 1e-14 J / eps:
-    # ~1e-9 against directional derivatives of ~1e-5 (measured: at most 3.5e-4 relative)
+    # directional derivatives of 2e-7 to 4e-5, each compared with the larger of itself and
+    # 1e-3 |grad|
     assert max(rel) <= 1e-3, rel
