@@ -20,6 +20,41 @@ static dim3 grid3(long long maxlen, int nseg, int nj) {
   return dim3((unsigned)(b < 1 ? 1 : (b > 65535 ? 65535 : b)), nseg, nj);
 }
 
+// (E p) of the three displacement components of one 3D node: the pressures of the
+// node's cells are read once for all three (same terms, same order as ep_node)
+template <typename T>
+__device__ __forceinline__ void ep_node3(const InstDev& I, const T* __restrict__ P, const int co[3], double s[3]) {
+  const double hx = 0.5 * I.h[0], hy = 0.5 * I.h[1], hz = 0.5 * I.h[2];
+  s[0] = s[1] = s[2] = 0.0;
+#pragma unroll
+  for (int sz = 0; sz < 2; ++sz) {
+    int cz, az;
+    if (!node_cell(co[2], I.n[2], sz, cz, az)) continue;
+#pragma unroll
+    for (int sy = 0; sy < 2; ++sy) {
+      int cy, ay;
+      if (!node_cell(co[1], I.n[1], sy, cy, ay)) continue;
+#pragma unroll
+      for (int sx = 0; sx < 2; ++sx) {
+        int cx, ax;
+        if (!node_cell(co[0], I.n[0], sx, cx, ax)) continue;
+        const T* pc = P + (2 * cx) + I.sp[0] * ((2 * cy) + I.sp[1] * (2 * cz));
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+          const int gx = g & 1, gy = (g >> 1) & 1, gz = (g >> 2) & 1;
+          const double p = (double)pc[gx + I.sp[0] * (gy + I.sp[1] * gz)];
+          const double bx = gb_sel(ax, gx), vx = hx * vg_sel(gx, ax);
+          const double by = gb_sel(ay, gy), vy = hy * vg_sel(gy, ay);
+          const double bz = gb_sel(az, gz), vz = hz * vg_sel(gz, az);
+          s[0] += bx * vy * vz * p;
+          s[1] += vx * by * vz * p;
+          s[2] += vx * vy * bz * p;
+        }
+      }
+    }
+  }
+}
+
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void coupling_kernel(const InstDev* __restrict__ insts, LevelCoef cu,
                                                        const T* __restrict__ rt, const T* __restrict__ zp,
@@ -30,6 +65,35 @@ __global__ __launch_bounds__(256) void coupling_kernel(const InstDev* __restrict
   const long long lo = I.x_off + j * I.N;
   const T* P = zp + lo + I.off_p;
   const int nuq = (int)I.off_p;
+  if constexpr (DIM == 3) {
+    // one thread per displacement node (its three rows), then one per flux row
+    const int nu1 = I.su[0] * I.su[1] * I.su[2];
+    const int q0 = (int)I.off_q[0];
+    const int nt = nu1 + (nuq - q0);
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += gridDim.x * blockDim.x) {
+      if (t < nu1) {
+        int co[3];
+        unrank((unsigned)t, I.su, co);
+        T r[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) r[c] = rt[lo + I.off_u[c] + t];
+        double ep[3];
+        ep_node3<T>(I, P, co, ep);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          fu[lo + I.off_u[c] + t] = u_fixed(I, c, co[0], co[1], co[2]) ? T(0) : r[c] + cuj * (T)ep[c];
+      } else {
+        const int tq = q0 + (t - nu1);
+        int blk, comp, co[3];
+        decode_dof(I, tq, blk, comp, co);
+        const T r = rt[lo + tq];
+        T mq, dg, bp;
+        flux_row<T, false>(I, nullptr, zp + lo, comp, co, tq - (int)I.off_q[comp], mq, dg, bp);
+        fq[lo + tq] = q_fixed(I, comp, co[comp]) ? T(0) : r - T(I.tau) * bp;
+      }
+    }
+    return;
+  }
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nuq; t += gridDim.x * blockDim.x) {
     int blk, comp, co[3];
     decode_dof(I, t, blk, comp, co);
