@@ -7,6 +7,8 @@
 // from the DG-Q1 pressure of the cells around a node:
 //   (B p)(q_e node m)  = -hp_e sum_{cells of m} sum_g GB(a, g) p(g)
 //   (E p)(u_c node)    = sum_{cells} sum_g GB(a_c, g_c) prod_{f != c} (h_f/2) VG(g_f, a_f) p(g).
+// In 3D one thread computes the three components of a displacement node, from one
+// read of its cells' pressures.
 // The flux block tau Mq is solved by Chebyshev-Jacobi; Mq acts only along the
 // flux component's own axis (the open basis is orthogonal under 2-point
 // Gauss) with the cellwise eta/K.
